@@ -1,0 +1,162 @@
+"""Cell integrals of the wavelet bases on [0, 1] (Sec. 3.2).
+
+Test infrastructure (see the package header).
+
+For a level k >= J0 the scaling basis B_{phi,k} is, in this order,
+  phi^left_m (m = 0..nu-1), interior phi_{k,m} (m = nu .. 2^k-nu-1),
+  phi^right_{2^k-1-m} (m = 2^k-nu .. 2^k-1),
+and B_{psi,k} is the same with psi.  Boundary functions are dilated as in
+Sec. 3.2: phi^bd_{k,m}(x) = 2^{k/2} phi^left_m(2^k x) on the left and
+2^{k/2} phi^right_{2^k-1-m}(2^k (x - 1)) on the right.  The multiscale basis
+is C_{psi,j} = B_{phi,J0} u B_{psi,J0} u ... u B_{psi,j-1}.
+
+Each function is returned by its cell integrals c[i] over the 2^J cells
+[i 2^-J, (i+1) 2^-J) of [0, 1], built from the cascade cell integrals of
+phi (Phi_r) and psi (Psi_r):
+  interior phi_{k,m}:  c[i] = 2^{-k/2} Phi_{J-k}[i - m 2^{J-k}]
+  interior psi_{k,m}:  c[i] = 2^{-k/2} Psi_{J-k}[i - m 2^{J-k}]
+  boundary functions:  the same for each translate in their coefficient
+                       vectors, keeping only cells inside [0, 1).
+
+Parity status: pinned by polynomial reproduction, orthonormality against
+point-value quadrature, zero mean of wavelets and the Haar closed form.
+"""
+import functools
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import cascade, halfline
+
+
+def _translate_cells(nu, level, t, J, scaling=True):
+    """(cell indices, values) of 2^{level/2} f(2^level x - t) on [0, 1), f = phi or psi."""
+    r = J - level
+    tab = cascade.phi_cells(nu, r) if scaling else cascade.psi_cells(nu, r)
+    s = np.arange(tab.lo, tab.lo + tab.values.size)
+    i = s + t * (1 << r)
+    keep = (i >= 0) & (i < (1 << J))
+    return i[keep], tab.values[keep] * 2.0 ** (-level / 2.0)
+
+
+def _combo_cells(nu, level, coef, offset, J):
+    """Cell integrals of sum_t coef[t] 2^{level/2} phi(2^level x - offset - t) on [0,1)."""
+    out = np.zeros(1 << J)
+    for t, a in coef.items():
+        i, v = _translate_cells(nu, level, offset + t, J)
+        out[i] += float(a) * v
+    nz = np.nonzero(out)[0]
+    return nz, out[nz]
+
+
+@functools.lru_cache(maxsize=None)
+def _edge_float(nu):
+    return (halfline.edge_scaling(nu, "left"), halfline.edge_scaling(nu, "right"),
+            halfline.edge_wavelets(nu, "left"), halfline.edge_wavelets(nu, "right"))
+
+
+def scaling_function_cells(nu, k, m, J):
+    """Cell integrals of the m-th function of B_{phi,k}."""
+    L, R, _, _ = _edge_float(nu)
+    size = 1 << k
+    if m < nu:
+        return _combo_cells(nu, k, L[m], 0, J)
+    if m >= size - nu:
+        return _combo_cells(nu, k, R[size - 1 - m], size, J)
+    return _translate_cells(nu, k, m, J, scaling=True)
+
+
+def wavelet_cells(nu, k, m, J):
+    """Cell integrals of the m-th function of B_{psi,k}."""
+    _, _, WL, WR = _edge_float(nu)
+    size = 1 << k
+    if m < nu:
+        return _combo_cells(nu, k + 1, WL[m], 0, J)
+    if m >= size - nu:
+        return _combo_cells(nu, k + 1, WR[size - 1 - m], 2 * size, J)
+    return _translate_cells(nu, k, m, J, scaling=False)
+
+
+def check_level(nu, k, j0=None):
+    if nu < 1:
+        raise ValueError("nu must be >= 1")
+    # Sec. 3.2: J0 >= ceil(log2(2 nu)) for nu >= 2 and J0 >= 0 for Haar (at k = 0 the
+    # single Haar function is both the left and the right boundary function)
+    if nu >= 2 and (1 << k) < 2 * nu:
+        raise ValueError("level too coarse for the boundary construction: need 2^k >= 2 nu")
+
+
+def block(nu, k, J, scaling):
+    """Sparse (2^J x 2^k) matrix of cell integrals of B_{phi,k} or B_{psi,k}."""
+    check_level(nu, k)
+    rows, cols, vals = [], [], []
+    for m in range(1 << k):
+        i, v = (scaling_function_cells if scaling else wavelet_cells)(nu, k, m, J)
+        rows.append(i)
+        cols.append(np.full(i.size, m))
+        vals.append(v)
+    return sp.csc_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(1 << J, 1 << k))
+
+
+def multiscale(nu, j, j0, J):
+    """Sparse (2^J x 2^j) cell-integral matrix of C_{psi,j} in the paper's order."""
+    parts = [block(nu, j0, J, True)]
+    for k in range(j0, j):
+        parts.append(block(nu, k, J, False))
+    return sp.hstack(parts).tocsc()
+
+
+def position_1d(c, j0):
+    """Map a C_{psi,j} position c to (level, 'phi'|'psi', index)."""
+    if c < (1 << j0):
+        return j0, "phi", c
+    k = int(c).bit_length() - 1
+    return k, "psi", c - (1 << k)
+
+
+# ---------------------------------------------------------------------------
+# Point values on the grid i 2^-R (for the brute-force quadrature cross-check).
+# They come from the point-value cascade, a path independent of the cell
+# integrals and of the half-line Gram matrix.
+
+def _translate_points(nu, level, t, R):
+    """2^{level/2} phi(2^level x - t) at x = i 2^-R, i = 0 .. 2^R."""
+    r = R - level
+    pts = cascade.phi_points(nu, r)
+    i = np.arange((1 << R) + 1)
+    idx = i - t * (1 << r) - ((-nu + 1) << r)
+    ok = (idx >= 0) & (idx < pts.size)
+    out = np.zeros(i.size)
+    out[ok] = pts[idx[ok]] * 2.0 ** (level / 2.0)
+    return out
+
+
+def _combo_points(nu, level, coef, offset, R):
+    out = np.zeros((1 << R) + 1)
+    for t, a in coef.items():
+        out += float(a) * _translate_points(nu, level, offset + t, R)
+    return out
+
+
+def scaling_function_points(nu, k, m, R):
+    L, Rr, _, _ = _edge_float(nu)
+    size = 1 << k
+    if m < nu:
+        return _combo_points(nu, k, L[m], 0, R)
+    if m >= size - nu:
+        return _combo_points(nu, k, Rr[size - 1 - m], size, R)
+    return _translate_points(nu, k, m, R)
+
+
+def wavelet_points(nu, k, m, R):
+    from . import filters
+    _, _, WL, WR = _edge_float(nu)
+    size = 1 << k
+    if m < nu:
+        return _combo_points(nu, k + 1, WL[m], 0, R)
+    if m >= size - nu:
+        return _combo_points(nu, k + 1, WR[size - 1 - m], 2 * size, R)
+    g = filters.wavelet(nu)
+    coef = {2 * m + c: g[ci] for ci, c in enumerate(range(-nu + 1, nu + 1))}
+    return _combo_points(nu, k + 1, coef, 0, R)

@@ -1,0 +1,173 @@
+"""Dense products with the Walsh-to-wavelet section and its adjoint.
+
+Test infrastructure (see the package header).
+
+1D.  With J = j + q (N = 2^J Walsh functions, M = 2^j wavelet functions),
+the matrix of Sec. 4 composed with the change of basis of the Remark on
+compressive sensing is  A[n, c] = <r_c, w_n>,  r_c the c-th function of
+C_{psi,j}.  w_n (n < N) is constant on each cell [i/N, (i+1)/N) (Def. 3.1
+with the non-terminating expansion), so A = H C exactly, with
+H[n, i] = w_n(i/N) from Def. 3.1 and C the cell integrals (module basis).
+Forward: y = A[Omega, :] x; adjoint: x = A[Omega, :]^T y (everything is
+real; Omega in increasing order as in the Notation section).
+
+2D.  Sampling functions w_{n1} (x) w_{n2}, reconstruction functions the
+isotropic 2D wavelet basis in the quadtree layout (reading: the paper
+defines only phi (x) phi and Algorithm 2; the 2D wavelet convention is the
+standard square one).  By Fubini (Sec. 5) every entry is a product of 1D
+entries, so alpha = sum over (level, band) of A_a X_band A_b^T with the 1D
+blocks A_a, A_b of B_{phi,k} / B_{psi,k}; y = alpha[Omega] in increasing
+linear index n1 N + n2, n1 belonging to the first coordinate.
+
+Parity status: pinned (Haar closed form, norm bound, polynomial
+reproduction, Fubini against the dense Kronecker matrix, Table 1 for DB2).
+"""
+import numpy as np
+
+from . import basis, walsh
+
+
+def walsh_rows(J, rows, C):
+    """Rows `rows` of H C (H = Walsh matrix of order 2^J), C sparse (2^J x K)."""
+    out = np.empty((len(rows), C.shape[1]))
+    step = 256
+    for a in range(0, len(rows), step):
+        Hr = walsh.walsh_matrix(J, rows=rows[a:a + step])
+        out[a:a + step] = (C.T @ Hr.T).T
+    return out
+
+
+def walsh_cols(J, C):
+    """Full H C, built in row chunks."""
+    return walsh_rows(J, np.arange(1 << J), C)
+
+
+class Config:
+    """Sizes of one operator: M = 2^j per dimension, N = 2^(j+q), coarse level j0."""
+
+    def __init__(self, nu, j, q, j0=None):
+        if j0 is None:
+            j0 = max(0, int(np.ceil(np.log2(2 * nu)))) if nu >= 2 else 0
+        if q < 1 or j < j0 or (1 << j0) < 2 * nu and nu >= 2:
+            raise ValueError("invalid (nu, j, q, j0)")
+        self.nu, self.j, self.q, self.j0 = nu, j, q, j0
+        self.J = j + q
+        self.M, self.N = 1 << j, 1 << (j + q)
+
+
+def matrix_1d(cfg):
+    """Dense N x M matrix A of the wavelet basis C_{psi,j}."""
+    C = basis.multiscale(cfg.nu, cfg.j, cfg.j0, cfg.J)
+    return walsh_cols(cfg.J, C)
+
+
+def scaling_matrix_1d(cfg):
+    """Dense N x M matrix of the scaling basis B_{phi,j} (P_N U P_M of Sec. 4)."""
+    C = basis.block(cfg.nu, cfg.j, cfg.J, True)
+    return walsh_cols(cfg.J, C)
+
+
+def forward_1d(A, x, omega=None):
+    y = A @ x
+    return y if omega is None else y[np.asarray(omega)]
+
+
+def adjoint_1d(A, y, omega=None):
+    if omega is None:
+        return A.T @ y
+    return A[np.asarray(omega)].T @ y
+
+
+class Blocks2D:
+    """1D Walsh-coefficient blocks A_phi[k], A_psi[k] (N x 2^k) for the 2D basis."""
+
+    def __init__(self, cfg, rows=None):
+        self.cfg = cfg
+        rows = np.arange(cfg.N) if rows is None else np.asarray(rows)
+        self.rows = rows
+        nu, J = cfg.nu, cfg.J
+        self.phi = {cfg.j0: walsh_rows(J, rows, basis.block(nu, cfg.j0, J, True))}
+        self.psi = {}
+        for k in range(cfg.j0, cfg.j):
+            self.phi.setdefault(k, walsh_rows(J, rows, basis.block(nu, k, J, True)))
+            self.psi[k] = walsh_rows(J, rows, basis.block(nu, k, J, False))
+
+    def bands(self):
+        """Yield (row slice, col slice, first-dim block, second-dim block)."""
+        c = self.cfg
+        s0 = slice(0, 1 << c.j0)
+        yield s0, s0, self.phi[c.j0], self.phi[c.j0]
+        for k in range(c.j0, c.j):
+            lo, hi = slice(0, 1 << k), slice(1 << k, 1 << (k + 1))
+            yield lo, hi, self.phi[k], self.psi[k]
+            yield hi, lo, self.psi[k], self.phi[k]
+            yield hi, hi, self.psi[k], self.psi[k]
+
+
+def _forward_2d(rows_blocks, col_blocks, X, omega):
+    """alpha[rows_blocks.rows, col_blocks.rows] = sum_bands A_a X_band A_b^T."""
+    cfg = rows_blocks.cfg
+    alpha = np.zeros((len(rows_blocks.rows), len(col_blocks.rows)))
+    it_r = rows_blocks.bands()
+    it_c = col_blocks.bands()
+    for (rs, cs, Aa, _), (_, _, _, Bb) in zip(it_r, it_c):
+        alpha += Aa @ X[rs, cs] @ Bb.T
+    if omega is None:
+        return alpha
+    return alpha.ravel()[np.asarray(omega)]
+
+
+def forward_2d_full(blocks, X, omega=None):
+    """Full N x N alpha (blocks must hold all N rows)."""
+    return _forward_2d(blocks, blocks, X, omega)
+
+
+def adjoint_2d_full(blocks, y, omega=None):
+    """x = A^T P_Omega^T y with the full blocks; returns the M x M quadtree array."""
+    cfg = blocks.cfg
+    if omega is None:
+        Y = np.asarray(y).reshape(cfg.N, cfg.N)
+    else:
+        Y = np.zeros(cfg.N * cfg.N)
+        Y[np.asarray(omega)] = y
+        Y = Y.reshape(cfg.N, cfg.N)
+    X = np.zeros((cfg.M, cfg.M))
+    for rs, cs, Aa, Bb in blocks.bands():
+        X[rs, cs] += Aa.T @ Y @ Bb
+    return X
+
+
+def quadtree_functions(cfg, c1, c2):
+    """For quadtree position (c1, c2): ((kind1, level1, idx1), (kind2, level2, idx2))."""
+    j0 = cfg.j0
+    if c1 < (1 << j0) and c2 < (1 << j0):
+        return ("phi", j0, c1), ("phi", j0, c2)
+    k = max(int(c1).bit_length(), int(c2).bit_length()) - 1
+    if c1 < (1 << k):
+        return ("phi", k, c1), ("psi", k, c2 - (1 << k))
+    if c2 < (1 << k):
+        return ("psi", k, c1 - (1 << k)), ("phi", k, c2)
+    return ("psi", k, c1 - (1 << k)), ("psi", k, c2 - (1 << k))
+
+
+def dense_2d(cfg):
+    """Dense (N^2 x M^2) matrix by Kronecker products of 1D columns (tiny sizes only)."""
+    J, nu = cfg.J, cfg.nu
+    cols = {}
+
+    def col(kind, level, idx):
+        key = (kind, level, idx)
+        if key not in cols:
+            f = basis.scaling_function_cells if kind == "phi" else basis.wavelet_cells
+            i, v = f(nu, level, idx, J)
+            c = np.zeros(cfg.N)
+            c[i] = v
+            cols[key] = walsh.walsh_matrix(J) @ c
+        return cols[key]
+
+    A2 = np.zeros((cfg.N * cfg.N, cfg.M * cfg.M))
+    for c1 in range(cfg.M):
+        for c2 in range(cfg.M):
+            f1, f2 = quadtree_functions(cfg, c1, c2)
+            A2[:, c1 * cfg.M + c2] = np.kron(col(*f1), col(*f2))
+    return A2
