@@ -1,0 +1,138 @@
+/*
+ * wh2wav: fast products with the Walsh-Hadamard-to-wavelet change-of-basis
+ * section and its adjoint, on AMD Instinct MI355X (gfx950).
+ *
+ * Operation (Antun, "Recovering wavelet coefficients from binary samples
+ * using fast transforms"):
+ *
+ *   forward   y = P_Omega A x
+ *   adjoint   x = A^T P_Omega^T y
+ *
+ * A is the N x M section <r_c, w_n> of the change-of-basis matrix between
+ * the sequency-ordered Walsh functions w_n (Def. 3.1) and the multiscale
+ * Daubechies basis C_{psi,j} on [0,1] with vanishing-moment-preserving
+ * boundary functions (Sec. 3.2).  In one dimension M = 2^j and N = 2^{j+q};
+ * in two dimensions A acts on M x M coefficient arrays and produces N x N
+ * Walsh samples (Sec. 5, Algorithm 2), so the section is N^2 x M^2.  The
+ * product is computed in O(N log N) (Algorithm 1 and Lemma 3.3) without
+ * forming A: inverse DWT C_{psi,j} -> B_{phi,j} (Remark on compressive
+ * sensing), a product with O(2^q) tables of Walsh coefficients of the
+ * scaling function (the operators D_l of Sec. 4.1 and Prop. 4.2), a
+ * sequency-ordered fast Walsh-Hadamard transform, and the gather onto
+ * Omega (P_Omega, Notation).  Everything is real (Algorithm 1 works in R),
+ * so the adjoint is the transpose.
+ *
+ * Layouts
+ *   x   1D: M values in C_{psi,j} order [a_{J0} | d_{J0} | ... | d_{j-1}].
+ *       2D: M x M row-major array in the quadtree (square / isotropic)
+ *       layout: the scaling block at [0, 2^{J0})^2 and, for each level
+ *       k = J0..j-1, the bands [0,2^k) x [2^k,2^{k+1}) (phi (x) psi),
+ *       [2^k,2^{k+1}) x [0,2^k) (psi (x) phi), [2^k,2^{k+1})^2 (psi (x) psi);
+ *       the first array index belongs to the first coordinate.
+ *   y   m = |Omega| values in increasing order of the sequency index n
+ *       (1D) or of n1 * N + n2 (2D), n1 the first coordinate.
+ *   Element type is float or double as chosen by the plan (dtype).
+ *
+ * Ownership and errors
+ *   Plans are created on the host and own their device tables; a plan is
+ *   immutable after creation and may be used from several streams at once
+ *   as long as each call has its own workspace.  x, y and ws are caller-
+ *   owned device pointers; x, y and ws must not overlap.  Calls are
+ *   asynchronous on `stream` (a hipStream_t, or NULL for the null stream).
+ *   Every function returns WH2WAV_OK (0) or a negative status; nothing
+ *   throws across this interface.  Argument errors are detected on the host
+ *   before any launch.  wh2wav_last_error() returns a thread-local message
+ *   for the last failure on the calling thread.
+ */
+#ifndef WH2WAV_H
+#define WH2WAV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  WH2WAV_OK = 0,
+  WH2WAV_EINVAL = -1,        /* bad argument or descriptor */
+  WH2WAV_EUNSUPPORTED = -2,  /* valid but not implemented (e.g. size limits) */
+  WH2WAV_ENOMEM = -3,        /* host or device allocation failed */
+  WH2WAV_EHIP = -4,          /* a HIP runtime call or launch failed */
+  WH2WAV_EINTERNAL = -5      /* plan construction failed a self-check */
+};
+
+enum { WH2WAV_F32 = 0, WH2WAV_F64 = 1 };
+enum { WH2WAV_DB = 0 };               /* Daubechies, minimum phase (Sec. 3.2) */
+enum { WH2WAV_BD = 0 };               /* vanishing-moment-preserving edges */
+
+typedef struct wh2wav_plan_s* wh2wav_plan_t;
+
+typedef struct {
+  int dim;              /* 1 or 2 */
+  int j;                /* M = 2^j per dimension, j0 <= j */
+  int q;                /* N = 2^{j+q} per dimension, q >= 1 (Sec. 4: q > 0) */
+  int j0;               /* coarsest level J0: 2^{J0} >= 2 nu for nu >= 2 (Sec. 3.2) */
+  int nu;               /* vanishing moments, 1 (Haar) .. 10 */
+  int family;           /* WH2WAV_DB */
+  int boundary;         /* WH2WAV_BD */
+  int dtype;            /* WH2WAV_F32 or WH2WAV_F64 */
+  int64_t m;            /* |Omega|; with omega == NULL, m must equal N^dim (all samples) */
+  const int64_t* omega; /* host array of m strictly increasing linear indices in
+                           [0, N^dim), or NULL; copied during wh2wav_plan */
+} wh2wav_desc;
+
+/* Build a plan: host-side tables (Sec. 3.2, Sec. 4.1, Prop. 4.2) and their
+ * upload to the current HIP device.  *out receives the handle. */
+int wh2wav_plan(const wh2wav_desc* desc, wh2wav_plan_t* out);
+
+/* Bytes of device workspace a forward or adjoint call needs (may be 0). */
+int wh2wav_workspace_size(wh2wav_plan_t plan, size_t* bytes);
+
+/* y = P_Omega A x.  x: M^dim elements, y: m elements (device pointers). */
+int wh2wav_forward(wh2wav_plan_t plan, const void* x, void* y, void* ws, void* stream);
+
+/* x = A^T P_Omega^T y.  y: m elements, x: M^dim elements (device pointers). */
+int wh2wav_adjoint(wh2wav_plan_t plan, const void* y, void* x, void* ws, void* stream);
+
+/* Staged execution, for callers that time or interleave the stages (for
+ * example with events recorded between them on the same stream).  Running
+ * stages 0 .. count-1 in order on one stream with one workspace is exactly
+ * wh2wav_forward / wh2wav_adjoint.  Forward (direction 0): 0 = inverse DWT
+ * (C_{psi,j} -> B_{phi,j}), 1 = column pass (2D; the whole line transform in
+ * 1D), 2 = row pass with the gather onto Omega (2D).  Adjoint (direction 1):
+ * 0 = row pass with the scatter from Omega (2D; the whole line transform in
+ * 1D), 1 = column pass (2D; nothing in 1D), 2 = forward DWT.  The workspace
+ * carries the intermediates between stages. */
+int wh2wav_stage_count(wh2wav_plan_t plan, int direction, int* count);
+int wh2wav_forward_stage(wh2wav_plan_t plan, int stage, const void* x, void* y, void* ws, void* stream);
+int wh2wav_adjoint_stage(wh2wav_plan_t plan, int stage, const void* y, void* x, void* ws, void* stream);
+
+/* Release the plan and its device memory.  NULL is accepted. */
+int wh2wav_destroy(wh2wav_plan_t plan);
+
+/* Message describing the last failure on this thread ("" if none). */
+const char* wh2wav_last_error(void);
+
+/* Host-side introspection (no GPU needed): the float64 tables a plan for
+ * `desc` would upload.  `which` selects the table; at most `capacity`
+ * values are written to `out` and the full length goes to *count.
+ *   WH2WAV_TABLE_H, _G        filter taps h_c, g_c, c = -nu+1 .. nu
+ *   WH2WAV_TABLE_T            interior table T[l][s], l = -nu+1..nu-1, s < 2^q
+ *   WH2WAV_TABLE_BAND_L, _R   boundary bands of Prop. 4.2 (layout in planner.h)
+ *   WH2WAV_TABLE_SYN_L, _R    boundary blocks of the one-level synthesis matrix
+ *   WH2WAV_TABLE_ROWPTR       Omega row offsets (as doubles) */
+enum {
+  WH2WAV_TABLE_H = 0, WH2WAV_TABLE_G = 1, WH2WAV_TABLE_T = 2,
+  WH2WAV_TABLE_BAND_L = 3, WH2WAV_TABLE_BAND_R = 4,
+  WH2WAV_TABLE_SYN_L = 5, WH2WAV_TABLE_SYN_R = 6, WH2WAV_TABLE_ROWPTR = 7
+};
+int wh2wav_host_table(const wh2wav_desc* desc, int which, double* out, size_t capacity,
+                      size_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WH2WAV_H */

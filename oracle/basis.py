@@ -29,24 +29,34 @@ import scipy.sparse as sp
 from . import cascade, halfline
 
 
-def _translate_cells(nu, level, t, J, scaling=True):
+def _translate_cells(nu, level, t, J, scaling=True, extended=False):
     """(cell indices, values) of 2^{level/2} f(2^level x - t) on [0, 1), f = phi or psi."""
     r = J - level
     tab = cascade.phi_cells(nu, r) if scaling else cascade.psi_cells(nu, r)
     s = np.arange(tab.lo, tab.lo + tab.values.size)
     i = s + t * (1 << r)
     keep = (i >= 0) & (i < (1 << J))
-    return i[keep], tab.values[keep] * 2.0 ** (-level / 2.0)
+    vals = tab.values_ld if extended else tab.values
+    return i[keep], vals[keep] * (np.longdouble(2) ** (-level) if extended else 2.0 ** (-level)) ** 0.5
 
 
 def _combo_cells(nu, level, coef, offset, J):
-    """Cell integrals of sum_t coef[t] 2^{level/2} phi(2^level x - offset - t) on [0,1)."""
-    out = np.zeros(1 << J)
+    """Cell integrals of sum_t coef[t] 2^{level/2} phi(2^level x - offset - t) on [0,1).
+
+    Formed in extended precision (the coefficients cancel strongly), then rounded.
+    """
+    out = np.zeros(1 << J, dtype=np.longdouble)
     for t, a in coef.items():
-        i, v = _translate_cells(nu, level, offset + t, J)
-        out[i] += float(a) * v
+        i, v = _translate_cells(nu, level, offset + t, J, extended=True)
+        out[i] += np.longdouble(mp_str(a)) * v
+    out = out.astype(np.float64)
     nz = np.nonzero(out)[0]
     return nz, out[nz]
+
+
+def mp_str(a):
+    import mpmath as mp
+    return mp.nstr(a, 40) if isinstance(a, mp.mpf) else repr(float(a))
 
 
 @functools.lru_cache(maxsize=None)
@@ -160,3 +170,27 @@ def wavelet_points(nu, k, m, R):
     g = filters.wavelet(nu)
     coef = {2 * m + c: g[ci] for ci, c in enumerate(range(-nu + 1, nu + 1))}
     return _combo_points(nu, k + 1, coef, 0, R)
+
+
+def halfline_scaling_cells(nu, side, m, r, cells):
+    """Cell integrals of phi^side_m over the sub-cells of the given unit cells.
+
+    Returns (values, bound), arrays of shape (len(cells), 2^r): entry [i, t] of
+    `values` is the integral of the boundary scaling function over
+    [c + t 2^-r, c + (t+1) 2^-r), c = cells[i] (level-0 units, measured from the
+    boundary point), summed in extended precision; `bound` is a rounding-error
+    bound for that sum (64 eps_ld times the sum of the absolute terms; the
+    terms cancel by up to six digits at nu = 8).
+    """
+    coef = halfline.edge_scaling(nu, side)[m]
+    tab = cascade.phi_cells(nu, r)
+    out = np.zeros((len(cells), 1 << r), dtype=np.longdouble)
+    mag = np.zeros((len(cells), 1 << r), dtype=np.longdouble)
+    sub = np.arange(1 << r)
+    for i, c in enumerate(cells):
+        for t, a in coef.items():
+            term = np.longdouble(mp_str(a)) * tab.take((c - t) * (1 << r) + sub, extended=True)
+            out[i] += term
+            mag[i] += np.abs(term)
+    eps = float(np.finfo(np.longdouble).eps)
+    return out.astype(np.float64), (64 * eps * mag).astype(np.float64) + 1e-17

@@ -32,12 +32,19 @@ from . import filters
 
 
 class CellIntegrals:
-    """Phi_r (or Psi_r) stored with an offset so that arr[s - lo] = value at s."""
+    """Phi_r (or Psi_r) stored with an offset so that arr[s - lo] = value at s.
 
-    def __init__(self, r, lo, values):
+    `values_ld` holds the same numbers in x87 extended precision (64-bit
+    mantissa); `values` is their float64 rounding.  The boundary functions are
+    combinations of translates whose coefficients reach 1e7 and cancel by up to
+    four digits (nu = 8), so their cell integrals are formed from `values_ld`.
+    """
+
+    def __init__(self, r, lo, values_ld):
         self.r = r
         self.lo = lo
-        self.values = values
+        self.values_ld = np.asarray(values_ld, dtype=np.longdouble)
+        self.values = self.values_ld.astype(np.float64)
 
     def __getitem__(self, s):
         i = s - self.lo
@@ -45,12 +52,13 @@ class CellIntegrals:
             return self.values[i]
         return 0.0
 
-    def take(self, s):
+    def take(self, s, extended=False):
         """Vectorised lookup with zeros outside the support."""
         s = np.asarray(s) - self.lo
         ok = (s >= 0) & (s < self.values.size)
-        out = np.zeros(s.shape)
-        out[ok] = self.values[s[ok]]
+        src = self.values_ld if extended else self.values
+        out = np.zeros(s.shape, dtype=src.dtype)
+        out[ok] = src[s[ok]]
         return out
 
 
@@ -67,23 +75,40 @@ def _phi0(h, nu):
     i = int(np.argmin(np.abs(w - 1.0)))
     if abs(w[i] - 1.0) > 1e-10:
         raise RuntimeError("refinement operator has no eigenvalue 1")
-    vec = np.real(v[:, i])
-    return vec / vec.sum()
+    vec = np.real(v[:, i]).astype(np.longdouble)
+    vec /= vec.sum()
+    # polish in extended precision: the other eigenvalues are at most 1/2 in modulus
+    h_ld = _taps_ld(filters.daubechies_mp(nu))
+    Tld = np.zeros((n, n), dtype=np.longdouble)
+    for a, s in enumerate(cells):
+        for ci, c in enumerate(range(-nu + 1, nu + 1)):
+            for t in (2 * s - c, 2 * s - c + 1):
+                if -nu + 1 <= t <= nu - 1:
+                    Tld[a, t + nu - 1] += h_ld[ci] / np.sqrt(np.longdouble(2))
+    for _ in range(80):
+        vec = Tld @ vec
+        vec /= vec.sum()
+    return vec
+
+
+def _taps_ld(taps_mp):
+    import mpmath as mp
+    return [np.longdouble(mp.nstr(t, 40)) for t in taps_mp]
 
 
 @functools.lru_cache(maxsize=None)
 def phi_cells(nu, r):
     """Phi_r for the Daubechies scaling function with nu vanishing moments."""
-    h = filters.daubechies(nu)
     if r == 0:
-        return CellIntegrals(0, -nu + 1, _phi0(h, nu))
+        return CellIntegrals(0, -nu + 1, _phi0(filters.daubechies(nu), nu))
+    h = _taps_ld(filters.daubechies_mp(nu))
     prev = phi_cells(nu, r - 1)
     lo, hi = (-nu + 1) << r, nu << r
     s = np.arange(lo, hi)
-    out = np.zeros(s.size)
+    out = np.zeros(s.size, dtype=np.longdouble)
     for ci, c in enumerate(range(-nu + 1, nu + 1)):
-        out += h[ci] * prev.take(s - c * (1 << (r - 1)))
-    return CellIntegrals(r, lo, out / np.sqrt(2.0))
+        out += h[ci] * prev.take(s - c * (1 << (r - 1)), extended=True)
+    return CellIntegrals(r, lo, out / np.sqrt(np.longdouble(2)))
 
 
 @functools.lru_cache(maxsize=None)
@@ -92,15 +117,15 @@ def psi_cells(nu, r):
     if r == 0:
         fine = psi_cells(nu, 1)
         s = np.arange(-nu + 1, nu)
-        return CellIntegrals(0, -nu + 1, fine.take(2 * s) + fine.take(2 * s + 1))
-    g = filters.wavelet(nu)
+        return CellIntegrals(0, -nu + 1, fine.take(2 * s, True) + fine.take(2 * s + 1, True))
+    g = _taps_ld(filters.wavelet_mp(nu))
     prev = phi_cells(nu, r - 1)
     lo, hi = (-nu + 1) << r, nu << r
     s = np.arange(lo, hi)
-    out = np.zeros(s.size)
+    out = np.zeros(s.size, dtype=np.longdouble)
     for ci, c in enumerate(range(-nu + 1, nu + 1)):
-        out += g[ci] * prev.take(s - c * (1 << (r - 1)))
-    return CellIntegrals(r, lo, out / np.sqrt(2.0))
+        out += g[ci] * prev.take(s - c * (1 << (r - 1)), extended=True)
+    return CellIntegrals(r, lo, out / np.sqrt(np.longdouble(2)))
 
 
 @functools.lru_cache(maxsize=None)

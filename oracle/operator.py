@@ -171,3 +171,45 @@ def dense_2d(cfg):
             f1, f2 = quadtree_functions(cfg, c1, c2)
             A2[:, c1 * cfg.M + c2] = np.kron(col(*f1), col(*f2))
     return A2
+
+
+# ---------------------------------------------------------------------------
+# Entry-by-entry evaluation for sizes where the full product is too costly.
+
+def forward_entries_2d(cfg, X, n1s, n2s):
+    """alpha[n1s[i], n2s[i]] for each i, from rows of the 1D blocks (plain sums)."""
+    n1s, n2s = np.asarray(n1s), np.asarray(n2s)
+    rows = np.unique(np.concatenate([n1s, n2s]))
+    B = Blocks2D(cfg, rows=rows)
+    pos = {int(r): i for i, r in enumerate(rows)}
+    i1 = np.array([pos[int(v)] for v in n1s])
+    i2 = np.array([pos[int(v)] for v in n2s])
+    out = np.zeros(n1s.size)
+    for rs, cs, Aa, Bb in B.bands():
+        out += np.einsum("ia,ab,ib->i", Aa[i1], X[rs, cs], Bb[i2])
+    return out
+
+
+def walsh_column(cfg, kind, level, idx):
+    """Column <f, w_n>, n < N, of one 1D basis function (kind 'phi' or 'psi')."""
+    f = basis.scaling_function_cells if kind == "phi" else basis.wavelet_cells
+    cells, vals = f(cfg.nu, level, idx, cfg.J)
+    out = np.zeros(cfg.N)
+    step = 1024
+    for a in range(0, cfg.N, step):
+        H = walsh.walsh_matrix_bits(cfg.J, rows=np.arange(a, min(cfg.N, a + step)), cols=cells)
+        out[a:a + step] = H @ vals
+    return out
+
+
+def adjoint_entries_2d(cfg, y, omega, positions):
+    """x[c1, c2] = sum_i A2[omega_i, (c1, c2)] y_i for each quadtree position (plain sums)."""
+    omega = np.asarray(omega)
+    n1, n2 = omega // cfg.N, omega % cfg.N
+    out = []
+    for c1, c2 in positions:
+        f1, f2 = quadtree_functions(cfg, c1, c2)
+        a1 = walsh_column(cfg, *f1)
+        a2 = walsh_column(cfg, *f2)
+        out.append(np.dot(a1[n1] * a2[n2], y))
+    return np.array(out)

@@ -51,3 +51,22 @@ def walsh_matrix(J, rows=None, cols=None):
 def xor_dyadic(k1, k2):
     """x ⊕ y for x = k1 / 2^J, y = k2 / 2^J: digitwise XOR (Sec. 3.1)."""
     return k1 ^ k2
+
+
+def walsh_matrix_bits(J, rows, cols):
+    """Same matrix as `walsh_matrix`, via the parity of gray(n) AND bitrev_J(k).
+
+    Def. 3.1 pairs digit n^(i) + n^(i+1) (bit i-1 of gray(n) = n xor (n >> 1))
+    with the i-th binary digit of k / 2^J (bit J-i of k, i.e. bit i-1 of the
+    J-bit reversal of k); the exponent is the number of common set bits.  Used
+    for large sampled columns; pinned equal to `walsh_matrix` by the tests.
+    """
+    n = np.asarray(rows, dtype=np.int64)
+    k = np.asarray(cols, dtype=np.int64)
+    # digits beyond J do not enter (x has J digits); gray bit J-1 uses n^(J+1)
+    gray = (n ^ (n >> 1)) & ((1 << J) - 1)
+    rev = np.zeros_like(k)
+    for b in range(J):
+        rev |= ((k >> b) & 1) << (J - 1 - b)
+    parity = np.bitwise_count(np.bitwise_and.outer(gray, rev)) & 1
+    return np.where(parity == 1, -1.0, 1.0)

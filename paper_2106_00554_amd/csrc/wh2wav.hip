@@ -1,0 +1,781 @@
+// Kernels and C-ABI entry points of the Walsh-to-boundary-wavelet operator.
+//
+// One 1D line of the operator in the scaling basis B_{phi,j} (the matrix of
+// Sec. 4, called G in Sec. 5) factors through the dyadic cells of [0, 1]:
+// for p < M = 2^j and t in [0, 1), Lemma 3.2 (1) and (3) give
+//     w_n((p + t)/M) = w_n(p/M) w_s(t),     s = floor(n / M) < 2^q,
+// so that (Lemma 3.3)
+//     <f, w_n> = sum_p w_n(p/M) L[p, s],
+//     L[p, s] = sum_m xi_m 2^{-j/2} W[phi_{0,p-m}](s)   (plus Prop. 4.2 edges).
+// The stages are therefore
+//   1. table product  L[:, s] = (2nu-1)-tap correlation of xi with the table
+//      T[l][s] (operators D_l, Sec. 4.1) plus the dense boundary bands;
+//   2. one M-point Walsh-Hadamard transform per phase s (2^q of them);
+//   3. index map: w_{sM+b}(p/M) = H_nat[k, p] with the natural (Sylvester)
+//      index k = bitrev_j(gray(b)) xor (s & 1) -- only the parity of s enters,
+//      through digit n^(j+1) of Def. 3.1;
+//   4. gather onto Omega (P_Omega) or scatter for the adjoint.
+// This is the same result as the paper's sum over l of D_l H_l (Alg. 1) with
+// the linear table product moved in front of the transform, which needs 2^q
+// transforms of length M instead of 2nu-1 transforms of length N.
+//
+// In 2D (Alg. 2, alpha = G xi G^T) a column pass applies G along the first
+// index and writes an N x M intermediate whose rows are in natural order
+// r = s M + k; the row pass applies G along the second index of each row and
+// gathers the samples of Omega in row n1 = seq(r).  The adjoint runs the same
+// passes transposed.  The inverse DWT from C_{psi,j} to B_{phi,j} (Remark on
+// compressive sensing) runs first in the forward direction and its transpose
+// last in the adjoint.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/wh2wav.h"
+#include "planner.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_OK(call)                                                        \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return fail(WH2WAV_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kThreads = 256;
+
+template <typename T>
+struct Tables {
+  const T* h;      // 2nu
+  const T* g;      // 2nu
+  const T* tabT;   // (2nu-1) * Q
+  const T* bandL;  // (2nu-1) * nu * Q
+  const T* bandR;  // (2nu-1) * nu * Q
+  const T* synL;   // (3nu-1) * 2nu
+  const T* synR;   // (3nu-1) * 2nu
+  int nu, q, Q;
+};
+
+struct OmegaDev {
+  const uint32_t* mask;    // rows * wpr, NULL when every sample is taken
+  const int64_t* row_ptr;  // rows + 1
+  int64_t wpr;             // words per row
+  int full;
+};
+
+__device__ __forceinline__ uint32_t bitrev_bits(uint32_t x, int bits) {
+  return bits == 0 ? 0u : (__brev(x) >> (32 - bits));
+}
+__device__ __forceinline__ uint32_t gray_inverse(uint32_t x) {
+  x ^= x >> 1;
+  x ^= x >> 2;
+  x ^= x >> 4;
+  x ^= x >> 8;
+  x ^= x >> 16;
+  return x;
+}
+// natural position (within phase s) of the sequency index b < M = 2^j
+__device__ __forceinline__ uint32_t natural_of(uint32_t b, uint32_t s, int j) {
+  return bitrev_bits(b ^ (b >> 1), j) ^ (s & 1u);
+}
+// sequency index of natural position k of phase s
+__device__ __forceinline__ uint32_t sequency_of(uint32_t k, uint32_t s, int j) {
+  return gray_inverse(bitrev_bits(k ^ (s & 1u), j));
+}
+
+// ------------------------------------------------------------------ IDWT
+// One level of the inverse DWT along lines: [a_k | d_k] (2^k + 2^k values)
+// -> scaling coefficients at level k+1 (2^{k+1} values).  Interior columns
+// use the filters (phi_{k,m} = sum_c h_c phi_{k+1,2m+c}); boundary columns
+// use the synthesis bands.  One thread per output value.
+template <typename T>
+__global__ void k_synth(const T* __restrict__ in, T* __restrict__ out, int64_t lines,
+                        int64_t line_stride, int64_t elem_stride, int k, int line_fast,
+                        Tables<T> t) {
+  const int64_t half = int64_t(1) << k, size = 2 * half;
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gid >= lines * size) return;
+  const int64_t line = line_fast ? gid % lines : gid / size;
+  const int64_t n = line_fast ? gid / lines : gid % size;
+  const T* src = in + line * line_stride;
+  const int nu = t.nu;
+  auto A = [&](int64_t m) { return src[m * elem_stride]; };
+  auto D = [&](int64_t m) { return src[(half + m) * elem_stride]; };
+  T acc = 0;
+  const int64_t right_first = half - nu > nu ? half - nu : nu;  // first right-boundary position
+  int64_t mlo = (n - nu + 1) / 2;  // ceil((n - nu) / 2) for n - nu >= -1
+  if (n - nu < 0) mlo = 0;
+  if (mlo < nu) mlo = nu;
+  int64_t mhi = (n + nu - 1) / 2;
+  if (mhi > half - nu - 1) mhi = half - nu - 1;
+  for (int64_t m = mlo; m <= mhi; ++m) {
+    const int c = int(n - 2 * m);
+    if (c < -nu + 1 || c > nu) continue;
+    acc += A(m) * t.h[c + nu - 1] + D(m) * t.g[c + nu - 1];
+  }
+  const int rows = 3 * nu - 1;
+  if (n < rows)
+    for (int cc = 0; cc < nu && cc < half; ++cc)
+      acc += t.synL[n * 2 * nu + cc] * A(cc) + t.synL[n * 2 * nu + nu + cc] * D(cc);
+  if (n >= size - rows) {
+    const int64_t i = n - (size - rows);
+    for (int cc = 0; cc < nu; ++cc) {
+      const int64_t pos = half - 1 - cc;
+      if (pos < right_first) continue;
+      acc += t.synR[i * 2 * nu + cc] * A(pos) + t.synR[i * 2 * nu + nu + cc] * D(pos);
+    }
+  }
+  out[line * line_stride + n * elem_stride] = acc;
+}
+
+// Transpose of k_synth (one level of the forward DWT).
+template <typename T>
+__global__ void k_analysis(const T* __restrict__ in, T* __restrict__ out, int64_t lines,
+                           int64_t line_stride, int64_t elem_stride, int k, int line_fast,
+                           Tables<T> t) {
+  const int64_t half = int64_t(1) << k, size = 2 * half;
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gid >= lines * size) return;
+  const int64_t line = line_fast ? gid % lines : gid / size;
+  const int64_t o = line_fast ? gid / lines : gid % size;
+  const T* src = in + line * line_stride;
+  const int nu = t.nu;
+  const int kind = o >= half ? 1 : 0;
+  const int64_t m = o - kind * half;
+  const int64_t right_first = half - nu > nu ? half - nu : nu;
+  const int rows = 3 * nu - 1;
+  T acc = 0;
+  if (m >= nu && m < right_first) {
+    const T* taps = kind ? t.g : t.h;
+    for (int c = -nu + 1; c <= nu; ++c) acc += taps[c + nu - 1] * src[(2 * m + c) * elem_stride];
+  } else if (m < nu) {
+    for (int r = 0; r < rows && r < size; ++r) acc += t.synL[r * 2 * nu + kind * nu + m] * src[r * elem_stride];
+  } else {
+    const int64_t cc = half - 1 - m;
+    for (int r = 0; r < rows; ++r)
+      acc += t.synR[r * 2 * nu + kind * nu + cc] * src[(size - rows + r) * elem_stride];
+  }
+  out[line * line_stride + o * elem_stride] = acc;
+}
+
+// Plain fill (kept as a kernel so that the path records no memset nodes when
+// a caller captures it into a graph).
+template <typename T>
+__global__ void k_fill(T* __restrict__ out, int64_t n, T value) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = value;
+}
+
+template <typename T>
+void launch_fill(T* out, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill<T>, dim3(unsigned((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, out, n, T(0));
+}
+
+// ------------------------------------------------------ shared helpers
+template <typename T>
+__device__ void fwht_lds(T* buf, int M, int tid, int nthreads) {
+  for (int hl = 1; hl < M; hl <<= 1) {
+    for (int b = tid; b < M / 2; b += nthreads) {
+      const int i = ((b / hl) * 2 * hl) + (b % hl);
+      const T a = buf[i], c = buf[i + hl];
+      buf[i] = a + c;
+      buf[i + hl] = a - c;
+    }
+    __syncthreads();
+  }
+}
+
+// Exclusive prefix of popcounts of `words` mask words into pre[] (LDS).
+__device__ void row_prefix(const uint32_t* __restrict__ words, int64_t wpr, int* pre, int* scratch,
+                           int tid, int nthreads) {
+  const int64_t chunk = (wpr + nthreads - 1) / nthreads;
+  const int64_t w0 = tid * chunk, w1 = w0 + chunk < wpr ? w0 + chunk : wpr;
+  int local = 0;
+  for (int64_t w = w0; w < w1; ++w) local += __popc(words[w]);
+  scratch[tid] = local;
+  __syncthreads();
+  for (int off = 1; off < nthreads; off <<= 1) {
+    int v = tid >= off ? scratch[tid - off] : 0;
+    __syncthreads();
+    scratch[tid] += v;
+    __syncthreads();
+  }
+  int run = scratch[tid] - local;
+  for (int64_t w = w0; w < w1; ++w) {
+    pre[w] = run;
+    run += __popc(words[w]);
+  }
+  __syncthreads();
+}
+
+// L[p, s] for one phase s from xi in LDS (table product with boundary bands).
+template <typename T>
+__device__ void table_product(const T* xi, T* L, int M, int s, int tid, int nthreads,
+                              const Tables<T>& t) {
+  const int nu = t.nu, Q = t.Q, band = 2 * nu - 1;
+  const int right_first = M - nu > nu ? M - nu : nu;
+  for (int p = tid; p < M; p += nthreads) {
+    T acc = 0;
+    for (int l = -nu + 1; l <= nu - 1; ++l) {
+      const int m = p - l;
+      if (m >= nu && m < right_first) acc += xi[m] * t.tabT[(l + nu - 1) * Q + s];
+    }
+    if (p < band)
+      for (int m = 0; m < nu && m < M; ++m) acc += xi[m] * t.bandL[(p * nu + m) * Q + s];
+    if (p >= M - band) {
+      const int i = p - (M - band);
+      for (int mp = 0; mp < nu; ++mp) {
+        const int m = M - 1 - mp;
+        if (m < right_first) continue;
+        acc += xi[m] * t.bandR[(i * nu + mp) * Q + s];
+      }
+    }
+    L[p] = acc;
+  }
+}
+
+// xi[m] += sum_p table(p, m, s) R[p] for one phase s (transpose of table_product).
+template <typename T>
+__device__ void table_product_t(const T* R, T* xi, int M, int s, int tid, int nthreads,
+                                const Tables<T>& t) {
+  const int nu = t.nu, Q = t.Q, band = 2 * nu - 1;
+  const int right_first = M - nu > nu ? M - nu : nu;
+  for (int m = tid; m < M; m += nthreads) {
+    T acc = 0;
+    if (m >= nu && m < right_first) {
+      for (int l = -nu + 1; l <= nu - 1; ++l) acc += R[m + l] * t.tabT[(l + nu - 1) * Q + s];
+    } else if (m < nu) {
+      for (int p = 0; p < band && p < M; ++p) acc += R[p] * t.bandL[(p * nu + m) * Q + s];
+    } else {
+      const int mp = M - 1 - m;
+      for (int i = 0; i < band; ++i) acc += R[M - band + i] * t.bandR[(i * nu + mp) * Q + s];
+    }
+    xi[m] += acc;
+  }
+}
+
+// ------------------------------------------------------------ line kernels
+// Forward G on lines.  gather == 0: write the N outputs of each line in natural
+// order r = s M + k at out + line * out_ls + r * out_es.  gather == 1: line
+// `line` is natural row r = line of the 2D intermediate (or the single 1D
+// line when dim1 != 0); its samples in Omega go to y.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_fwd_lines(const T* __restrict__ in, int64_t in_ls, int64_t in_es, T* __restrict__ out,
+            int64_t out_ls, int64_t out_es, int j, int gather, int dim1, Tables<T> t,
+            OmegaDev om) {
+  extern __shared__ unsigned char smem_raw[];
+  const int M = 1 << j, Q = t.Q, tid = threadIdx.x, nt = blockDim.x;
+  T* xi = reinterpret_cast<T*>(smem_raw);
+  T* L = xi + M;
+  int* pre = reinterpret_cast<int*>(L + M);
+  int* scratch = pre + (gather && !om.full ? om.wpr : 0);
+  const int64_t line = blockIdx.x;
+  for (int p = tid; p < M; p += nt) xi[p] = in[line * in_ls + p * in_es];
+  int64_t n1 = 0, base = 0;
+  const uint32_t* words = nullptr;
+  if (gather) {
+    if (!dim1) {
+      const uint32_t s1 = uint32_t(line >> j), k1 = uint32_t(line & (M - 1));
+      n1 = int64_t(s1) * M + sequency_of(k1, s1, j);
+    }
+    base = om.row_ptr[n1];
+    if (!om.full) {
+      words = om.mask + n1 * om.wpr;
+      row_prefix(words, om.wpr, pre, scratch, tid, nt);
+    }
+  }
+  __syncthreads();
+  for (int s = 0; s < Q; ++s) {
+    table_product(xi, L, M, s, tid, nt, t);
+    __syncthreads();
+    fwht_lds(L, M, tid, nt);
+    if (!gather) {
+      for (int k = tid; k < M; k += nt) out[line * out_ls + (int64_t(s) * M + k) * out_es] = L[k];
+    } else if (om.full) {
+      const int64_t N = int64_t(M) * Q;
+      for (int b = tid; b < M; b += nt)
+        out[base + int64_t(s) * M + b] = L[natural_of(uint32_t(b), uint32_t(s), j)];
+      (void)N;
+    } else {
+      const int64_t w0 = (int64_t(s) * M) >> 5, w1 = (int64_t(s + 1) * M + 31) >> 5;
+      for (int64_t w = w0 + tid; w < w1; w += nt) {
+        uint32_t bits = words[w];
+        int idx = pre[w];
+        while (bits) {
+          const int bit = __ffs(bits) - 1;
+          bits &= bits - 1;
+          const int64_t n2 = w * 32 + bit;
+          if (n2 >= int64_t(s + 1) * M || n2 < int64_t(s) * M) { ++idx; continue; }
+          const uint32_t b = uint32_t(n2 - int64_t(s) * M);
+          out[base + idx] = L[natural_of(b, uint32_t(s), j)];
+          ++idx;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Adjoint G^T on lines.  scatter == 0: read N natural-order values per line
+// from in + line * in_ls + r * in_es.  scatter == 1: line is natural row r of
+// the 2D intermediate (or the 1D line); its Omega samples come from y.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_adj_lines(const T* __restrict__ in, int64_t in_ls, int64_t in_es, T* __restrict__ out,
+            int64_t out_ls, int64_t out_es, int j, int scatter, int dim1, Tables<T> t,
+            OmegaDev om) {
+  extern __shared__ unsigned char smem_raw[];
+  const int M = 1 << j, Q = t.Q, tid = threadIdx.x, nt = blockDim.x;
+  T* xi = reinterpret_cast<T*>(smem_raw);
+  T* R = xi + M;
+  int* pre = reinterpret_cast<int*>(R + M);
+  int* scratch = pre + (scatter && !om.full ? om.wpr : 0);
+  const int64_t line = blockIdx.x;
+  for (int p = tid; p < M; p += nt) xi[p] = 0;
+  int64_t n1 = 0, base = 0;
+  const uint32_t* words = nullptr;
+  if (scatter) {
+    if (!dim1) {
+      const uint32_t s1 = uint32_t(line >> j), k1 = uint32_t(line & (M - 1));
+      n1 = int64_t(s1) * M + sequency_of(k1, s1, j);
+    }
+    base = om.row_ptr[n1];
+    if (!om.full) {
+      words = om.mask + n1 * om.wpr;
+      row_prefix(words, om.wpr, pre, scratch, tid, nt);
+    }
+  }
+  __syncthreads();
+  for (int s = 0; s < Q; ++s) {
+    if (!scatter) {
+      for (int k = tid; k < M; k += nt) R[k] = in[line * in_ls + (int64_t(s) * M + k) * in_es];
+    } else if (om.full) {
+      for (int b = tid; b < M; b += nt)
+        R[natural_of(uint32_t(b), uint32_t(s), j)] = in[base + int64_t(s) * M + b];
+    } else {
+      for (int k = tid; k < M; k += nt) R[k] = 0;
+      __syncthreads();
+      const int64_t w0 = (int64_t(s) * M) >> 5, w1 = (int64_t(s + 1) * M + 31) >> 5;
+      for (int64_t w = w0 + tid; w < w1; w += nt) {
+        uint32_t bits = words[w];
+        int idx = pre[w];
+        while (bits) {
+          const int bit = __ffs(bits) - 1;
+          bits &= bits - 1;
+          const int64_t n2 = w * 32 + bit;
+          if (n2 >= int64_t(s + 1) * M || n2 < int64_t(s) * M) { ++idx; continue; }
+          const uint32_t b = uint32_t(n2 - int64_t(s) * M);
+          R[natural_of(b, uint32_t(s), j)] = in[base + idx];
+          ++idx;
+        }
+      }
+    }
+    __syncthreads();
+    fwht_lds(R, M, tid, nt);
+    table_product_t(R, xi, M, s, tid, nt, t);
+    __syncthreads();
+  }
+  for (int m = tid; m < M; m += nt) out[line * out_ls + m * out_es] = xi[m];
+}
+
+}  // namespace
+
+// ======================================================== plan + entry points
+struct wh2wav_plan_s {
+  wh2wav::HostPlan host;
+  void* d_tables = nullptr;   // element type = dtype
+  uint32_t* d_mask = nullptr;
+  int64_t* d_row_ptr = nullptr;
+  size_t off_h = 0, off_g = 0, off_T = 0, off_BL = 0, off_BR = 0, off_SL = 0, off_SR = 0;
+};
+
+namespace {
+
+template <typename T>
+Tables<T> tables_of(const wh2wav_plan_s* p) {
+  const T* base = static_cast<const T*>(p->d_tables);
+  Tables<T> t;
+  t.h = base + p->off_h;
+  t.g = base + p->off_g;
+  t.tabT = base + p->off_T;
+  t.bandL = base + p->off_BL;
+  t.bandR = base + p->off_BR;
+  t.synL = base + p->off_SL;
+  t.synR = base + p->off_SR;
+  t.nu = p->host.nu;
+  t.q = p->host.q;
+  t.Q = p->host.Q;
+  return t;
+}
+
+OmegaDev omega_of(const wh2wav_plan_s* p) {
+  OmegaDev o;
+  o.mask = p->d_mask;
+  o.row_ptr = p->d_row_ptr;
+  o.wpr = p->host.words_per_row;
+  o.full = p->host.full_omega ? 1 : 0;
+  return o;
+}
+
+size_t line_smem(const wh2wav_plan_s* p, size_t elem, bool omega_side) {
+  size_t b = 2 * size_t(p->host.M) * elem;
+  if (omega_side && !p->host.full_omega) b += sizeof(int) * (size_t(p->host.words_per_row) + kThreads);
+  return b;
+}
+
+constexpr size_t kMaxLds = 160 * 1024;
+
+template <typename T>
+int check_and_set_smem(const void* kernel, size_t bytes) {
+  if (bytes > kMaxLds) return fail(WH2WAV_EUNSUPPORTED, "line too long for the LDS line kernels");
+  if (bytes > 64 * 1024)
+    HIP_OK(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
+  return WH2WAV_OK;
+}
+
+template <typename T>
+int launch_synth(const wh2wav_plan_s* p, const T* in, T* out, int64_t lines, int64_t ls, int64_t es,
+                 int k, bool line_fast, bool analysis, hipStream_t st) {
+  const int64_t total = lines * (int64_t(2) << k);
+  const int64_t blocks = (total + kThreads - 1) / kThreads;
+  if (analysis)
+    hipLaunchKernelGGL(k_analysis<T>, dim3(unsigned(blocks)), dim3(kThreads), 0, st, in, out, lines, ls, es, k,
+                       int(line_fast), tables_of<T>(p));
+  else
+    hipLaunchKernelGGL(k_synth<T>, dim3(unsigned(blocks)), dim3(kThreads), 0, st, in, out, lines, ls, es, k,
+                       int(line_fast), tables_of<T>(p));
+  HIP_OK(hipGetLastError());
+  return WH2WAV_OK;
+}
+
+// Forward stages: 0 = inverse DWT, 1 = column pass (2D) / line transform (1D),
+// 2 = row pass with the Omega gather (2D).  stage < 0 runs all of them.
+template <typename T>
+int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t st, int stage) {
+  const auto& H = p->host;
+  const int64_t M = H.M, N = H.N;
+  const Tables<T> t = tables_of<T>(p);
+  const OmegaDev om = omega_of(p);
+  if (H.m == 0) return WH2WAV_OK;
+  T* W = static_cast<T*>(ws);
+  auto run = [&](int s) { return stage < 0 || stage == s; };
+  if (H.dim == 1) {
+    T* TMP = W + M;
+    if (run(0)) {
+      HIP_OK(hipMemcpyAsync(W, x, sizeof(T) * M, hipMemcpyDeviceToDevice, st));
+      for (int k = H.j0; k < H.j; ++k) {
+        int rc = launch_synth<T>(p, W, TMP, 1, 0, 1, k, false, false, st);
+        if (rc) return rc;
+        HIP_OK(hipMemcpyAsync(W, TMP, sizeof(T) * (size_t(2) << k), hipMemcpyDeviceToDevice, st));
+      }
+    }
+    if (run(1)) {
+      size_t smem = line_smem(p, sizeof(T), true);
+      int rc = check_and_set_smem<T>((const void*)k_fwd_lines<T>, smem);
+      if (rc) return rc;
+      hipLaunchKernelGGL(k_fwd_lines<T>, dim3(1), dim3(kThreads), smem, st, W, 0, 1, y, 0, 0, H.j, 1, 1, t, om);
+      HIP_OK(hipGetLastError());
+    }
+    return WH2WAV_OK;
+  }
+  T* TMP = W + M * M;
+  T* Z = TMP + M * M;
+  if (run(0)) {
+    HIP_OK(hipMemcpyAsync(W, x, sizeof(T) * M * M, hipMemcpyDeviceToDevice, st));
+    for (int k = H.j0; k < H.j; ++k) {
+      const int64_t size = int64_t(2) << k;
+      int rc = launch_synth<T>(p, W, TMP, size, M, 1, k, false, false, st);  // rows
+      if (rc) return rc;
+      rc = launch_synth<T>(p, TMP, W, size, 1, M, k, true, false, st);      // columns
+      if (rc) return rc;
+    }
+  }
+  int rc = check_and_set_smem<T>((const void*)k_fwd_lines<T>, line_smem(p, sizeof(T), true));
+  if (rc) return rc;
+  if (run(1)) {  // column pass: G along the first index; Z[r, m2] with r natural
+    size_t smem0 = line_smem(p, sizeof(T), false);
+    hipLaunchKernelGGL(k_fwd_lines<T>, dim3(unsigned(M)), dim3(kThreads), smem0, st, W, 1, M, Z, 1, M, H.j, 0,
+                       0, t, om);
+    HIP_OK(hipGetLastError());
+  }
+  if (run(2)) {  // row pass: G along the second index, gather Omega
+    size_t smem1 = line_smem(p, sizeof(T), true);
+    hipLaunchKernelGGL(k_fwd_lines<T>, dim3(unsigned(N)), dim3(kThreads), smem1, st, Z, M, 1, y, 0, 0, H.j, 1,
+                       0, t, om);
+    HIP_OK(hipGetLastError());
+  }
+  return WH2WAV_OK;
+}
+
+// Adjoint stages: 0 = row pass with the Omega scatter (2D) / line transform
+// (1D), 1 = column pass (2D), 2 = forward DWT.  stage < 0 runs all of them.
+template <typename T>
+int adjoint_impl(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t st, int stage) {
+  const auto& H = p->host;
+  const int64_t M = H.M, N = H.N;
+  const Tables<T> t = tables_of<T>(p);
+  const OmegaDev om = omega_of(p);
+  T* W = static_cast<T*>(ws);
+  auto run = [&](int s) { return stage < 0 || stage == s; };
+  const int64_t xlen = H.dim == 1 ? M : M * M;
+  if (H.m == 0) {
+    if (run(2)) {
+      launch_fill<T>(x, xlen, st);
+      HIP_OK(hipGetLastError());
+    }
+    return WH2WAV_OK;
+  }
+  if (H.dim == 1) {
+    T* TMP = W + M;
+    if (run(0)) {
+      size_t smem = line_smem(p, sizeof(T), true);
+      int rc = check_and_set_smem<T>((const void*)k_adj_lines<T>, smem);
+      if (rc) return rc;
+      hipLaunchKernelGGL(k_adj_lines<T>, dim3(1), dim3(kThreads), smem, st, y, 0, 0, W, 0, 1, H.j, 1, 1, t, om);
+      HIP_OK(hipGetLastError());
+    }
+    if (run(2)) {
+      for (int k = H.j - 1; k >= H.j0; --k) {
+        int rc = launch_synth<T>(p, W, TMP, 1, 0, 1, k, false, true, st);
+        if (rc) return rc;
+        HIP_OK(hipMemcpyAsync(W, TMP, sizeof(T) * (size_t(2) << k), hipMemcpyDeviceToDevice, st));
+      }
+      HIP_OK(hipMemcpyAsync(x, W, sizeof(T) * M, hipMemcpyDeviceToDevice, st));
+    }
+    return WH2WAV_OK;
+  }
+  T* TMP = W + M * M;
+  T* Z = TMP + M * M;
+  int rc = check_and_set_smem<T>((const void*)k_adj_lines<T>, line_smem(p, sizeof(T), true));
+  if (rc) return rc;
+  if (run(0)) {
+    size_t smem1 = line_smem(p, sizeof(T), true);
+    hipLaunchKernelGGL(k_adj_lines<T>, dim3(unsigned(N)), dim3(kThreads), smem1, st, y, 0, 0, Z, M, 1, H.j, 1, 0,
+                       t, om);
+    HIP_OK(hipGetLastError());
+  }
+  if (run(1)) {
+    size_t smem0 = line_smem(p, sizeof(T), false);
+    hipLaunchKernelGGL(k_adj_lines<T>, dim3(unsigned(M)), dim3(kThreads), smem0, st, Z, 1, M, W, 1, M, H.j, 0,
+                       0, t, om);
+    HIP_OK(hipGetLastError());
+  }
+  if (run(2)) {
+    for (int k = H.j - 1; k >= H.j0; --k) {
+      const int64_t size = int64_t(2) << k;
+      rc = launch_synth<T>(p, W, TMP, size, 1, M, k, true, true, st);  // columns
+      if (rc) return rc;
+      rc = launch_synth<T>(p, TMP, W, size, M, 1, k, false, true, st);  // rows
+      if (rc) return rc;
+    }
+    HIP_OK(hipMemcpyAsync(x, W, sizeof(T) * M * M, hipMemcpyDeviceToDevice, st));
+  }
+  return WH2WAV_OK;
+}
+
+template <typename T>
+int upload_tables(wh2wav_plan_s* p) {
+  const auto& H = p->host;
+  std::vector<T> all;
+  auto put = [&](const std::vector<double>& v, size_t* off) {
+    *off = all.size();
+    for (double d : v) all.push_back(T(d));
+  };
+  put(H.h, &p->off_h);
+  put(H.g, &p->off_g);
+  put(H.tabT, &p->off_T);
+  put(H.tabBL, &p->off_BL);
+  put(H.tabBR, &p->off_BR);
+  put(H.synL, &p->off_SL);
+  put(H.synR, &p->off_SR);
+  HIP_OK(hipMalloc(&p->d_tables, sizeof(T) * all.size()));
+  HIP_OK(hipMemcpy(p->d_tables, all.data(), sizeof(T) * all.size(), hipMemcpyHostToDevice));
+  return WH2WAV_OK;
+}
+
+void release(wh2wav_plan_s* p) {
+  if (!p) return;
+  if (p->d_tables) (void)hipFree(p->d_tables);
+  if (p->d_mask) (void)hipFree(p->d_mask);
+  if (p->d_row_ptr) (void)hipFree(p->d_row_ptr);
+  delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wh2wav_last_error(void) { return g_last_error.c_str(); }
+
+int wh2wav_plan(const wh2wav_desc* desc, wh2wav_plan_t* out) {
+  g_last_error.clear();
+  if (!out) return fail(WH2WAV_EINVAL, "out is NULL");
+  *out = nullptr;
+  auto* p = new (std::nothrow) wh2wav_plan_s();
+  if (!p) return fail(WH2WAV_ENOMEM, "host allocation failed");
+  std::string err;
+  int rc = wh2wav::build_host_plan(desc, &p->host, &err);
+  if (rc != WH2WAV_OK) {
+    delete p;
+    return fail(rc, err);
+  }
+  const auto& H = p->host;
+  if (H.j < 1) {
+    delete p;
+    return fail(WH2WAV_EUNSUPPORTED, "j must be >= 1");
+  }
+  const size_t elem = H.dtype == WH2WAV_F64 ? 8 : 4;
+  if (2 * size_t(H.M) * elem + sizeof(int) * (size_t(H.words_per_row) + kThreads) > kMaxLds) {
+    delete p;
+    return fail(WH2WAV_EUNSUPPORTED, "M too large for the LDS line kernels");
+  }
+  rc = H.dtype == WH2WAV_F64 ? upload_tables<double>(p) : upload_tables<float>(p);
+  if (rc != WH2WAV_OK) {
+    std::string m = g_last_error;
+    release(p);
+    return fail(rc, m);
+  }
+  auto upload = [&](void** dst, const void* src, size_t bytes) -> int {
+    if (bytes == 0) return WH2WAV_OK;
+    HIP_OK(hipMalloc(dst, bytes));
+    HIP_OK(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+    return WH2WAV_OK;
+  };
+  rc = upload((void**)&p->d_row_ptr, H.row_ptr.data(), sizeof(int64_t) * H.row_ptr.size());
+  if (rc == WH2WAV_OK) rc = upload((void**)&p->d_mask, H.mask.data(), sizeof(uint32_t) * H.mask.size());
+  if (rc != WH2WAV_OK) {
+    std::string m = g_last_error;
+    release(p);
+    return fail(rc, m);
+  }
+  *out = p;
+  return WH2WAV_OK;
+}
+
+int wh2wav_workspace_size(wh2wav_plan_t p, size_t* bytes) {
+  if (!p || !bytes) return fail(WH2WAV_EINVAL, "NULL argument");
+  const auto& H = p->host;
+  const size_t elem = H.dtype == WH2WAV_F64 ? 8 : 4;
+  if (H.dim == 1)
+    *bytes = 2 * size_t(H.M) * elem;
+  else
+    *bytes = (2 * size_t(H.M) * size_t(H.M) + size_t(H.N) * size_t(H.M)) * elem;
+  return WH2WAV_OK;
+}
+
+static int check_call(wh2wav_plan_t p, const void* a, const void* b, void* ws) {
+  if (!p) return fail(WH2WAV_EINVAL, "plan is NULL");
+  const auto& H = p->host;
+  const size_t elem = H.dtype == WH2WAV_F64 ? 8 : 4;
+  const size_t in_out[2] = {size_t(H.dim == 1 ? H.M : H.M * H.M) * elem, size_t(H.m) * elem};
+  if (!ws) return fail(WH2WAV_EINVAL, "workspace is NULL");
+  if ((!a && in_out[0]) || (!b && in_out[1])) return fail(WH2WAV_EINVAL, "x or y is NULL");
+  auto overlap = [](const void* p1, size_t n1, const void* p2, size_t n2) {
+    if (!p1 || !p2 || !n1 || !n2) return false;
+    auto a1 = reinterpret_cast<uintptr_t>(p1), a2 = reinterpret_cast<uintptr_t>(p2);
+    return a1 < a2 + n2 && a2 < a1 + n1;
+  };
+  size_t wsb = 0;
+  wh2wav_workspace_size(p, &wsb);
+  if (overlap(a, in_out[0], b, in_out[1]) || overlap(a, in_out[0], ws, wsb) || overlap(b, in_out[1], ws, wsb))
+    return fail(WH2WAV_EINVAL, "x, y and workspace must not overlap");
+  return WH2WAV_OK;
+}
+
+static int forward_any(wh2wav_plan_t p, const void* x, void* y, void* ws, void* stream, int stage) {
+  g_last_error.clear();
+  int rc = check_call(p, x, y, ws);
+  if (rc) return rc;
+  auto st = static_cast<hipStream_t>(stream);
+  return p->host.dtype == WH2WAV_F64
+             ? forward_impl<double>(p, static_cast<const double*>(x), static_cast<double*>(y), ws, st, stage)
+             : forward_impl<float>(p, static_cast<const float*>(x), static_cast<float*>(y), ws, st, stage);
+}
+
+static int adjoint_any(wh2wav_plan_t p, const void* y, void* x, void* ws, void* stream, int stage) {
+  g_last_error.clear();
+  int rc = check_call(p, x, y, ws);
+  if (rc) return rc;
+  auto st = static_cast<hipStream_t>(stream);
+  return p->host.dtype == WH2WAV_F64
+             ? adjoint_impl<double>(p, static_cast<const double*>(y), static_cast<double*>(x), ws, st, stage)
+             : adjoint_impl<float>(p, static_cast<const float*>(y), static_cast<float*>(x), ws, st, stage);
+}
+
+int wh2wav_forward(wh2wav_plan_t p, const void* x, void* y, void* ws, void* stream) {
+  return forward_any(p, x, y, ws, stream, -1);
+}
+
+int wh2wav_adjoint(wh2wav_plan_t p, const void* y, void* x, void* ws, void* stream) {
+  return adjoint_any(p, y, x, ws, stream, -1);
+}
+
+int wh2wav_stage_count(wh2wav_plan_t p, int direction, int* count) {
+  if (!p || !count || (direction != 0 && direction != 1)) return fail(WH2WAV_EINVAL, "bad argument");
+  *count = p->host.dim == 1 ? (direction == 0 ? 2 : 3) : 3;
+  return WH2WAV_OK;
+}
+
+int wh2wav_forward_stage(wh2wav_plan_t p, int stage, const void* x, void* y, void* ws, void* stream) {
+  int n = 0;
+  int rc = wh2wav_stage_count(p, 0, &n);
+  if (rc) return rc;
+  if (stage < 0 || stage >= n) return fail(WH2WAV_EINVAL, "stage out of range");
+  return forward_any(p, x, y, ws, stream, stage);
+}
+
+int wh2wav_adjoint_stage(wh2wav_plan_t p, int stage, const void* y, void* x, void* ws, void* stream) {
+  int n = 0;
+  int rc = wh2wav_stage_count(p, 1, &n);
+  if (rc) return rc;
+  if (stage < 0 || stage >= n) return fail(WH2WAV_EINVAL, "stage out of range");
+  if (p->host.dim == 1 && stage == 1) return WH2WAV_OK;  // 1D has no column pass
+  return adjoint_any(p, y, x, ws, stream, stage);
+}
+
+int wh2wav_destroy(wh2wav_plan_t p) {
+  release(p);
+  return WH2WAV_OK;
+}
+
+int wh2wav_host_table(const wh2wav_desc* desc, int which, double* out, size_t capacity, size_t* count) {
+  g_last_error.clear();
+  if (!count) return fail(WH2WAV_EINVAL, "count is NULL");
+  wh2wav::HostPlan H;
+  std::string err;
+  int rc = wh2wav::build_host_plan(desc, &H, &err);
+  if (rc != WH2WAV_OK) return fail(rc, err);
+  std::vector<double> tmp;
+  const std::vector<double>* src = nullptr;
+  switch (which) {
+    case WH2WAV_TABLE_H: src = &H.h; break;
+    case WH2WAV_TABLE_G: src = &H.g; break;
+    case WH2WAV_TABLE_T: src = &H.tabT; break;
+    case WH2WAV_TABLE_BAND_L: src = &H.tabBL; break;
+    case WH2WAV_TABLE_BAND_R: src = &H.tabBR; break;
+    case WH2WAV_TABLE_SYN_L: src = &H.synL; break;
+    case WH2WAV_TABLE_SYN_R: src = &H.synR; break;
+    case WH2WAV_TABLE_ROWPTR:
+      for (int64_t v : H.row_ptr) tmp.push_back(double(v));
+      src = &tmp;
+      break;
+    default: return fail(WH2WAV_EINVAL, "unknown table");
+  }
+  *count = src->size();
+  if (out) std::memcpy(out, src->data(), sizeof(double) * std::min(capacity, src->size()));
+  return WH2WAV_OK;
+}
+
+}  // extern "C"

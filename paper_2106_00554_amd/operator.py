@@ -1,0 +1,91 @@
+"""torch-facing wrapper of the C ABI: device memory and streams only.
+
+`Wh2Wav` owns one plan (include/wh2wav.h) and its workspace; `forward` and
+`adjoint` hand device pointers and the current HIP stream to
+wh2wav_forward / wh2wav_adjoint.  All arithmetic happens in libwh2wav.so.
+"""
+import math
+
+import numpy as np
+import torch
+
+from . import _abi
+
+_DTYPES = {torch.float32: _abi.WH2WAV_F32, torch.float64: _abi.WH2WAV_F64}
+
+
+def default_j0(nu):
+    """Smallest coarse level allowed by Sec. 3.2: ceil(log2(2 nu)) (0 for Haar)."""
+    return 0 if nu == 1 else int(math.ceil(math.log2(2 * nu)))
+
+
+def make_desc(dim, j, q, nu, j0=None, dtype=torch.float64, omega=None):
+    """Build a wh2wav_desc; returns (desc, keepalive) -- keep the second alive until planned."""
+    j0 = default_j0(nu) if j0 is None else j0
+    N = 1 << (j + q)
+    total = N ** dim
+    if omega is None:
+        m, ptr, keep = total, None, None
+    else:
+        keep = np.ascontiguousarray(np.asarray(omega, dtype=np.int64))
+        m = int(keep.size)
+        ptr = keep.ctypes.data_as(_abi.ctypes.POINTER(_abi.ctypes.c_int64)) if m else \
+            _abi.ctypes.cast(_abi.ctypes.pointer(_abi.ctypes.c_int64(0)), _abi.ctypes.POINTER(_abi.ctypes.c_int64))
+    desc = _abi.wh2wav_desc(dim=dim, j=j, q=q, j0=j0, nu=nu, family=_abi.WH2WAV_DB,
+                            boundary=_abi.WH2WAV_BD, dtype=_DTYPES[dtype], m=m, omega=ptr)
+    return desc, keep
+
+
+class Wh2Wav:
+    """y = P_Omega A x and x = A^T P_Omega^T y on the current CUDA/HIP device."""
+
+    def __init__(self, dim, j, q, nu, j0=None, dtype=torch.float64, omega=None, device=None):
+        self.dim, self.j, self.q, self.nu = dim, j, q, nu
+        self.j0 = default_j0(nu) if j0 is None else j0
+        self.dtype = dtype
+        self.M, self.N = 1 << j, 1 << (j + q)
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        desc, keep = make_desc(dim, j, q, nu, self.j0, dtype, omega)
+        self.m = int(desc.m)
+        with torch.cuda.device(self.device):
+            self._plan = _abi.wh2wav_plan(desc)
+        del keep
+        nbytes = _abi.wh2wav_workspace_size(self._plan)
+        self.workspace = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=self.device)
+
+    @property
+    def x_shape(self):
+        return (self.M,) if self.dim == 1 else (self.M, self.M)
+
+    def _stream(self):
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    def _check(self, t, shape, name):
+        if t.device != self.device or t.dtype != self.dtype or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must be a contiguous {self.dtype} tensor of shape {tuple(shape)} "
+                             f"on {self.device}; got {tuple(t.shape)} {t.dtype} {t.device}")
+
+    def forward(self, x, out=None):
+        self._check(x, self.x_shape, "x")
+        y = torch.empty(self.m, dtype=self.dtype, device=self.device) if out is None else out
+        self._check(y, (self.m,), "y")
+        _abi.wh2wav_forward(self._plan, x.data_ptr(), y.data_ptr(), self.workspace.data_ptr(), self._stream())
+        return y
+
+    def adjoint(self, y, out=None):
+        self._check(y, (self.m,), "y")
+        x = torch.empty(self.x_shape, dtype=self.dtype, device=self.device) if out is None else out
+        self._check(x, self.x_shape, "x")
+        _abi.wh2wav_adjoint(self._plan, y.data_ptr(), x.data_ptr(), self.workspace.data_ptr(), self._stream())
+        return x
+
+    def close(self):
+        if getattr(self, "_plan", None) is not None:
+            _abi.wh2wav_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -60,3 +60,11 @@ def test_high_index_rows_reduce_to_low_ones():
         bit = (n >> J) & 1
         ref = base[low ^ ((1 << J) - 1) if bit else low]
         assert np.array_equal(H[n], ref)
+
+
+def test_bitwise_form_equals_definition():
+    rng = np.random.default_rng(4)
+    for J in (1, 3, 7, 11):
+        rows = rng.integers(0, 1 << (J + 3), 300)
+        cols = rng.integers(0, 1 << J, 200)
+        assert np.array_equal(walsh.walsh_matrix_bits(J, rows, cols), walsh.walsh_matrix(J, rows, cols))
