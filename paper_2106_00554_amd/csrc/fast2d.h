@@ -1,0 +1,49 @@
+// Wave-level line kernels for the 2D operator (internal interface between the
+// C-ABI file and the kernel file).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace wh2wav_fast {
+
+template <typename T>
+struct Tables {
+  const T* h;      // 2nu taps, index c + nu - 1
+  const T* g;      // 2nu taps
+  const T* tabT;   // (2nu-1) * Q, index (l + nu - 1) * Q + s
+  const T* bandL;  // (2nu-1) * nu * Q, index (p * nu + m) * Q + s
+  const T* bandR;  // (2nu-1) * nu * Q
+  const T* synL;   // (3nu-1) * 2nu
+  const T* synR;   // (3nu-1) * 2nu
+  int nu, q, Q;
+};
+
+struct Omega {
+  const uint32_t* mask;    // N rows of wpr words; NULL when every sample is taken
+  const int64_t* row_ptr;  // N + 1 offsets into y
+  int64_t wpr;             // words per row (N / 32)
+  int full;
+};
+
+// True when the wave kernels cover (element size, log2 M, nu).
+bool supported(int elem_bytes, int logm, int nu);
+
+// Forward row pass: rows r of Z (N x M, natural row order) -> y (gather on Omega).
+template <typename T>
+hipError_t rowpass_fwd(const T* Z, T* y, int logm, const Tables<T>& t, const Omega& om, hipStream_t st);
+// Adjoint row pass: y (scatter from Omega) -> rows r of Zt (N x M).
+template <typename T>
+hipError_t rowpass_adj(const T* y, T* Zt, int logm, const Tables<T>& t, const Omega& om, hipStream_t st);
+// Forward column pass: rows of xi^T (M x M) -> Z (N x M), Z[s M + k, c] natural order.
+template <typename T>
+hipError_t colpass_fwd(const T* xiT, T* Z, int logm, const Tables<T>& t, hipStream_t st);
+// Adjoint column pass: Zt (N x M) -> rows of xi'^T (M x M).
+template <typename T>
+hipError_t colpass_adj(const T* Zt, T* xiT, int logm, const Tables<T>& t, hipStream_t st);
+// out = in^T for an n x n row-major block (n a multiple of 32).
+template <typename T>
+hipError_t transpose(const T* in, T* out, int64_t n, hipStream_t st);
+
+}  // namespace wh2wav_fast

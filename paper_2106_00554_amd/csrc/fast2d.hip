@@ -1,0 +1,639 @@
+// Wave-level line kernels for the 2D operator on gfx950.
+//
+// A line of M = 64 R values lives in one wavefront, R consecutive values per
+// lane ("layout A": element p = lane * R + r).  Every stage of one line is
+// computed inside that wave:
+//   * table product (operators D_l of Sec. 4.1 and the boundary terms of
+//     Prop. 4.2): a (2nu-1)-tap correlation whose halo comes from the two
+//     neighbouring lanes, with the taps held as wave-uniform values;
+//   * natural-order Walsh-Hadamard transform: radix-R butterflies in
+//     registers, then six butterfly stages across lanes (DPP quad
+//     permutations for lane distance 1 and 2, ds_swizzle for 4..16,
+//     ds_bpermute for 32);
+//   * sequency order and the odd-phase mirror are index maps
+//     (k = bitrev(gray(b)) xor (s & 1)), applied in the gather / scatter.
+// Row passes run one workgroup per row of the N x M intermediate, one wave
+// per phase s; column passes read or write the intermediate in 16-column
+// (8 for the adjoint) tiles through an LDS staging area so that every global
+// access is a contiguous segment.
+#include "fast2d.h"
+
+namespace wh2wav_fast {
+namespace {
+
+__device__ __forceinline__ int lane_id() { return int(__lane_id()); }
+
+template <int D>
+__device__ __forceinline__ int xor_i32(int v) {
+  if constexpr (D == 1) {
+    return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  } else if constexpr (D == 2) {
+    return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  } else if constexpr (D < 32) {
+    return __builtin_amdgcn_ds_swizzle(v, 0x1F | (D << 10));     // bitmask mode, xor D
+  } else {
+    return __builtin_amdgcn_ds_bpermute((lane_id() ^ 32) << 2, v);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ float lane_xor(float v) {
+  return __int_as_float(xor_i32<D>(__float_as_int(v)));
+}
+template <int D>
+__device__ __forceinline__ double lane_xor(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = xor_i32<D>(int(b)), hi = xor_i32<D>(int(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+__device__ __forceinline__ float shfl_from(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+__device__ __forceinline__ double shfl_from(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, int(b));
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, int(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+__device__ __forceinline__ float read_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(int(b), l), hi = __builtin_amdgcn_readlane(int(b >> 32), l);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+__device__ __forceinline__ int wave_sum(int x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+  return x;
+}
+__device__ __forceinline__ int wave_exclusive_scan(int x, int lane) {
+  int inc = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(inc, d);
+    if (lane >= d) inc += t;
+  }
+  return inc - x;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t bitrev_bits(uint32_t x, int bits) { return __brev(x) >> (32 - bits); }
+__device__ __forceinline__ uint32_t gray_inverse(uint32_t x) {
+  x ^= x >> 1;
+  x ^= x >> 2;
+  x ^= x >> 4;
+  x ^= x >> 8;
+  x ^= x >> 16;
+  return x;
+}
+__device__ __forceinline__ uint32_t natural_of(uint32_t b, uint32_t s, int j) {
+  return bitrev_bits(b ^ (b >> 1), j) ^ (s & 1u);
+}
+__device__ __forceinline__ uint32_t sequency_of(uint32_t k, uint32_t s, int j) {
+  return gray_inverse(bitrev_bits(k ^ (s & 1u), j));
+}
+
+// ----------------------------------------------------------- vector I/O
+template <typename T, int R>
+__device__ __forceinline__ void load_line(const T* __restrict__ src, T (&v)[R]) {
+  if constexpr (sizeof(T) == 4) {
+    const float4* p = reinterpret_cast<const float4*>(src);
+#pragma unroll
+    for (int c = 0; c < R / 4; ++c) {
+      const float4 f = p[c];
+      v[4 * c] = f.x, v[4 * c + 1] = f.y, v[4 * c + 2] = f.z, v[4 * c + 3] = f.w;
+    }
+  } else {
+    const double2* p = reinterpret_cast<const double2*>(src);
+#pragma unroll
+    for (int c = 0; c < R / 2; ++c) {
+      const double2 f = p[c];
+      v[2 * c] = f.x, v[2 * c + 1] = f.y;
+    }
+  }
+}
+template <typename T, int R>
+__device__ __forceinline__ void store_line(T* __restrict__ dst, const T (&v)[R]) {
+  if constexpr (sizeof(T) == 4) {
+    float4* p = reinterpret_cast<float4*>(dst);
+#pragma unroll
+    for (int c = 0; c < R / 4; ++c) p[c] = make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
+  } else {
+    double2* p = reinterpret_cast<double2*>(dst);
+#pragma unroll
+    for (int c = 0; c < R / 2; ++c) p[c] = make_double2(v[2 * c], v[2 * c + 1]);
+  }
+}
+
+// ------------------------------------------------------------ transforms
+template <typename T, int R>
+__device__ __forceinline__ void fwht_regs(T (&v)[R]) {
+#pragma unroll
+  for (int h = 1; h < R; h <<= 1) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      if ((i & h) == 0) {
+        const T a = v[i], b = v[i + h];
+        v[i] = a + b;
+        v[i + h] = a - b;
+      }
+    }
+  }
+}
+
+template <int D, typename T, int R>
+__device__ __forceinline__ void lane_stage(T (&v)[R], int lane) {
+  const T sg = (lane & D) ? T(-1) : T(1);
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const T p = lane_xor<D>(v[i]);
+    v[i] = fma(sg, v[i], p);
+  }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void fwht_wave(T (&v)[R], int lane) {
+  fwht_regs<T, R>(v);
+  lane_stage<1>(v, lane);
+  lane_stage<2>(v, lane);
+  lane_stage<4>(v, lane);
+  lane_stage<8>(v, lane);
+  lane_stage<16>(v, lane);
+  lane_stage<32>(v, lane);
+}
+
+// Halo: window w[0 .. R+2H) with w[H + r] = x[r]; neighbours' values from the
+// adjacent lanes, zero beyond the ends of the line.
+template <typename T, int R, int H>
+__device__ __forceinline__ void make_window(const T (&x)[R], T (&w)[R + 2 * H], int lane) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) w[H + r] = x[r];
+#pragma unroll
+  for (int e = 0; e < H; ++e) {
+    const T a = shfl_from(x[R - 1 - e], (lane - 1) & 63);
+    const T b = shfl_from(x[e], (lane + 1) & 63);
+    w[H - 1 - e] = lane == 0 ? T(0) : a;
+    w[H + R + e] = lane == 63 ? T(0) : b;
+  }
+}
+
+// v[r] = sum_l x[p - l] T_l  (p = lane R + r, l in [-nu+1, nu-1], tap[l + nu - 1] = T_l)
+template <typename T, int R, int NU>
+__device__ __forceinline__ void table_product(const T (&x)[R], T (&v)[R], const T (&tap)[2 * NU - 1], int lane) {
+  constexpr int H = NU - 1;
+  T w[R + 2 * H];
+  make_window<T, R, H>(x, w, lane);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    T acc = 0;
+#pragma unroll
+    for (int li = 0; li < 2 * H + 1; ++li) acc = fma(w[2 * H + r - li], tap[li], acc);
+    v[r] = acc;
+  }
+}
+
+// acc[r] += sum_l T_l x[p + l]  (transpose of table_product on interior positions)
+template <typename T, int R, int NU>
+__device__ __forceinline__ void table_product_t(const T (&x)[R], T (&acc)[R], const T (&tap)[2 * NU - 1],
+                                                int lane) {
+  constexpr int H = NU - 1;
+  T w[R + 2 * H];
+  make_window<T, R, H>(x, w, lane);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    T a = acc[r];
+#pragma unroll
+    for (int li = 0; li < 2 * H + 1; ++li) a = fma(w[r + li], tap[li], a);
+    acc[r] = a;
+  }
+}
+
+// Forward line: xi (layout A, all M values, boundary values included) -> the
+// natural-order transform of phase s, in place in v.
+template <typename T, int R, int NU>
+__device__ __forceinline__ void line_forward(const T (&xi)[R], T (&v)[R], int s, const Tables<T>& t, int lane) {
+  constexpr int B = 2 * NU - 1;
+  const int Q = t.Q;
+  T x[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) x[r] = xi[r];
+  T eL[NU], eR[NU];
+#pragma unroll
+  for (int m = 0; m < NU; ++m) {
+    eL[m] = read_lane(xi[m], 0);
+    eR[m] = read_lane(xi[R - 1 - m], 63);
+    if (lane == 0) x[m] = T(0);
+    if (lane == 63) x[R - 1 - m] = T(0);
+  }
+  T tap[2 * NU - 1];
+#pragma unroll
+  for (int li = 0; li < 2 * NU - 1; ++li) tap[li] = t.tabT[li * Q + s];
+  table_product<T, R, NU>(x, v, tap, lane);
+  // boundary bands (Prop. 4.2): positions p < B and p >= M - B
+  T bv = T(0);
+  if (lane < B) {
+#pragma unroll
+    for (int m = 0; m < NU; ++m) bv = fma(eL[m], t.bandL[(lane * NU + m) * Q + s], bv);
+  } else if (lane < 2 * B) {
+#pragma unroll
+    for (int m = 0; m < NU; ++m) bv = fma(eR[m], t.bandR[((lane - B) * NU + m) * Q + s], bv);
+  }
+#pragma unroll
+  for (int e = 0; e < B; ++e) {
+    const T a = read_lane(bv, e), b = read_lane(bv, B + e);
+    if (lane == 0) v[e] += a;
+    if (lane == 63) v[R - B + e] += b;
+  }
+  fwht_wave<T, R>(v, lane);
+}
+
+// Adjoint line for one phase: v holds the natural-order values of phase s
+// (layout A); adds the transposed table product to acc (interior positions)
+// and the boundary-column products to eacc (lanes 0..2nu-1: left m = lane,
+// right position M-1-(lane-nu)).
+template <typename T, int R, int NU>
+__device__ __forceinline__ void line_adjoint(T (&v)[R], T (&acc)[R], T& eacc, int s, const Tables<T>& t, int lane) {
+  constexpr int B = 2 * NU - 1;
+  const int Q = t.Q;
+  fwht_wave<T, R>(v, lane);
+  T tap[2 * NU - 1];
+#pragma unroll
+  for (int li = 0; li < 2 * NU - 1; ++li) tap[li] = t.tabT[li * Q + s];
+  table_product_t<T, R, NU>(v, acc, tap, lane);
+  T rl[B], rr[B];
+#pragma unroll
+  for (int e = 0; e < B; ++e) {
+    rl[e] = read_lane(v[e], 0);
+    rr[e] = read_lane(v[R - B + e], 63);
+  }
+  T el = T(0);
+  if (lane < NU) {
+#pragma unroll
+    for (int p = 0; p < B; ++p) el = fma(t.bandL[(p * NU + lane) * Q + s], rl[p], el);
+  } else if (lane < 2 * NU) {
+#pragma unroll
+    for (int p = 0; p < B; ++p) el = fma(t.bandR[(p * NU + (lane - NU)) * Q + s], rr[p], el);
+  }
+  eacc += el;
+}
+
+// Boundary positions of acc take their values from eacc.
+template <typename T, int R, int NU>
+__device__ __forceinline__ void place_edges(T (&acc)[R], T eacc, int lane) {
+#pragma unroll
+  for (int m = 0; m < NU; ++m) {
+    const T a = read_lane(eacc, m), b = read_lane(eacc, NU + m);
+    if (lane == 0) acc[m] = a;
+    if (lane == 63) acc[R - 1 - m] = b;
+  }
+}
+
+template <int R>
+__device__ __forceinline__ int buf_addr(int k, int log_r) {
+  return k + 4 * (k >> log_r);
+}
+
+// ------------------------------------------------------------- row passes
+template <typename T, int LOGM, int NU>
+__global__ void __launch_bounds__(256) k_rowpass_fwd(const T* __restrict__ Z, T* __restrict__ y, Tables<T> t,
+                                                     Omega om) {
+  constexpr int M = 1 << LOGM, LOG_R = LOGM - 6, R = 1 << LOG_R;
+  constexpr int BUF = M + 4 * (M >> LOG_R);
+  extern __shared__ unsigned char smem_raw[];
+  const int lane = lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int nw = int(blockDim.x) >> 6;
+  const int Q = t.Q;
+  T* buf = reinterpret_cast<T*>(smem_raw) + wave * BUF;
+  const int64_t r = blockIdx.x;
+  T xi[R];
+  load_line<T, R>(Z + r * M + lane * R, xi);
+  const uint32_t s1 = uint32_t(r >> LOGM), k1 = uint32_t(r & (M - 1));
+  const int64_t n1 = int64_t(s1) * M + sequency_of(k1, s1, LOGM);
+  const int64_t N = int64_t(M) * Q;
+  for (int s = wave; s < Q; s += nw) {
+    T v[R];
+    line_forward<T, R, NU>(xi, v, s, t, lane);
+    store_line<T, R>(buf + lane * (R + 4), v);
+    wave_sync();
+    if (om.full) {
+      T* yrow = y + n1 * N + int64_t(s) * M;
+      for (int b = lane; b < M; b += 64) {
+        const uint32_t k = natural_of(uint32_t(b), uint32_t(s), LOGM);
+        yrow[b] = buf[buf_addr<R>(int(k), LOG_R)];
+      }
+    } else {
+      constexpr int WPP = M / 32, WPL = (WPP + 63) / 64;
+      const uint32_t* rowmask = om.mask + n1 * om.wpr;
+      int before = 0;
+      for (int w = lane; w < s * WPP; w += 64) before += __popc(rowmask[w]);
+      before = wave_sum(before);
+      uint32_t wv[WPL];
+      int cnt = 0;
+#pragma unroll
+      for (int i = 0; i < WPL; ++i) {
+        const int w = lane * WPL + i;
+        wv[i] = w < WPP ? rowmask[s * WPP + w] : 0u;
+        cnt += __popc(wv[i]);
+      }
+      int64_t o = om.row_ptr[n1] + before + wave_exclusive_scan(cnt, lane);
+#pragma unroll
+      for (int i = 0; i < WPL; ++i) {
+        uint32_t bits = wv[i];
+        const uint32_t wb = uint32_t(lane * WPL + i) * 32u;
+        while (bits) {
+          const int bit = __ffs(bits) - 1;
+          bits &= bits - 1;
+          const uint32_t k = natural_of(wb + uint32_t(bit), uint32_t(s), LOGM);
+          y[o++] = buf[buf_addr<R>(int(k), LOG_R)];
+        }
+      }
+    }
+    wave_sync();
+  }
+}
+
+template <typename T, int LOGM, int NU>
+__global__ void __launch_bounds__(256) k_rowpass_adj(const T* __restrict__ y, T* __restrict__ Zt, Tables<T> t,
+                                                     Omega om) {
+  constexpr int M = 1 << LOGM, LOG_R = LOGM - 6, R = 1 << LOG_R;
+  constexpr int BUF = M + 4 * (M >> LOG_R);
+  extern __shared__ unsigned char smem_raw[];
+  const int lane = lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int nw = int(blockDim.x) >> 6;
+  const int Q = t.Q;
+  T* bufs = reinterpret_cast<T*>(smem_raw);
+  T* buf = bufs + wave * BUF;
+  const int64_t r = blockIdx.x;
+  const uint32_t s1 = uint32_t(r >> LOGM), k1 = uint32_t(r & (M - 1));
+  const int64_t n1 = int64_t(s1) * M + sequency_of(k1, s1, LOGM);
+  const int64_t N = int64_t(M) * Q;
+  T acc[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) acc[i] = T(0);
+  T eacc = T(0);
+  for (int s = wave; s < Q; s += nw) {
+    T v[R];
+    if (om.full) {
+      const T* yrow = y + n1 * N + int64_t(s) * M;
+      for (int b = lane; b < M; b += 64) {
+        const uint32_t k = natural_of(uint32_t(b), uint32_t(s), LOGM);
+        buf[buf_addr<R>(int(k), LOG_R)] = yrow[b];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < R; ++i) v[i] = T(0);
+      store_line<T, R>(buf + lane * (R + 4), v);
+      wave_sync();
+      constexpr int WPP = M / 32, WPL = (WPP + 63) / 64;
+      const uint32_t* rowmask = om.mask + n1 * om.wpr;
+      int before = 0;
+      for (int w = lane; w < s * WPP; w += 64) before += __popc(rowmask[w]);
+      before = wave_sum(before);
+      uint32_t wv[WPL];
+      int cnt = 0;
+#pragma unroll
+      for (int i = 0; i < WPL; ++i) {
+        const int w = lane * WPL + i;
+        wv[i] = w < WPP ? rowmask[s * WPP + w] : 0u;
+        cnt += __popc(wv[i]);
+      }
+      int64_t o = om.row_ptr[n1] + before + wave_exclusive_scan(cnt, lane);
+#pragma unroll
+      for (int i = 0; i < WPL; ++i) {
+        uint32_t bits = wv[i];
+        const uint32_t wb = uint32_t(lane * WPL + i) * 32u;
+        while (bits) {
+          const int bit = __ffs(bits) - 1;
+          bits &= bits - 1;
+          const uint32_t k = natural_of(wb + uint32_t(bit), uint32_t(s), LOGM);
+          buf[buf_addr<R>(int(k), LOG_R)] = y[o++];
+        }
+      }
+    }
+    wave_sync();
+    load_line<T, R>(buf + lane * (R + 4), v);
+    wave_sync();
+    line_adjoint<T, R, NU>(v, acc, eacc, s, t, lane);
+  }
+  place_edges<T, R, NU>(acc, eacc, lane);
+  // cross-wave sum (waves that had no phase contribute zeros)
+  store_line<T, R>(buf + lane * (R + 4), acc);
+  __syncthreads();
+  for (int p = int(threadIdx.x); p < M; p += int(blockDim.x)) {
+    T sum = T(0);
+    for (int w = 0; w < nw; ++w) sum += bufs[w * BUF + buf_addr<R>(p, LOG_R)];
+    Zt[r * M + p] = sum;
+  }
+}
+
+// ---------------------------------------------------------- column passes
+// Forward: block = 16 waves = 16 rows of xi^T (columns c0..c0+15 of xi), one
+// phase s.  Blocks that share a tile are placed on the same XCD (the
+// dispatcher deals consecutive block ids round-robin over the 8 XCDs).
+template <typename T, int LOGM, int NU>
+__global__ void __launch_bounds__(1024) k_colpass_fwd(const T* __restrict__ xiT, T* __restrict__ Z, Tables<T> t) {
+  constexpr int M = 1 << LOGM, LOG_R = LOGM - 6, R = 1 << LOG_R;
+  constexpr int TILE = 16, SP = 64 * 4 + 4;  // staging stride per wave (padded)
+  extern __shared__ unsigned char smem_raw[];
+  T* stage = reinterpret_cast<T*>(smem_raw);
+  const int lane = lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int Q = t.Q;
+  const int nblk = int(gridDim.x), bid = int(blockIdx.x);
+  const int per = nblk / 8;
+  const int idx = (nblk % 8 == 0) ? (bid % 8) * per + bid / 8 : bid;
+  const int tile = idx / Q, s = idx % Q;
+  const int c = tile * TILE + wave;
+  T xi[R], v[R];
+  load_line<T, R>(xiT + int64_t(c) * M + lane * R, xi);
+  line_forward<T, R, NU>(xi, v, s, t, lane);
+  const int tid = int(threadIdx.x);
+  const int e = tid >> 2, qg = tid & 3;            // 256 output rows x 4 column groups
+  const int le = e >> 2, te = e & 3;
+#pragma unroll
+  for (int i = 0; i < R / 4; ++i) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) stage[wave * SP + lane * 4 + u] = v[4 * i + u];
+    __syncthreads();
+    const int k = le * R + 4 * i + te;
+    T o[4];
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) o[cc] = stage[(4 * qg + cc) * SP + le * 4 + te];
+    T* dst = Z + (int64_t(s) * M + k) * M + tile * TILE + 4 * qg;
+    if constexpr (sizeof(T) == 4) {
+      *reinterpret_cast<float4*>(dst) = make_float4(o[0], o[1], o[2], o[3]);
+    } else {
+      reinterpret_cast<double2*>(dst)[0] = make_double2(o[0], o[1]);
+      reinterpret_cast<double2*>(dst)[1] = make_double2(o[2], o[3]);
+    }
+    __syncthreads();
+  }
+}
+
+// Adjoint: block = 8 waves = columns c0..c0+7 of the intermediate, all phases.
+template <typename T, int LOGM, int NU>
+__global__ void __launch_bounds__(512) k_colpass_adj(const T* __restrict__ Zt, T* __restrict__ xiT, Tables<T> t) {
+  constexpr int M = 1 << LOGM, LOG_R = LOGM - 6, R = 1 << LOG_R;
+  constexpr int TILE = 8, SP = 64 * 4 + 4;
+  extern __shared__ unsigned char smem_raw[];
+  T* stage = reinterpret_cast<T*>(smem_raw);
+  const int lane = lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int Q = t.Q;
+  const int nblk = int(gridDim.x), bid = int(blockIdx.x);
+  const int per = nblk / 8;
+  const int tile = (nblk % 8 == 0) ? (bid % 8) * per + bid / 8 : bid;
+  const int c = tile * TILE + wave;
+  const int tid = int(threadIdx.x);
+  const int e = tid >> 1, half = tid & 1;          // 256 input rows x 2 halves of 4 columns
+  const int le = e >> 2, te = e & 3;
+  T acc[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) acc[i] = T(0);
+  T eacc = T(0);
+  for (int s = 0; s < Q; ++s) {
+    T v[R];
+#pragma unroll
+    for (int i = 0; i < R / 4; ++i) {
+      const int k = le * R + 4 * i + te;
+      const T* src = Zt + (int64_t(s) * M + k) * M + tile * TILE + 4 * half;
+      T o[4];
+      if constexpr (sizeof(T) == 4) {
+        const float4 f = *reinterpret_cast<const float4*>(src);
+        o[0] = f.x, o[1] = f.y, o[2] = f.z, o[3] = f.w;
+      } else {
+        const double2 f0 = reinterpret_cast<const double2*>(src)[0], f1 = reinterpret_cast<const double2*>(src)[1];
+        o[0] = f0.x, o[1] = f0.y, o[2] = f1.x, o[3] = f1.y;
+      }
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) stage[(4 * half + cc) * SP + le * 4 + te] = o[cc];
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[4 * i + u] = stage[wave * SP + lane * 4 + u];
+      __syncthreads();
+    }
+    line_adjoint<T, R, NU>(v, acc, eacc, s, t, lane);
+  }
+  place_edges<T, R, NU>(acc, eacc, lane);
+  store_line<T, R>(xiT + int64_t(c) * M + lane * R, acc);
+}
+
+// ------------------------------------------------------------ transpose
+template <typename T>
+__global__ void __launch_bounds__(256) k_transpose(const T* __restrict__ in, T* __restrict__ out, int64_t n) {
+  __shared__ T tile[32][33];
+  const int64_t bx = int64_t(blockIdx.x) * 32, by = int64_t(blockIdx.y) * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int j = ty; j < 32; j += 8) tile[j][tx] = in[(by + j) * n + bx + tx];
+  __syncthreads();
+  for (int j = ty; j < 32; j += 8) out[(bx + j) * n + by + tx] = tile[tx][j];
+}
+
+// ------------------------------------------------------------- dispatch
+template <typename T, int LOGM, int NU>
+hipError_t launch_rowpass_fwd(const T* Z, T* y, const Tables<T>& t, const Omega& om, hipStream_t st) {
+  constexpr int M = 1 << LOGM, R = M / 64;
+  const int nw = t.Q < 4 ? t.Q : 4;
+  const size_t smem = size_t(nw) * (M + 4 * (M / R)) * sizeof(T);
+  const int64_t rows = int64_t(M) * t.Q;
+  hipLaunchKernelGGL((k_rowpass_fwd<T, LOGM, NU>), dim3(unsigned(rows)), dim3(64 * nw), smem, st, Z, y, t, om);
+  return hipGetLastError();
+}
+template <typename T, int LOGM, int NU>
+hipError_t launch_rowpass_adj(const T* y, T* Zt, const Tables<T>& t, const Omega& om, hipStream_t st) {
+  constexpr int M = 1 << LOGM, R = M / 64;
+  const int nw = t.Q < 4 ? t.Q : 4;
+  const size_t smem = size_t(nw) * (M + 4 * (M / R)) * sizeof(T);
+  const int64_t rows = int64_t(M) * t.Q;
+  hipLaunchKernelGGL((k_rowpass_adj<T, LOGM, NU>), dim3(unsigned(rows)), dim3(64 * nw), smem, st, y, Zt, t, om);
+  return hipGetLastError();
+}
+template <typename T, int LOGM, int NU>
+hipError_t launch_colpass_fwd(const T* xiT, T* Z, const Tables<T>& t, hipStream_t st) {
+  constexpr int M = 1 << LOGM;
+  const size_t smem = size_t(16) * (64 * 4 + 4) * sizeof(T);
+  hipLaunchKernelGGL((k_colpass_fwd<T, LOGM, NU>), dim3(unsigned((M / 16) * t.Q)), dim3(1024), smem, st, xiT, Z, t);
+  return hipGetLastError();
+}
+template <typename T, int LOGM, int NU>
+hipError_t launch_colpass_adj(const T* Zt, T* xiT, const Tables<T>& t, hipStream_t st) {
+  constexpr int M = 1 << LOGM;
+  const size_t smem = size_t(8) * (64 * 4 + 4) * sizeof(T);
+  hipLaunchKernelGGL((k_colpass_adj<T, LOGM, NU>), dim3(unsigned(M / 8)), dim3(512), smem, st, Zt, xiT, t);
+  return hipGetLastError();
+}
+
+// Supported (log2 M, nu): R = M / 64 must hold the boundary band (R >= 2 nu - 1).
+#define WH2WAV_FAST_CASES(X) \
+  X(9, 2) X(9, 3) X(9, 4)    \
+  X(10, 2) X(10, 3) X(10, 4) X(10, 6) X(10, 8) \
+  X(11, 2) X(11, 3) X(11, 4) X(11, 6) X(11, 8)
+
+}  // namespace
+
+bool supported(int elem_bytes, int logm, int nu) {
+  (void)elem_bytes;
+#define X(L, V) if (logm == L && nu == V) return true;
+  WH2WAV_FAST_CASES(X)
+#undef X
+  return false;
+}
+
+template <typename T>
+hipError_t rowpass_fwd(const T* Z, T* y, int logm, const Tables<T>& t, const Omega& om, hipStream_t st) {
+#define X(L, V) if (logm == L && t.nu == V) return launch_rowpass_fwd<T, L, V>(Z, y, t, om, st);
+  WH2WAV_FAST_CASES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+template <typename T>
+hipError_t rowpass_adj(const T* y, T* Zt, int logm, const Tables<T>& t, const Omega& om, hipStream_t st) {
+#define X(L, V) if (logm == L && t.nu == V) return launch_rowpass_adj<T, L, V>(y, Zt, t, om, st);
+  WH2WAV_FAST_CASES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+template <typename T>
+hipError_t colpass_fwd(const T* xiT, T* Z, int logm, const Tables<T>& t, hipStream_t st) {
+#define X(L, V) if (logm == L && t.nu == V) return launch_colpass_fwd<T, L, V>(xiT, Z, t, st);
+  WH2WAV_FAST_CASES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+template <typename T>
+hipError_t colpass_adj(const T* Zt, T* xiT, int logm, const Tables<T>& t, hipStream_t st) {
+#define X(L, V) if (logm == L && t.nu == V) return launch_colpass_adj<T, L, V>(Zt, xiT, t, st);
+  WH2WAV_FAST_CASES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+template <typename T>
+hipError_t transpose(const T* in, T* out, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_transpose<T>, dim3(unsigned(n / 32), unsigned(n / 32)), dim3(256), 0, st, in, out, n);
+  return hipGetLastError();
+}
+
+template hipError_t rowpass_fwd<float>(const float*, float*, int, const Tables<float>&, const Omega&, hipStream_t);
+template hipError_t rowpass_fwd<double>(const double*, double*, int, const Tables<double>&, const Omega&, hipStream_t);
+template hipError_t rowpass_adj<float>(const float*, float*, int, const Tables<float>&, const Omega&, hipStream_t);
+template hipError_t rowpass_adj<double>(const double*, double*, int, const Tables<double>&, const Omega&, hipStream_t);
+template hipError_t colpass_fwd<float>(const float*, float*, int, const Tables<float>&, hipStream_t);
+template hipError_t colpass_fwd<double>(const double*, double*, int, const Tables<double>&, hipStream_t);
+template hipError_t colpass_adj<float>(const float*, float*, int, const Tables<float>&, hipStream_t);
+template hipError_t colpass_adj<double>(const double*, double*, int, const Tables<double>&, hipStream_t);
+template hipError_t transpose<float>(const float*, float*, int64_t, hipStream_t);
+template hipError_t transpose<double>(const double*, double*, int64_t, hipStream_t);
+
+}  // namespace wh2wav_fast

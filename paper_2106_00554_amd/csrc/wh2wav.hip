@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "../../include/wh2wav.h"
+#include "fast2d.h"
 #include "planner.h"
 
 namespace {
@@ -420,6 +421,29 @@ Tables<T> tables_of(const wh2wav_plan_s* p) {
   return t;
 }
 
+template <typename T>
+wh2wav_fast::Tables<T> fast_tables_of(const wh2wav_plan_s* p) {
+  const Tables<T> a = tables_of<T>(p);
+  wh2wav_fast::Tables<T> f;
+  f.h = a.h, f.g = a.g, f.tabT = a.tabT, f.bandL = a.bandL, f.bandR = a.bandR, f.synL = a.synL, f.synR = a.synR;
+  f.nu = a.nu, f.q = a.q, f.Q = a.Q;
+  return f;
+}
+
+wh2wav_fast::Omega fast_omega_of(const wh2wav_plan_s* p) {
+  wh2wav_fast::Omega o;
+  o.mask = p->d_mask;
+  o.row_ptr = p->d_row_ptr;
+  o.wpr = p->host.words_per_row;
+  o.full = p->host.full_omega ? 1 : 0;
+  return o;
+}
+
+bool use_fast(const wh2wav_plan_s* p) {
+  const auto& H = p->host;
+  return H.dim == 2 && wh2wav_fast::supported(H.dtype == WH2WAV_F64 ? 8 : 4, H.j, H.nu);
+}
+
 OmegaDev omega_of(const wh2wav_plan_s* p) {
   OmegaDev o;
   o.mask = p->d_mask;
@@ -492,6 +516,7 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
   }
   T* TMP = W + M * M;
   T* Z = TMP + M * M;
+  const bool fast = use_fast(p);
   if (run(0)) {
     HIP_OK(hipMemcpyAsync(W, x, sizeof(T) * M * M, hipMemcpyDeviceToDevice, st));
     for (int k = H.j0; k < H.j; ++k) {
@@ -501,6 +526,12 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
       rc = launch_synth<T>(p, TMP, W, size, 1, M, k, true, false, st);      // columns
       if (rc) return rc;
     }
+    if (fast) HIP_OK(wh2wav_fast::transpose<T>(W, TMP, M, st));  // xi^T for the column pass
+  }
+  if (fast) {
+    if (run(1)) HIP_OK(wh2wav_fast::colpass_fwd<T>(TMP, Z, H.j, fast_tables_of<T>(p), st));
+    if (run(2)) HIP_OK(wh2wav_fast::rowpass_fwd<T>(Z, y, H.j, fast_tables_of<T>(p), fast_omega_of(p), st));
+    return WH2WAV_OK;
   }
   int rc = check_and_set_smem<T>((const void*)k_fwd_lines<T>, line_smem(p, sizeof(T), true));
   if (rc) return rc;
@@ -558,6 +589,22 @@ int adjoint_impl(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t
   }
   T* TMP = W + M * M;
   T* Z = TMP + M * M;
+  if (use_fast(p)) {
+    if (run(0)) HIP_OK(wh2wav_fast::rowpass_adj<T>(y, Z, H.j, fast_tables_of<T>(p), fast_omega_of(p), st));
+    if (run(1)) HIP_OK(wh2wav_fast::colpass_adj<T>(Z, TMP, H.j, fast_tables_of<T>(p), st));
+    if (run(2)) {
+      HIP_OK(wh2wav_fast::transpose<T>(TMP, W, M, st));
+      for (int k = H.j - 1; k >= H.j0; --k) {
+        const int64_t size = int64_t(2) << k;
+        int rc = launch_synth<T>(p, W, TMP, size, 1, M, k, true, true, st);  // columns
+        if (rc) return rc;
+        rc = launch_synth<T>(p, TMP, W, size, M, 1, k, false, true, st);  // rows
+        if (rc) return rc;
+      }
+      HIP_OK(hipMemcpyAsync(x, W, sizeof(T) * M * M, hipMemcpyDeviceToDevice, st));
+    }
+    return WH2WAV_OK;
+  }
   int rc = check_and_set_smem<T>((const void*)k_adj_lines<T>, line_smem(p, sizeof(T), true));
   if (rc) return rc;
   if (run(0)) {

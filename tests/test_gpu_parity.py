@@ -212,3 +212,27 @@ def test_call_errors_are_reported():
         _abi.wh2wav_forward(opr._plan, x.data_ptr(), None, opr.workspace.data_ptr(), None)
     with pytest.raises(ValueError):
         opr.forward(torch.zeros(16, dtype=torch.float32, device="cuda"))
+
+
+# Sizes and orders served by the wave-level kernels (M = 2^9 .. 2^11).
+CASES_2D_WAVE = [
+    (2, 9, 1, 2, 0.25), (3, 9, 2, 3, None), (4, 9, 3, 3, 0.125),
+    (4, 10, 1, 3, None), (6, 10, 1, 4, 0.3), (8, 10, 1, 4, 0.2), (2, 10, 2, 2, 0.15),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("nu,j,q,j0,dens", CASES_2D_WAVE)
+def test_parity_2d_wave_kernels(nu, j, q, j0, dens, dtype):
+    cfg = op.Config(nu, j, q, j0)
+    seed = 5000 + 100 * nu + 10 * j + q
+    X = inputs.coefficients_2d(j, j0, seed)
+    omega = None if dens is None else inputs.multilevel_omega_2d(cfg.N, dens, seed + 1)
+    m = cfg.N ** 2 if omega is None else omega.size
+    yv = inputs.sample_vector(m, seed + 2)
+    blocks = op.Blocks2D(cfg)
+    y_ref = op.forward_2d_full(blocks, X, omega).reshape(-1)
+    x_ref = op.adjoint_2d_full(blocks, yv, omega)
+    y, xa = gpu_pair(2, nu, j, q, j0, dtype, X, omega, yv)
+    assert rel(y, y_ref) < TOL[dtype], rel(y, y_ref)
+    assert rel(xa, x_ref) < TOL[dtype], rel(xa, x_ref)
