@@ -1,0 +1,666 @@
+// Two-dimensional inverse DWT (C_{psi,j} quadtree -> B_{phi,j} (x) B_{phi,j}) and its
+// transpose, for the square (isotropic) 2D basis.
+//
+// One level k -> k+1 maps the 2^{k+1} x 2^{k+1} block [[LL, LH], [HL, HH]] to
+// S X S^T, S the one-level synthesis matrix (interior columns: the filters h, g
+// at stride 2; boundary columns: the dense blocks built by the planner).  The
+// transpose (the forward DWT) is S^T X S.
+//   * Coarse levels (block <= 128 x 128 in FP32, 64 x 64 in FP64) run in one
+//     workgroup with the block in LDS.
+//   * Each finer level is one launch over 2D output tiles: a tile loads the
+//     input window it depends on (both halves, both directions), filters the
+//     rows, then the columns, in LDS.
+//   * The last synthesis level writes xi^T (the layout the column pass reads);
+//     the first analysis level reads xi'^T (the layout the adjoint column pass
+//     writes) and stores the detail bands straight into x.
+#include "fast2d.h"
+
+namespace wh2wav_fast {
+namespace {
+
+// Synthesis of output n of one line: a(m) = A(m), d(m) = D(m), m < half.
+template <typename T, int NU, class FA, class FD>
+__device__ __forceinline__ T synth_at(int n, int half, const T* __restrict__ h, const T* __restrict__ g,
+                                      const T* __restrict__ synL, const T* __restrict__ synR, FA A, FD D) {
+  constexpr int ROWS = 3 * NU - 1;
+  const int size = 2 * half;
+  const int right_first = half - NU > NU ? half - NU : NU;
+  T acc = T(0);
+  int mlo = n - NU + 1 > 0 ? (n - NU + 1) >> 1 : 0;
+  if (mlo < NU) mlo = NU;
+  int mhi = (n + NU - 1) >> 1;
+  if (mhi > half - NU - 1) mhi = half - NU - 1;
+  for (int m = mlo; m <= mhi; ++m) {
+    const int c = n - 2 * m + NU - 1;
+    acc = fma(A(m), h[c], acc);
+    acc = fma(D(m), g[c], acc);
+  }
+  if (n < ROWS) {
+#pragma unroll
+    for (int cc = 0; cc < NU; ++cc) {
+      if (cc >= half) break;
+      acc = fma(synL[n * 2 * NU + cc], A(cc), acc);
+      acc = fma(synL[n * 2 * NU + NU + cc], D(cc), acc);
+    }
+  }
+  if (n >= size - ROWS) {
+    const int i = n - (size - ROWS);
+#pragma unroll
+    for (int cc = 0; cc < NU; ++cc) {
+      const int pos = half - 1 - cc;
+      if (pos < right_first) continue;
+      acc = fma(synR[i * 2 * NU + cc], A(pos), acc);
+      acc = fma(synR[i * 2 * NU + NU + cc], D(pos), acc);
+    }
+  }
+  return acc;
+}
+
+// Analysis output o of one line (o < half: scaling coefficient, else wavelet).
+template <typename T, int NU, class FX>
+__device__ __forceinline__ T analysis_at(int o, int half, const T* __restrict__ h, const T* __restrict__ g,
+                                         const T* __restrict__ synL, const T* __restrict__ synR, FX X) {
+  constexpr int ROWS = 3 * NU - 1;
+  const int size = 2 * half;
+  const int kind = o >= half ? 1 : 0;
+  const int m = o - kind * half;
+  const int right_first = half - NU > NU ? half - NU : NU;
+  T acc = T(0);
+  if (m >= NU && m < right_first) {
+    const T* taps = kind ? g : h;
+#pragma unroll
+    for (int c = 0; c < 2 * NU; ++c) acc = fma(taps[c], X(2 * m + c - NU + 1), acc);
+  } else if (m < NU) {
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) acc = fma(synL[r * 2 * NU + kind * NU + m], X(r), acc);
+  } else {
+    const int cc = half - 1 - m;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) acc = fma(synR[r * 2 * NU + kind * NU + cc], X(size - ROWS + r), acc);
+  }
+  return acc;
+}
+
+// Index range of a-part (or d-part) inputs m that synthesis outputs
+// [n0, n1) read, boundary columns included.
+template <int NU>
+__device__ __forceinline__ void synth_input_range(int n0, int n1, int half, int& lo, int& hi) {
+  constexpr int ROWS = 3 * NU - 1;
+  lo = n0 - NU > 0 ? (n0 - NU) >> 1 : 0;
+  hi = (n1 - 1 + NU) >> 1;
+  if (hi > half - 1) hi = half - 1;
+  if (n0 < ROWS) lo = 0;
+  if (n1 > 2 * half - ROWS) hi = half - 1;
+}
+
+// Index range of inputs n that analysis outputs m in [m0, m1) (of either half) read.
+template <int NU>
+__device__ __forceinline__ void analysis_input_range(int m0, int m1, int half, int& lo, int& hi) {
+  constexpr int ROWS = 3 * NU - 1;
+  const int size = 2 * half;
+  lo = 2 * m0 - NU + 1;
+  hi = 2 * (m1 - 1) + NU;
+  if (lo < 0) lo = 0;
+  if (hi > size - 1) hi = size - 1;
+  if (m0 < NU) lo = 0;
+  if (m1 > half - NU) hi = size - 1;
+  (void)ROWS;
+}
+
+// Interior synthesis pair: outputs 2i and 2i+1 when every filter tap lands on
+// an interior coefficient (3nu-1 <= 2i and 2i+1 <= size-3nu).  With
+// c = n - 2m in [-nu+1, nu]: even n uses the even taps, odd n the odd taps.
+template <typename T, int NU, class FA, class FD>
+__device__ __forceinline__ void synth_pair(int i, const T* __restrict__ h, const T* __restrict__ g, FA A, FD D,
+                                           T& e, T& o) {
+  T ae = T(0), ao = T(0);
+#pragma unroll
+  for (int c = -NU + 1; c <= NU; ++c) {
+    if (((c % 2) + 2) % 2 == 0) {
+      const int m = i - c / 2;
+      ae = fma(A(m), h[c + NU - 1], ae);
+      ae = fma(D(m), g[c + NU - 1], ae);
+    } else {
+      const int m = i - (c - 1) / 2;  // c - 1 is even: exact
+      ao = fma(A(m), h[c + NU - 1], ao);
+      ao = fma(D(m), g[c + NU - 1], ao);
+    }
+  }
+  e = ae;
+  o = ao;
+}
+
+template <int NU>
+__device__ __forceinline__ bool pair_is_interior(int i, int half) {
+  return 2 * i >= 3 * NU - 1 && 2 * i + 1 <= 2 * half - 3 * NU;
+}
+
+// Analysis pair (a[m], d[m]) for an interior m (nu <= m < half - nu).
+template <typename T, int NU, class FX>
+__device__ __forceinline__ void analysis_pair(int m, const T* __restrict__ h, const T* __restrict__ g, FX X, T& a,
+                                              T& d) {
+  T sa = T(0), sd = T(0);
+#pragma unroll
+  for (int c = 0; c < 2 * NU; ++c) {
+    const T v = X(2 * m + c - NU + 1);
+    sa = fma(h[c], v, sa);
+    sd = fma(g[c], v, sd);
+  }
+  a = sa;
+  d = sd;
+}
+
+// ---------------------------------------------------------- tiled levels
+// Synthesis level k: X[r][c] = (r < half && c < half) ? ll[r][c] : det[r][c];
+// out = S X S^T (trans: out^T).  Tile: TS x TS outputs, 256 threads.
+template <typename T, int NU, int TS>
+__global__ void __launch_bounds__(256) k_synth2d_tile(const T* __restrict__ ll, int64_t ld_ll,
+                                                      const T* __restrict__ det, int64_t ld_det, T* __restrict__ out,
+                                                      int64_t ld_out, int k, int trans, Tables<T> t) {
+  extern __shared__ unsigned char smem_raw[];
+  T hr[2 * NU], gr[2 * NU];  // filter taps in registers (uniform)
+#pragma unroll
+  for (int c = 0; c < 2 * NU; ++c) hr[c] = t.h[c], gr[c] = t.g[c];
+  // filters and boundary blocks in LDS for the banded (runtime-indexed) path
+  __shared__ T tab_lds[4 * NU + 2 * (3 * NU - 1) * 2 * NU];
+  T* const hs = tab_lds;
+  T* const gs = hs + 2 * NU;
+  T* const sLs = gs + 2 * NU;
+  T* const sRs = sLs + (3 * NU - 1) * 2 * NU;
+  for (int e = int(threadIdx.x); e < 2 * NU; e += int(blockDim.x)) hs[e] = t.h[e], gs[e] = t.g[e];
+  for (int e = int(threadIdx.x); e < (3 * NU - 1) * 2 * NU; e += int(blockDim.x)) sLs[e] = t.synL[e], sRs[e] = t.synR[e];
+  const int half = 1 << k, size = 2 * half;
+  const int ntile = size / TS;
+  const int r0 = int(blockIdx.x / ntile) * TS, c0 = int(blockIdx.x % ntile) * TS;
+  int rlo, rhi, clo, chi;
+  synth_input_range<NU>(r0, r0 + TS, half, rlo, rhi);
+  synth_input_range<NU>(c0, c0 + TS, half, clo, chi);
+  const int nr = rhi - rlo + 1, nc = chi - clo + 1;
+  const int W = 2 * nc + 1;                       // padded LDS row
+  T* Xs = reinterpret_cast<T*>(smem_raw);        // (2 nr) x W
+  T* Ys = Xs + 2 * nr * W;                        // (2 nr) x (TS + 1)
+  constexpr int YW = TS + 1;
+  const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
+  {
+    // all loads of the window are issued before any is consumed
+    constexpr int MAXR = 2 * (TS / 2 + NU + 2), RI = (MAXR + 3) / 4, CJ = (MAXR + 63) / 64;
+    T r[RI][CJ];
+#pragma unroll
+    for (int ii = 0; ii < RI; ++ii) {
+      const int i = wave + 4 * ii;
+      const int row = i < nr ? rlo + i : half + rlo + (i - nr);
+#pragma unroll
+      for (int jj = 0; jj < CJ; ++jj) {
+        const int j = lane + 64 * jj;
+        const int col = j < nc ? clo + j : half + clo + (j - nc);
+        T v = T(0);
+        if (i < 2 * nr && j < 2 * nc)
+          v = (row < half && col < half) ? ll[int64_t(row) * ld_ll + col] : det[int64_t(row) * ld_det + col];
+        r[ii][jj] = v;
+      }
+    }
+#pragma unroll
+    for (int ii = 0; ii < RI; ++ii) {
+      const int i = wave + 4 * ii;
+#pragma unroll
+      for (int jj = 0; jj < CJ; ++jj) {
+        const int j = lane + 64 * jj;
+        if (i < 2 * nr && j < 2 * nc) Xs[i * W + j] = r[ii][jj];
+      }
+    }
+  }
+  __syncthreads();
+  // rows: output column pairs c0 + 2p, p < TS/2; two input rows per wave pass
+  for (int i2 = wave * 2 + (lane >= 32 ? 1 : 0); i2 < 2 * nr; i2 += 8) {
+    const T* xr = Xs + i2 * W;
+    auto A = [&](int m) { return xr[m - clo]; };
+    auto D = [&](int m) { return xr[nc + m - clo]; };
+    for (int p = lane & 31; p < TS / 2; p += 32) {
+      const int ip = (c0 >> 1) + p;
+      T e, o;
+      if (pair_is_interior<NU>(ip, half)) {
+        synth_pair<T, NU>(ip, hr, gr, A, D, e, o);
+      } else {
+        e = synth_at<T, NU>(2 * ip, half, hs, gs, sLs, sRs, A, D);
+        o = synth_at<T, NU>(2 * ip + 1, half, hs, gs, sLs, sRs, A, D);
+      }
+      Ys[i2 * YW + 2 * p] = e;
+      Ys[i2 * YW + 2 * p + 1] = o;
+    }
+  }
+  __syncthreads();
+  // columns: lane = output column, output row pairs over waves; result kept in Xs
+  T* Os = Xs;  // TS x (TS + 1)
+  for (int cc = lane; cc < TS; cc += 64) {
+    auto A = [&](int m) { return Ys[(m - rlo) * YW + cc]; };
+    auto D = [&](int m) { return Ys[(nr + m - rlo) * YW + cc]; };
+    for (int p = wave; p < TS / 2; p += 4) {
+      const int ip = (r0 >> 1) + p;
+      T e, o;
+      if (pair_is_interior<NU>(ip, half)) {
+        synth_pair<T, NU>(ip, hr, gr, A, D, e, o);
+      } else {
+        e = synth_at<T, NU>(2 * ip, half, hs, gs, sLs, sRs, A, D);
+        o = synth_at<T, NU>(2 * ip + 1, half, hs, gs, sLs, sRs, A, D);
+      }
+      Os[(2 * p) * YW + cc] = e;
+      Os[(2 * p + 1) * YW + cc] = o;
+    }
+  }
+  __syncthreads();
+  for (int rr = wave; rr < TS; rr += 4) {
+    for (int cc = lane; cc < TS; cc += 64) {
+      if (trans)
+        out[int64_t(c0 + rr) * ld_out + r0 + cc] = Os[cc * YW + rr];
+      else
+        out[int64_t(r0 + rr) * ld_out + c0 + cc] = Os[rr * YW + cc];
+    }
+  }
+}
+
+// Analysis level k: input xi (size x size; trans: read in^T); output quadrants:
+// LL -> ll[a][b], other bands -> det[row][col].  Tile: TH x TH outputs in each
+// of the four quadrants at the same (a0, b0); 256 threads.
+template <typename T, int NU, int TH>
+__global__ void __launch_bounds__(256) k_analysis2d_tile(const T* __restrict__ in, int64_t ld_in, int trans,
+                                                         T* __restrict__ ll, int64_t ld_ll, T* __restrict__ det,
+                                                         int64_t ld_det, int k, Tables<T> t) {
+  extern __shared__ unsigned char smem_raw[];
+  T hr[2 * NU], gr[2 * NU];  // filter taps in registers (uniform)
+#pragma unroll
+  for (int c = 0; c < 2 * NU; ++c) hr[c] = t.h[c], gr[c] = t.g[c];
+  // filters and boundary blocks in LDS for the banded (runtime-indexed) path
+  __shared__ T tab_lds[4 * NU + 2 * (3 * NU - 1) * 2 * NU];
+  T* const hs = tab_lds;
+  T* const gs = hs + 2 * NU;
+  T* const sLs = gs + 2 * NU;
+  T* const sRs = sLs + (3 * NU - 1) * 2 * NU;
+  for (int e = int(threadIdx.x); e < 2 * NU; e += int(blockDim.x)) hs[e] = t.h[e], gs[e] = t.g[e];
+  for (int e = int(threadIdx.x); e < (3 * NU - 1) * 2 * NU; e += int(blockDim.x)) sLs[e] = t.synL[e], sRs[e] = t.synR[e];
+  const int half = 1 << k;
+  const int ntile = half / TH;
+  const int a0 = int(blockIdx.x / ntile) * TH, b0 = int(blockIdx.x % ntile) * TH;
+  int rlo, rhi, clo, chi;
+  analysis_input_range<NU>(a0, a0 + TH, half, rlo, rhi);
+  analysis_input_range<NU>(b0, b0 + TH, half, clo, chi);
+  const int nr = rhi - rlo + 1, nc = chi - clo + 1;
+  const int W = nc + 1;
+  constexpr int YW = 2 * TH + 1;
+  T* Xs = reinterpret_cast<T*>(smem_raw);   // nr x W
+  T* Ys = Xs + nr * W;                        // nr x YW: a columns then d columns
+  const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
+  {
+    // outer index over waves, inner over lanes (the contiguous direction of `in`)
+    constexpr int MAXR = 2 * TH + 2 * NU + 4, OI = (MAXR + 3) / 4, IJ = (MAXR + 63) / 64;
+    const int no = trans ? nc : nr, ni = trans ? nr : nc;
+    const int64_t ob = trans ? clo : rlo, ib = trans ? rlo : clo;
+    T r[OI][IJ];
+#pragma unroll
+    for (int u = 0; u < OI; ++u) {
+      const int a = wave + 4 * u;
+#pragma unroll
+      for (int v = 0; v < IJ; ++v) {
+        const int b = lane + 64 * v;
+        r[u][v] = (a < no && b < ni) ? in[(ob + a) * ld_in + ib + b] : T(0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < OI; ++u) {
+      const int a = wave + 4 * u;
+#pragma unroll
+      for (int v = 0; v < IJ; ++v) {
+        const int b = lane + 64 * v;
+        if (a < no && b < ni) {
+          if (trans)
+            Xs[b * W + a] = r[u][v];
+          else
+            Xs[a * W + b] = r[u][v];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // rows: each thread forms (a[m], d[m]) for one output column index m
+  for (int i2 = wave * 2 + (lane >= 32 ? 1 : 0); i2 < nr; i2 += 8) {
+    const T* xr = Xs + i2 * W;
+    auto X = [&](int n) { return xr[n - clo]; };
+    for (int p = lane & 31; p < TH; p += 32) {
+      const int m = b0 + p;
+      T a, d;
+      if (m >= NU && m < half - NU) {
+        analysis_pair<T, NU>(m, hr, gr, X, a, d);
+      } else {
+        a = analysis_at<T, NU>(m, half, hs, gs, sLs, sRs, X);
+        d = analysis_at<T, NU>(half + m, half, hs, gs, sLs, sRs, X);
+      }
+      Ys[i2 * YW + p] = a;
+      Ys[i2 * YW + TH + p] = d;
+    }
+  }
+  __syncthreads();
+  // columns: lane = output column (a then d part), rows over waves
+  T* Os = Xs;  // (2 TH) x YW
+  for (int oc = lane; oc < 2 * TH; oc += 64) {
+    auto X = [&](int n) { return Ys[(n - rlo) * YW + oc]; };
+    for (int p = wave; p < TH; p += 4) {
+      const int m = a0 + p;
+      T a, d;
+      if (m >= NU && m < half - NU) {
+        analysis_pair<T, NU>(m, hr, gr, X, a, d);
+      } else {
+        a = analysis_at<T, NU>(m, half, hs, gs, sLs, sRs, X);
+        d = analysis_at<T, NU>(half + m, half, hs, gs, sLs, sRs, X);
+      }
+      Os[p * YW + oc] = a;
+      Os[(TH + p) * YW + oc] = d;
+    }
+  }
+  __syncthreads();
+  for (int rr = wave; rr < 2 * TH; rr += 4) {
+    const int o = rr < TH ? a0 + rr : half + a0 + (rr - TH);
+    for (int oc = lane; oc < 2 * TH; oc += 64) {
+      const int col = oc < TH ? b0 + oc : half + b0 + (oc - TH);
+      const T v = Os[rr * YW + oc];
+      if (o < half && col < half)
+        ll[int64_t(o) * ld_ll + col] = v;
+      else
+        det[int64_t(o) * ld_det + col] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------- coarse levels
+// One workgroup: levels j0 .. kc-1 (output block 2^kc) with the block in LDS.
+// Input x (quadtree, row stride ld_x).  Output: the 2^kc block into out
+// (trans: transposed).
+template <typename T, int NU>
+__global__ void __launch_bounds__(1024) k_synth2d_coarse(const T* __restrict__ x, int64_t ld_x, T* __restrict__ out,
+                                                         int64_t ld_out, int j0, int kc, int trans, Tables<T> t) {
+  extern __shared__ unsigned char smem_raw[];
+  T hr[2 * NU], gr[2 * NU];  // filter taps in registers (uniform)
+#pragma unroll
+  for (int c = 0; c < 2 * NU; ++c) hr[c] = t.h[c], gr[c] = t.g[c];
+  // filters and boundary blocks in LDS for the banded (runtime-indexed) path
+  __shared__ T tab_lds[4 * NU + 2 * (3 * NU - 1) * 2 * NU];
+  T* const hs = tab_lds;
+  T* const gs = hs + 2 * NU;
+  T* const sLs = gs + 2 * NU;
+  T* const sRs = sLs + (3 * NU - 1) * 2 * NU;
+  for (int e = int(threadIdx.x); e < 2 * NU; e += int(blockDim.x)) hs[e] = t.h[e], gs[e] = t.g[e];
+  for (int e = int(threadIdx.x); e < (3 * NU - 1) * 2 * NU; e += int(blockDim.x)) sLs[e] = t.synL[e], sRs[e] = t.synR[e];
+  const int S = 1 << kc, P = S + 1;
+  T* blk = reinterpret_cast<T*>(smem_raw);  // S x P
+  T* tmp = blk + S * P;
+  const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;  // 16 waves
+  for (int i0 = 0; i0 < S; i0 += 128) {  // 8 rows per wave per batch, loads first
+    T r[8][2];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int i = i0 + wave + 16 * u, c = lane + 64 * v;
+        r[u][v] = (i < S && c < S) ? x[int64_t(i) * ld_x + c] : T(0);
+      }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int i = i0 + wave + 16 * u, c = lane + 64 * v;
+        if (i < S && c < S) blk[i * P + c] = r[u][v];
+      }
+  }
+  __syncthreads();
+  for (int k = j0; k < kc; ++k) {
+    const int half = 1 << k, size = 2 * half;
+    for (int i = wave; i < size; i += 16) {  // rows
+      const T* xr = blk + i * P;
+      auto A = [&](int m) { return xr[m]; };
+      auto D = [&](int m) { return xr[half + m]; };
+      for (int p = lane; p < half; p += 64) {
+        T e, o;
+        if (pair_is_interior<NU>(p, half)) {
+          synth_pair<T, NU>(p, hr, gr, A, D, e, o);
+        } else {
+          e = synth_at<T, NU>(2 * p, half, hs, gs, sLs, sRs, A, D);
+          o = synth_at<T, NU>(2 * p + 1, half, hs, gs, sLs, sRs, A, D);
+        }
+        tmp[i * P + 2 * p] = e;
+        tmp[i * P + 2 * p + 1] = o;
+      }
+    }
+    __syncthreads();
+    for (int c = lane; c < size; c += 64) {  // columns
+      auto A = [&](int m) { return tmp[m * P + c]; };
+      auto D = [&](int m) { return tmp[(half + m) * P + c]; };
+      for (int p = wave; p < half; p += 16) {
+        T e, o;
+        if (pair_is_interior<NU>(p, half)) {
+          synth_pair<T, NU>(p, hr, gr, A, D, e, o);
+        } else {
+          e = synth_at<T, NU>(2 * p, half, hs, gs, sLs, sRs, A, D);
+          o = synth_at<T, NU>(2 * p + 1, half, hs, gs, sLs, sRs, A, D);
+        }
+        blk[(2 * p) * P + c] = e;
+        blk[(2 * p + 1) * P + c] = o;
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = wave; i < S; i += 16)
+    for (int c = lane; c < S; c += 64)
+      out[int64_t(i) * ld_out + c] = trans ? blk[c * P + i] : blk[i * P + c];
+}
+
+// One workgroup: analysis levels kc-1 down to j0 on the 2^kc block read from
+// in (trans: in^T); writes the whole 2^kc block of the quadtree into x.
+template <typename T, int NU>
+__global__ void __launch_bounds__(1024) k_analysis2d_coarse(const T* __restrict__ in, int64_t ld_in, int trans,
+                                                            T* __restrict__ x, int64_t ld_x, int j0, int kc,
+                                                            Tables<T> t) {
+  extern __shared__ unsigned char smem_raw[];
+  T hr[2 * NU], gr[2 * NU];  // filter taps in registers (uniform)
+#pragma unroll
+  for (int c = 0; c < 2 * NU; ++c) hr[c] = t.h[c], gr[c] = t.g[c];
+  // filters and boundary blocks in LDS for the banded (runtime-indexed) path
+  __shared__ T tab_lds[4 * NU + 2 * (3 * NU - 1) * 2 * NU];
+  T* const hs = tab_lds;
+  T* const gs = hs + 2 * NU;
+  T* const sLs = gs + 2 * NU;
+  T* const sRs = sLs + (3 * NU - 1) * 2 * NU;
+  for (int e = int(threadIdx.x); e < 2 * NU; e += int(blockDim.x)) hs[e] = t.h[e], gs[e] = t.g[e];
+  for (int e = int(threadIdx.x); e < (3 * NU - 1) * 2 * NU; e += int(blockDim.x)) sLs[e] = t.synL[e], sRs[e] = t.synR[e];
+  const int S = 1 << kc, P = S + 1;
+  T* blk = reinterpret_cast<T*>(smem_raw);
+  T* tmp = blk + S * P;
+  const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
+  for (int i0 = 0; i0 < S; i0 += 128) {
+    T r[8][2];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int i = i0 + wave + 16 * u, c = lane + 64 * v;
+        r[u][v] = (i < S && c < S) ? in[int64_t(i) * ld_in + c] : T(0);
+      }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int i = i0 + wave + 16 * u, c = lane + 64 * v;
+        if (i < S && c < S) {
+          if (trans)
+            blk[c * P + i] = r[u][v];
+          else
+            blk[i * P + c] = r[u][v];
+        }
+      }
+  }
+  __syncthreads();
+  for (int k = kc - 1; k >= j0; --k) {
+    const int half = 1 << k;
+    for (int i = wave; i < 2 * half; i += 16) {  // rows
+      const T* xr = blk + i * P;
+      auto X = [&](int n) { return xr[n]; };
+      for (int m = lane; m < half; m += 64) {
+        T a, d;
+        if (m >= NU && m < half - NU) {
+          analysis_pair<T, NU>(m, hr, gr, X, a, d);
+        } else {
+          a = analysis_at<T, NU>(m, half, hs, gs, sLs, sRs, X);
+          d = analysis_at<T, NU>(half + m, half, hs, gs, sLs, sRs, X);
+        }
+        tmp[i * P + m] = a;
+        tmp[i * P + half + m] = d;
+      }
+    }
+    __syncthreads();
+    for (int c = lane; c < 2 * half; c += 64) {  // columns
+      auto X = [&](int n) { return tmp[n * P + c]; };
+      for (int m = wave; m < half; m += 16) {
+        T a, d;
+        if (m >= NU && m < half - NU) {
+          analysis_pair<T, NU>(m, hr, gr, X, a, d);
+        } else {
+          a = analysis_at<T, NU>(m, half, hs, gs, sLs, sRs, X);
+          d = analysis_at<T, NU>(half + m, half, hs, gs, sLs, sRs, X);
+        }
+        blk[m * P + c] = a;
+        blk[(half + m) * P + c] = d;
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = wave; i < S; i += 16)
+    for (int c = lane; c < S; c += 64) x[int64_t(i) * ld_x + c] = blk[i * P + c];
+}
+
+template <typename T>
+constexpr int coarse_limit() {
+  return sizeof(T) == 4 ? 7 : 6;  // log2 of the largest block kept in LDS
+}
+
+template <typename T, int NU>
+hipError_t idwt2d_impl(const T* x, T* outT, T* s0, T* s1, int64_t M, int j0, int j, const Tables<T>& t,
+                       hipStream_t st) {
+  // Coarse levels in one workgroup, unless the coarsest block is already too
+  // large for LDS (then the first tiled level reads LL_{j0} from x).
+  const bool coarse = j0 < coarse_limit<T>();
+  const int kc = coarse ? (j < coarse_limit<T>() ? j : coarse_limit<T>()) : j0;
+  const bool last = kc == j;
+  hipError_t e = hipSuccess;
+  if (coarse) {
+    const int S = 1 << kc;
+    const size_t smem_c = 2 * size_t(S) * (S + 1) * sizeof(T);
+    T* prev = last ? outT : s0;
+    hipLaunchKernelGGL((k_synth2d_coarse<T, NU>), dim3(1), dim3(1024), smem_c, st, x, M, prev, M, j0, kc,
+                       last ? 1 : 0, t);
+    e = hipGetLastError();
+    if (e != hipSuccess || last) return e;
+  }
+  constexpr int TS = sizeof(T) == 4 ? 64 : 32;
+  const int nrmax = TS / 2 + NU + 2;
+  const size_t smem_t = (size_t(2 * nrmax) * (2 * nrmax + 1) + size_t(2 * nrmax) * (TS + 1)) * sizeof(T);
+  const T* ll = coarse ? s0 : x;
+  for (int k = kc; k < j; ++k) {
+    const bool fin = k == j - 1;
+    T* dst = fin ? outT : (ll == s0 ? s1 : s0);
+    const int ntile = (2 << k) / TS;
+    hipLaunchKernelGGL((k_synth2d_tile<T, NU, TS>), dim3(unsigned(ntile * ntile)), dim3(256), smem_t, st, ll, M, x,
+                       M, dst, M, k, fin ? 1 : 0, t);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    ll = dst;
+  }
+  return hipSuccess;
+}
+
+template <typename T, int NU>
+hipError_t dwt2d_impl(const T* inT, T* x, T* s0, T* s1, int64_t M, int j0, int j, const Tables<T>& t,
+                      hipStream_t st) {
+  const bool coarse = j0 < coarse_limit<T>();
+  const int kc = coarse ? (j < coarse_limit<T>() ? j : coarse_limit<T>()) : j0;
+  const int S = 1 << kc;
+  constexpr int TH = sizeof(T) == 4 ? 32 : 16;
+  const int nrmax = 2 * TH + 2 * NU + 4;
+  const size_t smem_t = (size_t(nrmax) * (nrmax + 1) + size_t(nrmax) * (2 * TH + 1)) * sizeof(T);
+  hipError_t e = hipSuccess;
+  const T* src = inT;
+  int trans = 1;
+  for (int k = j - 1; k >= kc; --k) {
+    // without a coarse stage the last tiled level writes LL_{j0} into x itself
+    T* dst = (!coarse && k == kc) ? x : ((src == s0) ? s1 : s0);
+    const int ntile = (1 << k) / TH;
+    hipLaunchKernelGGL((k_analysis2d_tile<T, NU, TH>), dim3(unsigned(ntile * ntile)), dim3(256), smem_t, st, src, M,
+                       trans, dst, M, x, M, k, t);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    src = dst;
+    trans = 0;
+  }
+  if (!coarse) return hipSuccess;
+  const size_t smem_c = 2 * size_t(S) * (S + 1) * sizeof(T);
+  hipLaunchKernelGGL((k_analysis2d_coarse<T, NU>), dim3(1), dim3(1024), smem_c, st, src, M, trans, x, M, j0, kc, t);
+  return hipGetLastError();
+}
+
+// Raise the dynamic-LDS limit of the kernels that need more than 64 KB (once
+// per plan, outside any stream work).
+template <typename T, int NU>
+hipError_t prepare_impl() {
+  // 160 KB per workgroup, less the static table each kernel keeps in LDS
+  const int lim = 160 * 1024 - int((4 * NU + 2 * (3 * NU - 1) * 2 * NU) * sizeof(T));
+  hipError_t e = hipFuncSetAttribute((const void*)k_synth2d_coarse<T, NU>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_analysis2d_coarse<T, NU>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_synth2d_tile<T, NU, sizeof(T) == 4 ? 64 : 32>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_analysis2d_tile<T, NU, sizeof(T) == 4 ? 32 : 16>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  return e;
+}
+
+#define WH2WAV_DWT_NUS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
+
+}  // namespace
+
+template <typename T>
+hipError_t prepare_dwt2d(int nu) {
+#define X(V) if (nu == V) return prepare_impl<T, V>();
+  WH2WAV_DWT_NUS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+template hipError_t prepare_dwt2d<float>(int);
+template hipError_t prepare_dwt2d<double>(int);
+
+template <typename T>
+hipError_t idwt2d(const T* x, T* outT, T* s0, T* s1, int64_t M, int j0, int j, const Tables<T>& t,
+                  hipStream_t st) {
+#define X(V) if (t.nu == V) return idwt2d_impl<T, V>(x, outT, s0, s1, M, j0, j, t, st);
+  WH2WAV_DWT_NUS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t dwt2d(const T* inT, T* x, T* s0, T* s1, int64_t M, int j0, int j, const Tables<T>& t,
+                 hipStream_t st) {
+#define X(V) if (t.nu == V) return dwt2d_impl<T, V>(inT, x, s0, s1, M, j0, j, t, st);
+  WH2WAV_DWT_NUS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+template hipError_t idwt2d<float>(const float*, float*, float*, float*, int64_t, int, int, const Tables<float>&,
+                                  hipStream_t);
+template hipError_t idwt2d<double>(const double*, double*, double*, double*, int64_t, int, int,
+                                   const Tables<double>&, hipStream_t);
+template hipError_t dwt2d<float>(const float*, float*, float*, float*, int64_t, int, int, const Tables<float>&,
+                                 hipStream_t);
+template hipError_t dwt2d<double>(const double*, double*, double*, double*, int64_t, int, int,
+                                  const Tables<double>&, hipStream_t);
+
+}  // namespace wh2wav_fast

@@ -42,6 +42,19 @@ hipError_t colpass_fwd(const T* xiT, T* Z, int logm, const Tables<T>& t, hipStre
 // Adjoint column pass: Zt (N x M) -> rows of xi'^T (M x M).
 template <typename T>
 hipError_t colpass_adj(const T* Zt, T* xiT, int logm, const Tables<T>& t, hipStream_t st);
+// Multilevel 2D inverse DWT of the quadtree array x (M x M) into xi^T (outT);
+// s0, s1 are M x M scratch arrays (row stride M).
+template <typename T>
+hipError_t idwt2d(const T* x, T* outT, T* s0, T* s1, int64_t M, int j0, int j, const Tables<T>& t, hipStream_t st);
+// Its transpose: xi'^T (inT) -> quadtree x.
+template <typename T>
+hipError_t dwt2d(const T* inT, T* x, T* s0, T* s1, int64_t M, int j0, int j, const Tables<T>& t, hipStream_t st);
+// One-time setup (dynamic LDS limits) for the line kernels of (log2 M, nu).
+template <typename T>
+hipError_t prepare_lines(int logm, int nu);
+// One-time setup (dynamic LDS limits) for the 2D wavelet kernels of order nu.
+template <typename T>
+hipError_t prepare_dwt2d(int nu);
 // out = in^T for an n x n row-major block (n a multiple of 32).
 template <typename T>
 hipError_t transpose(const T* in, T* out, int64_t n, hipStream_t st);

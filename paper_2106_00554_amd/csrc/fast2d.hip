@@ -315,12 +315,17 @@ __global__ void __launch_bounds__(256) k_rowpass_fwd(const T* __restrict__ Z, T*
   const int nw = int(blockDim.x) >> 6;
   const int Q = t.Q;
   T* buf = reinterpret_cast<T*>(smem_raw) + wave * BUF;
+  uint32_t* mrow = reinterpret_cast<uint32_t*>(reinterpret_cast<T*>(smem_raw) + nw * BUF);
   const int64_t r = blockIdx.x;
   T xi[R];
   load_line<T, R>(Z + r * M + lane * R, xi);
   const uint32_t s1 = uint32_t(r >> LOGM), k1 = uint32_t(r & (M - 1));
   const int64_t n1 = int64_t(s1) * M + sequency_of(k1, s1, LOGM);
   const int64_t N = int64_t(M) * Q;
+  if (!om.full) {
+    for (int w = int(threadIdx.x); w < int(om.wpr); w += int(blockDim.x)) mrow[w] = om.mask[n1 * om.wpr + w];
+    __syncthreads();
+  }
   for (int s = wave; s < Q; s += nw) {
     T v[R];
     line_forward<T, R, NU>(xi, v, s, t, lane);
@@ -334,16 +339,15 @@ __global__ void __launch_bounds__(256) k_rowpass_fwd(const T* __restrict__ Z, T*
       }
     } else {
       constexpr int WPP = M / 32, WPL = (WPP + 63) / 64;
-      const uint32_t* rowmask = om.mask + n1 * om.wpr;
       int before = 0;
-      for (int w = lane; w < s * WPP; w += 64) before += __popc(rowmask[w]);
+      for (int w = lane; w < s * WPP; w += 64) before += __popc(mrow[w]);
       before = wave_sum(before);
       uint32_t wv[WPL];
       int cnt = 0;
 #pragma unroll
       for (int i = 0; i < WPL; ++i) {
         const int w = lane * WPL + i;
-        wv[i] = w < WPP ? rowmask[s * WPP + w] : 0u;
+        wv[i] = w < WPP ? mrow[s * WPP + w] : 0u;
         cnt += __popc(wv[i]);
       }
       int64_t o = om.row_ptr[n1] + before + wave_exclusive_scan(cnt, lane);
@@ -375,10 +379,15 @@ __global__ void __launch_bounds__(256) k_rowpass_adj(const T* __restrict__ y, T*
   const int Q = t.Q;
   T* bufs = reinterpret_cast<T*>(smem_raw);
   T* buf = bufs + wave * BUF;
+  uint32_t* mrow = reinterpret_cast<uint32_t*>(bufs + nw * BUF);
   const int64_t r = blockIdx.x;
   const uint32_t s1 = uint32_t(r >> LOGM), k1 = uint32_t(r & (M - 1));
   const int64_t n1 = int64_t(s1) * M + sequency_of(k1, s1, LOGM);
   const int64_t N = int64_t(M) * Q;
+  if (!om.full) {
+    for (int w = int(threadIdx.x); w < int(om.wpr); w += int(blockDim.x)) mrow[w] = om.mask[n1 * om.wpr + w];
+    __syncthreads();
+  }
   T acc[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) acc[i] = T(0);
@@ -387,38 +396,59 @@ __global__ void __launch_bounds__(256) k_rowpass_adj(const T* __restrict__ y, T*
     T v[R];
     if (om.full) {
       const T* yrow = y + n1 * N + int64_t(s) * M;
-      for (int b = lane; b < M; b += 64) {
-        const uint32_t k = natural_of(uint32_t(b), uint32_t(s), LOGM);
-        buf[buf_addr<R>(int(k), LOG_R)] = yrow[b];
+      constexpr int NB = M / 64;
+      T rv[NB];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) rv[i] = yrow[lane + 64 * i];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const uint32_t k = natural_of(uint32_t(lane + 64 * i), uint32_t(s), LOGM);
+        buf[buf_addr<R>(int(k), LOG_R)] = rv[i];
       }
     } else {
 #pragma unroll
       for (int i = 0; i < R; ++i) v[i] = T(0);
       store_line<T, R>(buf + lane * (R + 4), v);
-      wave_sync();
       constexpr int WPP = M / 32, WPL = (WPP + 63) / 64;
-      const uint32_t* rowmask = om.mask + n1 * om.wpr;
       int before = 0;
-      for (int w = lane; w < s * WPP; w += 64) before += __popc(rowmask[w]);
+      for (int w = lane; w < s * WPP; w += 64) before += __popc(mrow[w]);
       before = wave_sum(before);
       uint32_t wv[WPL];
       int cnt = 0;
 #pragma unroll
       for (int i = 0; i < WPL; ++i) {
         const int w = lane * WPL + i;
-        wv[i] = w < WPP ? rowmask[s * WPP + w] : 0u;
+        wv[i] = w < WPP ? mrow[s * WPP + w] : 0u;
         cnt += __popc(wv[i]);
       }
-      int64_t o = om.row_ptr[n1] + before + wave_exclusive_scan(cnt, lane);
+      const int64_t o0 = om.row_ptr[n1] + before + wave_exclusive_scan(cnt, lane);
+      wave_sync();  // zero fill of buf before the scatter
+      // scatter in batches of 8 samples per lane: loads issued before the stores
+      int o = 0;
 #pragma unroll
       for (int i = 0; i < WPL; ++i) {
         uint32_t bits = wv[i];
         const uint32_t wb = uint32_t(lane * WPL + i) * 32u;
         while (bits) {
-          const int bit = __ffs(bits) - 1;
-          bits &= bits - 1;
-          const uint32_t k = natural_of(wb + uint32_t(bit), uint32_t(s), LOGM);
-          buf[buf_addr<R>(int(k), LOG_R)] = y[o++];
+          T rv[8];
+          int kk[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            kk[u] = -1;
+            if (bits) {
+              const int bit = __ffs(bits) - 1;
+              bits &= bits - 1;
+              kk[u] = int(natural_of(wb + uint32_t(bit), uint32_t(s), LOGM));
+              rv[u] = y[o0 + o + u];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (kk[u] >= 0) {
+              buf[buf_addr<R>(kk[u], LOG_R)] = rv[u];
+              ++o;
+            }
+          }
         }
       }
     }
@@ -505,20 +535,23 @@ __global__ void __launch_bounds__(512) k_colpass_adj(const T* __restrict__ Zt, T
   T eacc = T(0);
   for (int s = 0; s < Q; ++s) {
     T v[R];
+    T o[R / 4][4];  // every load of the phase is issued before the exchange rounds
 #pragma unroll
     for (int i = 0; i < R / 4; ++i) {
       const int k = le * R + 4 * i + te;
       const T* src = Zt + (int64_t(s) * M + k) * M + tile * TILE + 4 * half;
-      T o[4];
       if constexpr (sizeof(T) == 4) {
         const float4 f = *reinterpret_cast<const float4*>(src);
-        o[0] = f.x, o[1] = f.y, o[2] = f.z, o[3] = f.w;
+        o[i][0] = f.x, o[i][1] = f.y, o[i][2] = f.z, o[i][3] = f.w;
       } else {
         const double2 f0 = reinterpret_cast<const double2*>(src)[0], f1 = reinterpret_cast<const double2*>(src)[1];
-        o[0] = f0.x, o[1] = f0.y, o[2] = f1.x, o[3] = f1.y;
+        o[i][0] = f0.x, o[i][1] = f0.y, o[i][2] = f1.x, o[i][3] = f1.y;
       }
+    }
 #pragma unroll
-      for (int cc = 0; cc < 4; ++cc) stage[(4 * half + cc) * SP + le * 4 + te] = o[cc];
+    for (int i = 0; i < R / 4; ++i) {
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) stage[(4 * half + cc) * SP + le * 4 + te] = o[i][cc];
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < 4; ++u) v[4 * i + u] = stage[wave * SP + lane * 4 + u];
@@ -546,7 +579,7 @@ template <typename T, int LOGM, int NU>
 hipError_t launch_rowpass_fwd(const T* Z, T* y, const Tables<T>& t, const Omega& om, hipStream_t st) {
   constexpr int M = 1 << LOGM, R = M / 64;
   const int nw = t.Q < 4 ? t.Q : 4;
-  const size_t smem = size_t(nw) * (M + 4 * (M / R)) * sizeof(T);
+  const size_t smem = size_t(nw) * (M + 4 * (M / R)) * sizeof(T) + size_t(om.wpr) * sizeof(uint32_t);
   const int64_t rows = int64_t(M) * t.Q;
   hipLaunchKernelGGL((k_rowpass_fwd<T, LOGM, NU>), dim3(unsigned(rows)), dim3(64 * nw), smem, st, Z, y, t, om);
   return hipGetLastError();
@@ -555,7 +588,7 @@ template <typename T, int LOGM, int NU>
 hipError_t launch_rowpass_adj(const T* y, T* Zt, const Tables<T>& t, const Omega& om, hipStream_t st) {
   constexpr int M = 1 << LOGM, R = M / 64;
   const int nw = t.Q < 4 ? t.Q : 4;
-  const size_t smem = size_t(nw) * (M + 4 * (M / R)) * sizeof(T);
+  const size_t smem = size_t(nw) * (M + 4 * (M / R)) * sizeof(T) + size_t(om.wpr) * sizeof(uint32_t);
   const int64_t rows = int64_t(M) * t.Q;
   hipLaunchKernelGGL((k_rowpass_adj<T, LOGM, NU>), dim3(unsigned(rows)), dim3(64 * nw), smem, st, y, Zt, t, om);
   return hipGetLastError();
@@ -619,6 +652,30 @@ hipError_t colpass_adj(const T* Zt, T* xiT, int logm, const Tables<T>& t, hipStr
 #undef X
   return hipErrorInvalidValue;
 }
+template <typename T, int LOGM, int NU>
+hipError_t prepare_lines_impl() {
+  const int lim = 160 * 1024;
+  hipError_t e = hipFuncSetAttribute((const void*)k_rowpass_fwd<T, LOGM, NU>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_rowpass_adj<T, LOGM, NU>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_colpass_fwd<T, LOGM, NU>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_colpass_adj<T, LOGM, NU>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  return e;
+}
+
+template <typename T>
+hipError_t prepare_lines(int logm, int nu) {
+#define X(L, V) if (logm == L && nu == V) return prepare_lines_impl<T, L, V>();
+  WH2WAV_FAST_CASES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+template hipError_t prepare_lines<float>(int, int);
+template hipError_t prepare_lines<double>(int, int);
+
 template <typename T>
 hipError_t transpose(const T* in, T* out, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_transpose<T>, dim3(unsigned(n / 32), unsigned(n / 32)), dim3(256), 0, st, in, out, n);

@@ -461,11 +461,19 @@ size_t line_smem(const wh2wav_plan_s* p, size_t elem, bool omega_side) {
 
 constexpr size_t kMaxLds = 160 * 1024;
 
+// The dynamic-LDS limit of the line kernels is raised once per plan
+// (prepare_line_kernels); calls only check the size.
 template <typename T>
 int check_and_set_smem(const void* kernel, size_t bytes) {
+  (void)kernel;
   if (bytes > kMaxLds) return fail(WH2WAV_EUNSUPPORTED, "line too long for the LDS line kernels");
-  if (bytes > 64 * 1024)
-    HIP_OK(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
+  return WH2WAV_OK;
+}
+
+template <typename T>
+int prepare_line_kernels() {
+  HIP_OK(hipFuncSetAttribute((const void*)k_fwd_lines<T>, hipFuncAttributeMaxDynamicSharedMemorySize, int(kMaxLds)));
+  HIP_OK(hipFuncSetAttribute((const void*)k_adj_lines<T>, hipFuncAttributeMaxDynamicSharedMemorySize, int(kMaxLds)));
   return WH2WAV_OK;
 }
 
@@ -517,7 +525,9 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
   T* TMP = W + M * M;
   T* Z = TMP + M * M;
   const bool fast = use_fast(p);
-  if (run(0)) {
+  if (fast && run(0))  // xi^T into TMP; W and Z serve as scratch
+    HIP_OK(wh2wav_fast::idwt2d<T>(x, TMP, W, Z, M, H.j0, H.j, fast_tables_of<T>(p), st));
+  if (!fast && run(0)) {
     HIP_OK(hipMemcpyAsync(W, x, sizeof(T) * M * M, hipMemcpyDeviceToDevice, st));
     for (int k = H.j0; k < H.j; ++k) {
       const int64_t size = int64_t(2) << k;
@@ -526,7 +536,6 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
       rc = launch_synth<T>(p, TMP, W, size, 1, M, k, true, false, st);      // columns
       if (rc) return rc;
     }
-    if (fast) HIP_OK(wh2wav_fast::transpose<T>(W, TMP, M, st));  // xi^T for the column pass
   }
   if (fast) {
     if (run(1)) HIP_OK(wh2wav_fast::colpass_fwd<T>(TMP, Z, H.j, fast_tables_of<T>(p), st));
@@ -592,17 +601,7 @@ int adjoint_impl(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t
   if (use_fast(p)) {
     if (run(0)) HIP_OK(wh2wav_fast::rowpass_adj<T>(y, Z, H.j, fast_tables_of<T>(p), fast_omega_of(p), st));
     if (run(1)) HIP_OK(wh2wav_fast::colpass_adj<T>(Z, TMP, H.j, fast_tables_of<T>(p), st));
-    if (run(2)) {
-      HIP_OK(wh2wav_fast::transpose<T>(TMP, W, M, st));
-      for (int k = H.j - 1; k >= H.j0; --k) {
-        const int64_t size = int64_t(2) << k;
-        int rc = launch_synth<T>(p, W, TMP, size, 1, M, k, true, true, st);  // columns
-        if (rc) return rc;
-        rc = launch_synth<T>(p, TMP, W, size, M, 1, k, false, true, st);  // rows
-        if (rc) return rc;
-      }
-      HIP_OK(hipMemcpyAsync(x, W, sizeof(T) * M * M, hipMemcpyDeviceToDevice, st));
-    }
+    if (run(2)) HIP_OK(wh2wav_fast::dwt2d<T>(TMP, x, W, Z, M, H.j0, H.j, fast_tables_of<T>(p), st));
     return WH2WAV_OK;
   }
   int rc = check_and_set_smem<T>((const void*)k_adj_lines<T>, line_smem(p, sizeof(T), true));
@@ -687,6 +686,23 @@ int wh2wav_plan(const wh2wav_desc* desc, wh2wav_plan_t* out) {
   if (2 * size_t(H.M) * elem + sizeof(int) * (size_t(H.words_per_row) + kThreads) > kMaxLds) {
     delete p;
     return fail(WH2WAV_EUNSUPPORTED, "M too large for the LDS line kernels");
+  }
+  rc = H.dtype == WH2WAV_F64 ? prepare_line_kernels<double>() : prepare_line_kernels<float>();
+  if (rc != WH2WAV_OK) {
+    std::string m = g_last_error;
+    delete p;
+    return fail(rc, m);
+  }
+  if (use_fast(p)) {
+    hipError_t e = H.dtype == WH2WAV_F64 ? wh2wav_fast::prepare_dwt2d<double>(H.nu)
+                                         : wh2wav_fast::prepare_dwt2d<float>(H.nu);
+    if (e == hipSuccess)
+      e = H.dtype == WH2WAV_F64 ? wh2wav_fast::prepare_lines<double>(H.j, H.nu)
+                                : wh2wav_fast::prepare_lines<float>(H.j, H.nu);
+    if (e != hipSuccess) {
+      delete p;
+      return fail(WH2WAV_EHIP, std::string("kernel setup: ") + hipGetErrorString(e));
+    }
   }
   rc = H.dtype == WH2WAV_F64 ? upload_tables<double>(p) : upload_tables<float>(p);
   if (rc != WH2WAV_OK) {

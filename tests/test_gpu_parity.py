@@ -236,3 +236,17 @@ def test_parity_2d_wave_kernels(nu, j, q, j0, dens, dtype):
     y, xa = gpu_pair(2, nu, j, q, j0, dtype, X, omega, yv)
     assert rel(y, y_ref) < TOL[dtype], rel(y, y_ref)
     assert rel(xa, x_ref) < TOL[dtype], rel(xa, x_ref)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("nu,j,q,j0", [(2, 9, 1, 7), (4, 9, 1, 8), (3, 10, 1, 6)])
+def test_parity_2d_large_coarse_level(nu, j, q, j0, dtype):
+    """Coarse level J0 at or above the LDS-resident limit of the 2D wavelet kernels."""
+    cfg = op.Config(nu, j, q, j0)
+    X = inputs.coefficients_2d(j, j0, 600 + j0)
+    omega = inputs.multilevel_omega_2d(cfg.N, 0.2, 601)
+    yv = inputs.sample_vector(omega.size, 602)
+    blocks = op.Blocks2D(cfg)
+    y, xa = gpu_pair(2, nu, j, q, j0, dtype, X, omega, yv)
+    assert rel(y, op.forward_2d_full(blocks, X, omega)) < TOL[dtype]
+    assert rel(xa, op.adjoint_2d_full(blocks, yv, omega)) < TOL[dtype]
