@@ -1,0 +1,119 @@
+"""Differentiable form of the operator, and FISTA on top of it.
+
+`forward(op, x)` computes y = P_Omega A x and records it for autograd.  The
+gradient with respect to x is A^T P_Omega^T g, which is exactly the adjoint
+product, so the backward calls the adjoint kernels (and the adjoint's
+backward calls the forward kernels, so every order of derivative is
+available).  A is real (Algorithm 1 works over the reals), so the adjoint is
+the transpose.
+
+Compressive-sensing solvers only need the two products (the paper's
+reconstructions call a solver with the forward and the adjoint); `fista`
+solves the l1-regularised least-squares problem
+
+    min_x  0.5 || P_Omega A x - y ||^2 + lam || x ||_1
+
+with the gradient of the smooth term taken through autograd.  The step 1/L
+with L = 1 is valid because || P_Omega A || <= 1 (the section of an
+orthogonal change of basis, Sec. 2).
+
+A leading batch dimension is accepted: x of shape (B, *op.x_shape) maps to y
+of shape (B, op.m), one product per instance.
+"""
+import torch
+
+
+def _apply(fn, t, in_shape, out_shape, op):
+    lead = tuple(t.shape[: t.dim() - len(in_shape)])
+    if tuple(t.shape[len(lead):]) != tuple(in_shape):
+        raise ValueError(f"expected trailing shape {tuple(in_shape)}, got {tuple(t.shape)}")
+    t = t.contiguous()
+    if not lead:
+        return fn(t)
+    flat = t.reshape((-1,) + tuple(in_shape))
+    out = torch.empty((flat.shape[0],) + tuple(out_shape), dtype=op.dtype, device=op.device)
+    for b in range(flat.shape[0]):
+        fn(flat[b], out=out[b])
+    return out.reshape(lead + tuple(out_shape))
+
+
+class _Forward(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, op):
+        ctx.op = op
+        return _apply(op.forward, x.detach(), op.x_shape, (op.m,), op)
+
+    @staticmethod
+    def backward(ctx, g):
+        return _Adjoint.apply(g, ctx.op), None
+
+
+class _Adjoint(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, y, op):
+        ctx.op = op
+        return _apply(op.adjoint, y.detach(), (op.m,), op.x_shape, op)
+
+    @staticmethod
+    def backward(ctx, g):
+        return _Forward.apply(g, ctx.op), None
+
+
+def forward(op, x):
+    """y = P_Omega A x, differentiable in x."""
+    return _Forward.apply(x, op)
+
+
+def adjoint(op, y):
+    """x = A^T P_Omega^T y, differentiable in y."""
+    return _Adjoint.apply(y, op)
+
+
+class Wh2WavLayer(torch.nn.Module):
+    """nn.Module holding one operator: layer(x) = P_Omega A x."""
+
+    def __init__(self, op):
+        super().__init__()
+        self.op = op
+
+    def forward(self, x):
+        return forward(self.op, x)
+
+    def adjoint(self, y):
+        return adjoint(self.op, y)
+
+
+def soft_threshold(z, t):
+    return torch.sign(z) * torch.clamp(z.abs() - t, min=0.0)
+
+
+def objective(op, x, y, lam):
+    r = forward(op, x) - y
+    return 0.5 * torch.dot(r.reshape(-1), r.reshape(-1)) + lam * x.abs().sum()
+
+
+def fista(op, y, lam, iters, x0=None, L=1.0, callback=None):
+    """FISTA (Beck and Teboulle) for 0.5 ||P_Omega A x - y||^2 + lam ||x||_1.
+
+    The gradient of the smooth term at the extrapolated point is obtained by
+    autograd through `forward` (its backward is the adjoint kernel).  Returns
+    the last iterate.  `callback(k, x)` is called after each iteration if
+    given.
+    """
+    x = torch.zeros(op.x_shape, dtype=op.dtype, device=op.device) if x0 is None else x0.clone()
+    z = x.clone()
+    t = 1.0
+    step = 1.0 / L
+    for k in range(iters):
+        z = z.detach().requires_grad_(True)
+        r = forward(op, z) - y
+        loss = 0.5 * torch.dot(r, r)
+        (grad,) = torch.autograd.grad(loss, z)
+        with torch.no_grad():
+            x_new = soft_threshold(z - step * grad, step * lam)
+            t_new = 0.5 * (1.0 + (1.0 + 4.0 * t * t) ** 0.5)
+            z = x_new + ((t - 1.0) / t_new) * (x_new - x)
+        x, t = x_new, t_new
+        if callback is not None:
+            callback(k, x)
+    return x

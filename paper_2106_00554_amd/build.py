@@ -5,6 +5,7 @@ the kernels and the C-ABI entry points with hipcc for gfx950.  Packed FP32
 instructions are disabled for all device code.  The library is written next
 to this file so that it travels with the source tree.
 """
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -41,18 +42,21 @@ def _run(cmd, verbose):
 def build(verbose=False):
     """Compile every source and link libwh2wav.so; returns the library path."""
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    jobs = []
     for src in sorted(os.listdir(CSRC)):
         path = os.path.join(CSRC, src)
         base, ext = os.path.splitext(src)
         obj = os.path.join(BUILD, base + ".o")
         if ext == ".cpp":
-            _run([shutil.which("g++") or "g++"] + CXX_FLAGS + ["-c", path, "-o", obj], verbose)
+            jobs.append(([shutil.which("g++") or "g++"] + CXX_FLAGS + ["-c", path, "-o", obj], obj))
         elif ext == ".hip":
-            _run([HIPCC] + HIP_FLAGS + ["-c", path, "-o", obj], verbose)
-        else:
-            continue
-        objs.append(obj)
+            jobs.append(([HIPCC] + HIP_FLAGS + ["-c", path, "-o", obj], obj))
+    # one compiler process per source file, side by side
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", "4"))))
+    with concurrent.futures.ThreadPoolExecutor(workers) as pool:
+        for f in [pool.submit(_run, cmd, verbose) for cmd, _ in jobs]:
+            f.result()
+    objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-o", tmp] + objs + ["-lquadmath"], verbose)
     os.replace(tmp, LIB)

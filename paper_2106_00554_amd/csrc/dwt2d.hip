@@ -84,7 +84,7 @@ __device__ __forceinline__ T analysis_at(int o, int half, const T* __restrict__ 
 // Index range of a-part (or d-part) inputs m that synthesis outputs
 // [n0, n1) read, boundary columns included.
 template <int NU>
-__device__ __forceinline__ void synth_input_range(int n0, int n1, int half, int& lo, int& hi) {
+__host__ __device__ __forceinline__ void synth_input_range(int n0, int n1, int half, int& lo, int& hi) {
   constexpr int ROWS = 3 * NU - 1;
   lo = n0 - NU > 0 ? (n0 - NU) >> 1 : 0;
   hi = (n1 - 1 + NU) >> 1;
@@ -95,7 +95,7 @@ __device__ __forceinline__ void synth_input_range(int n0, int n1, int half, int&
 
 // Index range of inputs n that analysis outputs m in [m0, m1) (of either half) read.
 template <int NU>
-__device__ __forceinline__ void analysis_input_range(int m0, int m1, int half, int& lo, int& hi) {
+__host__ __device__ __forceinline__ void analysis_input_range(int m0, int m1, int half, int& lo, int& hi) {
   constexpr int ROWS = 3 * NU - 1;
   const int size = 2 * half;
   lo = 2 * m0 - NU + 1;
@@ -150,25 +150,120 @@ __device__ __forceinline__ void analysis_pair(int m, const T* __restrict__ h, co
   d = sd;
 }
 
+// Offsets m - i of the inputs that interior synthesis pair i reads.
+template <int NU>
+__host__ __device__ constexpr int synth_off(int c) {
+  return (((c % 2) + 2) % 2 == 0) ? -c / 2 : -(c - 1) / 2;
+}
+template <int NU>
+__host__ __device__ constexpr int synth_lo() {
+  int v = 0;
+  for (int c = -NU + 1; c <= NU; ++c) v = synth_off<NU>(c) < v ? synth_off<NU>(c) : v;
+  return v;
+}
+template <int NU>
+__host__ __device__ constexpr int synth_hi() {
+  int v = 0;
+  for (int c = -NU + 1; c <= NU; ++c) v = synth_off<NU>(c) > v ? synth_off<NU>(c) : v;
+  return v;
+}
+
+// P consecutive interior synthesis pairs i0 .. i0+P-1 of one line.  pa points
+// at a(i0 + lo), pd at d(i0 + lo); consecutive m are `stride` elements apart.
+// Inputs are read once into registers and reused by every tap.
+template <typename T, int NU, int P>
+__device__ __forceinline__ void synth_run(const T* __restrict__ pa, const T* __restrict__ pd, int stride,
+                                          const T (&hr)[2 * NU], const T (&gr)[2 * NU], T (&e)[P], T (&o)[P]) {
+  constexpr int LO = synth_lo<NU>(), L = P + synth_hi<NU>() - LO;
+  T a[L], d[L];
+#pragma unroll
+  for (int u = 0; u < L; ++u) {
+    a[u] = pa[u * stride];
+    d[u] = pd[u * stride];
+  }
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    T ae = T(0), ao = T(0);
+#pragma unroll
+    for (int c = -NU + 1; c <= NU; ++c) {
+      const int idx = p + synth_off<NU>(c) - LO;
+      if (((c % 2) + 2) % 2 == 0) {
+        ae = fma(a[idx], hr[c + NU - 1], ae);
+        ae = fma(d[idx], gr[c + NU - 1], ae);
+      } else {
+        ao = fma(a[idx], hr[c + NU - 1], ao);
+        ao = fma(d[idx], gr[c + NU - 1], ao);
+      }
+    }
+    e[p] = ae;
+    o[p] = ao;
+  }
+}
+
+// P consecutive interior analysis outputs m0 .. m0+P-1 (scaling and wavelet
+// coefficient of each); px points at x(2 m0 - nu + 1).
+template <typename T, int NU, int P>
+__device__ __forceinline__ void analysis_run(const T* __restrict__ px, int stride, const T (&hr)[2 * NU],
+                                             const T (&gr)[2 * NU], T (&a)[P], T (&d)[P]) {
+  constexpr int L = 2 * P + 2 * NU - 2;
+  T v[L];
+#pragma unroll
+  for (int u = 0; u < L; ++u) v[u] = px[u * stride];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    T sa = T(0), sd = T(0);
+#pragma unroll
+    for (int c = 0; c < 2 * NU; ++c) {
+      sa = fma(hr[c], v[2 * p + c], sa);
+      sd = fma(gr[c], v[2 * p + c], sd);
+    }
+    a[p] = sa;
+    d[p] = sd;
+  }
+}
+
+template <typename T>
+struct TileLds {
+  T* hs;
+  T* gs;
+  T* sLs;
+  T* sRs;
+};
+
+// Filters and boundary blocks: taps in registers for the interior runs, a
+// copy in LDS for the runtime-indexed boundary outputs.
+template <typename T, int NU>
+__device__ __forceinline__ TileLds<T> load_tables(const Tables<T>& t, T* tab_lds, T (&hr)[2 * NU], T (&gr)[2 * NU]) {
+#pragma unroll
+  for (int c = 0; c < 2 * NU; ++c) hr[c] = t.h[c], gr[c] = t.g[c];
+  TileLds<T> L;
+  L.hs = tab_lds;
+  L.gs = L.hs + 2 * NU;
+  L.sLs = L.gs + 2 * NU;
+  L.sRs = L.sLs + (3 * NU - 1) * 2 * NU;
+  for (int e = int(threadIdx.x); e < 2 * NU; e += int(blockDim.x)) L.hs[e] = t.h[e], L.gs[e] = t.g[e];
+  for (int e = int(threadIdx.x); e < (3 * NU - 1) * 2 * NU; e += int(blockDim.x))
+    L.sLs[e] = t.synL[e], L.sRs[e] = t.synR[e];
+  return L;
+}
+
+template <int NU>
+constexpr int tab_lds_size() {
+  return 4 * NU + 2 * (3 * NU - 1) * 2 * NU;
+}
+
 // ---------------------------------------------------------- tiled levels
 // Synthesis level k: X[r][c] = (r < half && c < half) ? ll[r][c] : det[r][c];
-// out = S X S^T (trans: out^T).  Tile: TS x TS outputs, 256 threads.
-template <typename T, int NU, int TS>
+// out = S X S^T (trans: out^T).  Tile: TS x TS outputs, 256 threads; each
+// thread produces runs of P output pairs.
+template <typename T, int NU, int TS, int P>
 __global__ void __launch_bounds__(256) k_synth2d_tile(const T* __restrict__ ll, int64_t ld_ll,
                                                       const T* __restrict__ det, int64_t ld_det, T* __restrict__ out,
                                                       int64_t ld_out, int k, int trans, Tables<T> t) {
   extern __shared__ unsigned char smem_raw[];
-  T hr[2 * NU], gr[2 * NU];  // filter taps in registers (uniform)
-#pragma unroll
-  for (int c = 0; c < 2 * NU; ++c) hr[c] = t.h[c], gr[c] = t.g[c];
-  // filters and boundary blocks in LDS for the banded (runtime-indexed) path
-  __shared__ T tab_lds[4 * NU + 2 * (3 * NU - 1) * 2 * NU];
-  T* const hs = tab_lds;
-  T* const gs = hs + 2 * NU;
-  T* const sLs = gs + 2 * NU;
-  T* const sRs = sLs + (3 * NU - 1) * 2 * NU;
-  for (int e = int(threadIdx.x); e < 2 * NU; e += int(blockDim.x)) hs[e] = t.h[e], gs[e] = t.g[e];
-  for (int e = int(threadIdx.x); e < (3 * NU - 1) * 2 * NU; e += int(blockDim.x)) sLs[e] = t.synL[e], sRs[e] = t.synR[e];
+  __shared__ T tab_lds[tab_lds_size<NU>()];
+  T hr[2 * NU], gr[2 * NU];
+  const TileLds<T> tl = load_tables<T, NU>(t, tab_lds, hr, gr);
   const int half = 1 << k, size = 2 * half;
   const int ntile = size / TS;
   const int r0 = int(blockIdx.x / ntile) * TS, c0 = int(blockIdx.x % ntile) * TS;
@@ -178,8 +273,8 @@ __global__ void __launch_bounds__(256) k_synth2d_tile(const T* __restrict__ ll, 
   const int nr = rhi - rlo + 1, nc = chi - clo + 1;
   const int W = 2 * nc + 1;                       // padded LDS row
   T* Xs = reinterpret_cast<T*>(smem_raw);        // (2 nr) x W
-  T* Ys = Xs + 2 * nr * W;                        // (2 nr) x (TS + 1)
   constexpr int YW = TS + 1;
+  T* Ys = Xs + 2 * nr * W;                        // (2 nr) x YW
   const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
   {
     // all loads of the window are issued before any is consumed
@@ -210,41 +305,46 @@ __global__ void __launch_bounds__(256) k_synth2d_tile(const T* __restrict__ ll, 
     }
   }
   __syncthreads();
-  // rows: output column pairs c0 + 2p, p < TS/2; two input rows per wave pass
-  for (int i2 = wave * 2 + (lane >= 32 ? 1 : 0); i2 < 2 * nr; i2 += 8) {
+  constexpr int RUNS = TS / (2 * P), LO = synth_lo<NU>();
+  // rows: work item = (window row, run of P output pairs)
+  for (int item = int(threadIdx.x); item < 2 * nr * RUNS; item += 256) {
+    const int i2 = item % (2 * nr), u = item / (2 * nr);
     const T* xr = Xs + i2 * W;
-    auto A = [&](int m) { return xr[m - clo]; };
-    auto D = [&](int m) { return xr[nc + m - clo]; };
-    for (int p = lane & 31; p < TS / 2; p += 32) {
-      const int ip = (c0 >> 1) + p;
-      T e, o;
-      if (pair_is_interior<NU>(ip, half)) {
-        synth_pair<T, NU>(ip, hr, gr, A, D, e, o);
-      } else {
-        e = synth_at<T, NU>(2 * ip, half, hs, gs, sLs, sRs, A, D);
-        o = synth_at<T, NU>(2 * ip + 1, half, hs, gs, sLs, sRs, A, D);
+    const int i0 = (c0 >> 1) + u * P;
+    T* yr = Ys + i2 * YW + 2 * u * P;
+    if (pair_is_interior<NU>(i0, half) && pair_is_interior<NU>(i0 + P - 1, half)) {
+      T e[P], o[P];
+      synth_run<T, NU, P>(xr + i0 + LO - clo, xr + nc + i0 + LO - clo, 1, hr, gr, e, o);
+#pragma unroll
+      for (int p = 0; p < P; ++p) yr[2 * p] = e[p], yr[2 * p + 1] = o[p];
+    } else {
+      auto A = [&](int m) { return xr[m - clo]; };
+      auto D = [&](int m) { return xr[nc + m - clo]; };
+      for (int p = 0; p < P; ++p) {
+        yr[2 * p] = synth_at<T, NU>(2 * (i0 + p), half, tl.hs, tl.gs, tl.sLs, tl.sRs, A, D);
+        yr[2 * p + 1] = synth_at<T, NU>(2 * (i0 + p) + 1, half, tl.hs, tl.gs, tl.sLs, tl.sRs, A, D);
       }
-      Ys[i2 * YW + 2 * p] = e;
-      Ys[i2 * YW + 2 * p + 1] = o;
     }
   }
   __syncthreads();
-  // columns: lane = output column, output row pairs over waves; result kept in Xs
-  T* Os = Xs;  // TS x (TS + 1)
-  for (int cc = lane; cc < TS; cc += 64) {
-    auto A = [&](int m) { return Ys[(m - rlo) * YW + cc]; };
-    auto D = [&](int m) { return Ys[(nr + m - rlo) * YW + cc]; };
-    for (int p = wave; p < TS / 2; p += 4) {
-      const int ip = (r0 >> 1) + p;
-      T e, o;
-      if (pair_is_interior<NU>(ip, half)) {
-        synth_pair<T, NU>(ip, hr, gr, A, D, e, o);
-      } else {
-        e = synth_at<T, NU>(2 * ip, half, hs, gs, sLs, sRs, A, D);
-        o = synth_at<T, NU>(2 * ip + 1, half, hs, gs, sLs, sRs, A, D);
+  // columns: work item = (output column, run of P output row pairs); result in Xs
+  T* Os = Xs;  // TS x YW
+  for (int item = int(threadIdx.x); item < TS * RUNS; item += 256) {
+    const int cc = item % TS, u = item / TS;
+    const int i0 = (r0 >> 1) + u * P;
+    T* oc = Os + 2 * u * P * YW + cc;
+    if (pair_is_interior<NU>(i0, half) && pair_is_interior<NU>(i0 + P - 1, half)) {
+      T e[P], o[P];
+      synth_run<T, NU, P>(Ys + (i0 + LO - rlo) * YW + cc, Ys + (nr + i0 + LO - rlo) * YW + cc, YW, hr, gr, e, o);
+#pragma unroll
+      for (int p = 0; p < P; ++p) oc[2 * p * YW] = e[p], oc[(2 * p + 1) * YW] = o[p];
+    } else {
+      auto A = [&](int m) { return Ys[(m - rlo) * YW + cc]; };
+      auto D = [&](int m) { return Ys[(nr + m - rlo) * YW + cc]; };
+      for (int p = 0; p < P; ++p) {
+        oc[2 * p * YW] = synth_at<T, NU>(2 * (i0 + p), half, tl.hs, tl.gs, tl.sLs, tl.sRs, A, D);
+        oc[(2 * p + 1) * YW] = synth_at<T, NU>(2 * (i0 + p) + 1, half, tl.hs, tl.gs, tl.sLs, tl.sRs, A, D);
       }
-      Os[(2 * p) * YW + cc] = e;
-      Os[(2 * p + 1) * YW + cc] = o;
     }
   }
   __syncthreads();
@@ -260,23 +360,15 @@ __global__ void __launch_bounds__(256) k_synth2d_tile(const T* __restrict__ ll, 
 
 // Analysis level k: input xi (size x size; trans: read in^T); output quadrants:
 // LL -> ll[a][b], other bands -> det[row][col].  Tile: TH x TH outputs in each
-// of the four quadrants at the same (a0, b0); 256 threads.
-template <typename T, int NU, int TH>
+// of the four quadrants at the same (a0, b0); 256 threads; runs of P outputs.
+template <typename T, int NU, int TH, int P>
 __global__ void __launch_bounds__(256) k_analysis2d_tile(const T* __restrict__ in, int64_t ld_in, int trans,
                                                          T* __restrict__ ll, int64_t ld_ll, T* __restrict__ det,
                                                          int64_t ld_det, int k, Tables<T> t) {
   extern __shared__ unsigned char smem_raw[];
-  T hr[2 * NU], gr[2 * NU];  // filter taps in registers (uniform)
-#pragma unroll
-  for (int c = 0; c < 2 * NU; ++c) hr[c] = t.h[c], gr[c] = t.g[c];
-  // filters and boundary blocks in LDS for the banded (runtime-indexed) path
-  __shared__ T tab_lds[4 * NU + 2 * (3 * NU - 1) * 2 * NU];
-  T* const hs = tab_lds;
-  T* const gs = hs + 2 * NU;
-  T* const sLs = gs + 2 * NU;
-  T* const sRs = sLs + (3 * NU - 1) * 2 * NU;
-  for (int e = int(threadIdx.x); e < 2 * NU; e += int(blockDim.x)) hs[e] = t.h[e], gs[e] = t.g[e];
-  for (int e = int(threadIdx.x); e < (3 * NU - 1) * 2 * NU; e += int(blockDim.x)) sLs[e] = t.synL[e], sRs[e] = t.synR[e];
+  __shared__ T tab_lds[tab_lds_size<NU>()];
+  T hr[2 * NU], gr[2 * NU];
+  const TileLds<T> tl = load_tables<T, NU>(t, tab_lds, hr, gr);
   const int half = 1 << k;
   const int ntile = half / TH;
   const int a0 = int(blockIdx.x / ntile) * TH, b0 = int(blockIdx.x % ntile) * TH;
@@ -320,39 +412,43 @@ __global__ void __launch_bounds__(256) k_analysis2d_tile(const T* __restrict__ i
     }
   }
   __syncthreads();
-  // rows: each thread forms (a[m], d[m]) for one output column index m
-  for (int i2 = wave * 2 + (lane >= 32 ? 1 : 0); i2 < nr; i2 += 8) {
+  constexpr int RUNS = TH / P;
+  // rows: work item = (window row, run of P outputs m)
+  for (int item = int(threadIdx.x); item < nr * RUNS; item += 256) {
+    const int i2 = item % nr, u = item / nr;
     const T* xr = Xs + i2 * W;
-    auto X = [&](int n) { return xr[n - clo]; };
-    for (int p = lane & 31; p < TH; p += 32) {
-      const int m = b0 + p;
-      T a, d;
-      if (m >= NU && m < half - NU) {
-        analysis_pair<T, NU>(m, hr, gr, X, a, d);
-      } else {
-        a = analysis_at<T, NU>(m, half, hs, gs, sLs, sRs, X);
-        d = analysis_at<T, NU>(half + m, half, hs, gs, sLs, sRs, X);
+    const int m0 = b0 + u * P;
+    T* yr = Ys + i2 * YW + u * P;
+    if (m0 >= NU && m0 + P - 1 < half - NU) {
+      T a[P], d[P];
+      analysis_run<T, NU, P>(xr + 2 * m0 - NU + 1 - clo, 1, hr, gr, a, d);
+#pragma unroll
+      for (int p = 0; p < P; ++p) yr[p] = a[p], yr[TH + p] = d[p];
+    } else {
+      auto X = [&](int n) { return xr[n - clo]; };
+      for (int p = 0; p < P; ++p) {
+        yr[p] = analysis_at<T, NU>(m0 + p, half, tl.hs, tl.gs, tl.sLs, tl.sRs, X);
+        yr[TH + p] = analysis_at<T, NU>(half + m0 + p, half, tl.hs, tl.gs, tl.sLs, tl.sRs, X);
       }
-      Ys[i2 * YW + p] = a;
-      Ys[i2 * YW + TH + p] = d;
     }
   }
   __syncthreads();
-  // columns: lane = output column (a then d part), rows over waves
+  // columns: work item = (output column of the a|d row, run of P outputs)
   T* Os = Xs;  // (2 TH) x YW
-  for (int oc = lane; oc < 2 * TH; oc += 64) {
-    auto X = [&](int n) { return Ys[(n - rlo) * YW + oc]; };
-    for (int p = wave; p < TH; p += 4) {
-      const int m = a0 + p;
-      T a, d;
-      if (m >= NU && m < half - NU) {
-        analysis_pair<T, NU>(m, hr, gr, X, a, d);
-      } else {
-        a = analysis_at<T, NU>(m, half, hs, gs, sLs, sRs, X);
-        d = analysis_at<T, NU>(half + m, half, hs, gs, sLs, sRs, X);
+  for (int item = int(threadIdx.x); item < 2 * TH * RUNS; item += 256) {
+    const int oc = item % (2 * TH), u = item / (2 * TH);
+    const int m0 = a0 + u * P;
+    if (m0 >= NU && m0 + P - 1 < half - NU) {
+      T a[P], d[P];
+      analysis_run<T, NU, P>(Ys + (2 * m0 - NU + 1 - rlo) * YW + oc, YW, hr, gr, a, d);
+#pragma unroll
+      for (int p = 0; p < P; ++p) Os[(u * P + p) * YW + oc] = a[p], Os[(TH + u * P + p) * YW + oc] = d[p];
+    } else {
+      auto X = [&](int n) { return Ys[(n - rlo) * YW + oc]; };
+      for (int p = 0; p < P; ++p) {
+        Os[(u * P + p) * YW + oc] = analysis_at<T, NU>(m0 + p, half, tl.hs, tl.gs, tl.sLs, tl.sRs, X);
+        Os[(TH + u * P + p) * YW + oc] = analysis_at<T, NU>(half + m0 + p, half, tl.hs, tl.gs, tl.sLs, tl.sRs, X);
       }
-      Os[p * YW + oc] = a;
-      Os[(TH + p) * YW + oc] = d;
     }
   }
   __syncthreads();
@@ -377,17 +473,9 @@ template <typename T, int NU>
 __global__ void __launch_bounds__(1024) k_synth2d_coarse(const T* __restrict__ x, int64_t ld_x, T* __restrict__ out,
                                                          int64_t ld_out, int j0, int kc, int trans, Tables<T> t) {
   extern __shared__ unsigned char smem_raw[];
-  T hr[2 * NU], gr[2 * NU];  // filter taps in registers (uniform)
-#pragma unroll
-  for (int c = 0; c < 2 * NU; ++c) hr[c] = t.h[c], gr[c] = t.g[c];
-  // filters and boundary blocks in LDS for the banded (runtime-indexed) path
-  __shared__ T tab_lds[4 * NU + 2 * (3 * NU - 1) * 2 * NU];
-  T* const hs = tab_lds;
-  T* const gs = hs + 2 * NU;
-  T* const sLs = gs + 2 * NU;
-  T* const sRs = sLs + (3 * NU - 1) * 2 * NU;
-  for (int e = int(threadIdx.x); e < 2 * NU; e += int(blockDim.x)) hs[e] = t.h[e], gs[e] = t.g[e];
-  for (int e = int(threadIdx.x); e < (3 * NU - 1) * 2 * NU; e += int(blockDim.x)) sLs[e] = t.synL[e], sRs[e] = t.synR[e];
+  __shared__ T tab_lds[tab_lds_size<NU>()];
+  T hr[2 * NU], gr[2 * NU];
+  const TileLds<T> tl = load_tables<T, NU>(t, tab_lds, hr, gr);
   const int S = 1 << kc, P = S + 1;
   T* blk = reinterpret_cast<T*>(smem_raw);  // S x P
   T* tmp = blk + S * P;
@@ -410,38 +498,46 @@ __global__ void __launch_bounds__(1024) k_synth2d_coarse(const T* __restrict__ x
       }
   }
   __syncthreads();
+  constexpr int CP = 2, LO = synth_lo<NU>();
   for (int k = j0; k < kc; ++k) {
     const int half = 1 << k, size = 2 * half;
-    for (int i = wave; i < size; i += 16) {  // rows
+    const int runs = (half + CP - 1) / CP;
+    // rows: work item = (row, run of CP output pairs); consecutive lanes take consecutive rows
+    for (int item = int(threadIdx.x); item < size * runs; item += 1024) {
+      const int i = item % size, i0 = (item / size) * CP;
       const T* xr = blk + i * P;
-      auto A = [&](int m) { return xr[m]; };
-      auto D = [&](int m) { return xr[half + m]; };
-      for (int p = lane; p < half; p += 64) {
-        T e, o;
-        if (pair_is_interior<NU>(p, half)) {
-          synth_pair<T, NU>(p, hr, gr, A, D, e, o);
-        } else {
-          e = synth_at<T, NU>(2 * p, half, hs, gs, sLs, sRs, A, D);
-          o = synth_at<T, NU>(2 * p + 1, half, hs, gs, sLs, sRs, A, D);
+      T* yr = tmp + i * P + 2 * i0;
+      if (pair_is_interior<NU>(i0, half) && pair_is_interior<NU>(i0 + CP - 1, half)) {
+        T e[CP], o[CP];
+        synth_run<T, NU, CP>(xr + i0 + LO, xr + half + i0 + LO, 1, hr, gr, e, o);
+#pragma unroll
+        for (int p = 0; p < CP; ++p) yr[2 * p] = e[p], yr[2 * p + 1] = o[p];
+      } else {
+        auto A = [&](int m) { return xr[m]; };
+        auto D = [&](int m) { return xr[half + m]; };
+        for (int p = 0; p < CP && i0 + p < half; ++p) {
+          yr[2 * p] = synth_at<T, NU>(2 * (i0 + p), half, tl.hs, tl.gs, tl.sLs, tl.sRs, A, D);
+          yr[2 * p + 1] = synth_at<T, NU>(2 * (i0 + p) + 1, half, tl.hs, tl.gs, tl.sLs, tl.sRs, A, D);
         }
-        tmp[i * P + 2 * p] = e;
-        tmp[i * P + 2 * p + 1] = o;
       }
     }
     __syncthreads();
-    for (int c = lane; c < size; c += 64) {  // columns
-      auto A = [&](int m) { return tmp[m * P + c]; };
-      auto D = [&](int m) { return tmp[(half + m) * P + c]; };
-      for (int p = wave; p < half; p += 16) {
-        T e, o;
-        if (pair_is_interior<NU>(p, half)) {
-          synth_pair<T, NU>(p, hr, gr, A, D, e, o);
-        } else {
-          e = synth_at<T, NU>(2 * p, half, hs, gs, sLs, sRs, A, D);
-          o = synth_at<T, NU>(2 * p + 1, half, hs, gs, sLs, sRs, A, D);
+    // columns: work item = (column, run of CP output row pairs)
+    for (int item = int(threadIdx.x); item < size * runs; item += 1024) {
+      const int c = item % size, i0 = (item / size) * CP;
+      T* oc = blk + 2 * i0 * P + c;
+      if (pair_is_interior<NU>(i0, half) && pair_is_interior<NU>(i0 + CP - 1, half)) {
+        T e[CP], o[CP];
+        synth_run<T, NU, CP>(tmp + (i0 + LO) * P + c, tmp + (half + i0 + LO) * P + c, P, hr, gr, e, o);
+#pragma unroll
+        for (int p = 0; p < CP; ++p) oc[2 * p * P] = e[p], oc[(2 * p + 1) * P] = o[p];
+      } else {
+        auto A = [&](int m) { return tmp[m * P + c]; };
+        auto D = [&](int m) { return tmp[(half + m) * P + c]; };
+        for (int p = 0; p < CP && i0 + p < half; ++p) {
+          oc[2 * p * P] = synth_at<T, NU>(2 * (i0 + p), half, tl.hs, tl.gs, tl.sLs, tl.sRs, A, D);
+          oc[(2 * p + 1) * P] = synth_at<T, NU>(2 * (i0 + p) + 1, half, tl.hs, tl.gs, tl.sLs, tl.sRs, A, D);
         }
-        blk[(2 * p) * P + c] = e;
-        blk[(2 * p + 1) * P + c] = o;
       }
     }
     __syncthreads();
@@ -458,17 +554,9 @@ __global__ void __launch_bounds__(1024) k_analysis2d_coarse(const T* __restrict_
                                                             T* __restrict__ x, int64_t ld_x, int j0, int kc,
                                                             Tables<T> t) {
   extern __shared__ unsigned char smem_raw[];
-  T hr[2 * NU], gr[2 * NU];  // filter taps in registers (uniform)
-#pragma unroll
-  for (int c = 0; c < 2 * NU; ++c) hr[c] = t.h[c], gr[c] = t.g[c];
-  // filters and boundary blocks in LDS for the banded (runtime-indexed) path
-  __shared__ T tab_lds[4 * NU + 2 * (3 * NU - 1) * 2 * NU];
-  T* const hs = tab_lds;
-  T* const gs = hs + 2 * NU;
-  T* const sLs = gs + 2 * NU;
-  T* const sRs = sLs + (3 * NU - 1) * 2 * NU;
-  for (int e = int(threadIdx.x); e < 2 * NU; e += int(blockDim.x)) hs[e] = t.h[e], gs[e] = t.g[e];
-  for (int e = int(threadIdx.x); e < (3 * NU - 1) * 2 * NU; e += int(blockDim.x)) sLs[e] = t.synL[e], sRs[e] = t.synR[e];
+  __shared__ T tab_lds[tab_lds_size<NU>()];
+  T hr[2 * NU], gr[2 * NU];
+  const TileLds<T> tl = load_tables<T, NU>(t, tab_lds, hr, gr);
   const int S = 1 << kc, P = S + 1;
   T* blk = reinterpret_cast<T*>(smem_raw);
   T* tmp = blk + S * P;
@@ -496,36 +584,43 @@ __global__ void __launch_bounds__(1024) k_analysis2d_coarse(const T* __restrict_
       }
   }
   __syncthreads();
+  constexpr int CP = 2;
   for (int k = kc - 1; k >= j0; --k) {
-    const int half = 1 << k;
-    for (int i = wave; i < 2 * half; i += 16) {  // rows
+    const int half = 1 << k, size = 2 * half;
+    const int runs = (half + CP - 1) / CP;
+    // rows: work item = (row, run of CP outputs m)
+    for (int item = int(threadIdx.x); item < size * runs; item += 1024) {
+      const int i = item % size, m0 = (item / size) * CP;
       const T* xr = blk + i * P;
-      auto X = [&](int n) { return xr[n]; };
-      for (int m = lane; m < half; m += 64) {
-        T a, d;
-        if (m >= NU && m < half - NU) {
-          analysis_pair<T, NU>(m, hr, gr, X, a, d);
-        } else {
-          a = analysis_at<T, NU>(m, half, hs, gs, sLs, sRs, X);
-          d = analysis_at<T, NU>(half + m, half, hs, gs, sLs, sRs, X);
+      T* yr = tmp + i * P + m0;
+      if (m0 >= NU && m0 + CP - 1 < half - NU) {
+        T a[CP], d[CP];
+        analysis_run<T, NU, CP>(xr + 2 * m0 - NU + 1, 1, hr, gr, a, d);
+#pragma unroll
+        for (int p = 0; p < CP; ++p) yr[p] = a[p], yr[half + p] = d[p];
+      } else {
+        auto X = [&](int n) { return xr[n]; };
+        for (int p = 0; p < CP && m0 + p < half; ++p) {
+          yr[p] = analysis_at<T, NU>(m0 + p, half, tl.hs, tl.gs, tl.sLs, tl.sRs, X);
+          yr[half + p] = analysis_at<T, NU>(half + m0 + p, half, tl.hs, tl.gs, tl.sLs, tl.sRs, X);
         }
-        tmp[i * P + m] = a;
-        tmp[i * P + half + m] = d;
       }
     }
     __syncthreads();
-    for (int c = lane; c < 2 * half; c += 64) {  // columns
-      auto X = [&](int n) { return tmp[n * P + c]; };
-      for (int m = wave; m < half; m += 16) {
-        T a, d;
-        if (m >= NU && m < half - NU) {
-          analysis_pair<T, NU>(m, hr, gr, X, a, d);
-        } else {
-          a = analysis_at<T, NU>(m, half, hs, gs, sLs, sRs, X);
-          d = analysis_at<T, NU>(half + m, half, hs, gs, sLs, sRs, X);
+    // columns: work item = (column, run of CP outputs)
+    for (int item = int(threadIdx.x); item < size * runs; item += 1024) {
+      const int c = item % size, m0 = (item / size) * CP;
+      if (m0 >= NU && m0 + CP - 1 < half - NU) {
+        T a[CP], d[CP];
+        analysis_run<T, NU, CP>(tmp + (2 * m0 - NU + 1) * P + c, P, hr, gr, a, d);
+#pragma unroll
+        for (int p = 0; p < CP; ++p) blk[(m0 + p) * P + c] = a[p], blk[(half + m0 + p) * P + c] = d[p];
+      } else {
+        auto X = [&](int n) { return tmp[n * P + c]; };
+        for (int p = 0; p < CP && m0 + p < half; ++p) {
+          blk[(m0 + p) * P + c] = analysis_at<T, NU>(m0 + p, half, tl.hs, tl.gs, tl.sLs, tl.sRs, X);
+          blk[(half + m0 + p) * P + c] = analysis_at<T, NU>(half + m0 + p, half, tl.hs, tl.gs, tl.sLs, tl.sRs, X);
         }
-        blk[m * P + c] = a;
-        blk[(half + m) * P + c] = d;
       }
     }
     __syncthreads();
@@ -537,6 +632,64 @@ __global__ void __launch_bounds__(1024) k_analysis2d_coarse(const T* __restrict_
 template <typename T>
 constexpr int coarse_limit() {
   return sizeof(T) == 4 ? 7 : 6;  // log2 of the largest block kept in LDS
+}
+
+// Largest input window (rows of one half) over the tiles of a level, from
+// the same range functions the kernels use.
+template <int NU>
+int max_synth_window(int half, int ts) {
+  int w = 0;
+  for (int n0 = 0; n0 < 2 * half; n0 += ts) {
+    int lo, hi;
+    synth_input_range<NU>(n0, n0 + ts, half, lo, hi);
+    w = hi - lo + 1 > w ? hi - lo + 1 : w;
+  }
+  return w;
+}
+template <int NU>
+int max_analysis_window(int half, int th) {
+  int w = 0;
+  for (int m0 = 0; m0 < half; m0 += th) {
+    int lo, hi;
+    analysis_input_range<NU>(m0, m0 + th, half, lo, hi);
+    w = hi - lo + 1 > w ? hi - lo + 1 : w;
+  }
+  return w;
+}
+
+// Tile shapes: large tiles with long register runs where a level has enough
+// tiles to fill the chip, small tiles (more workgroups) on coarser levels.
+template <typename T>
+constexpr bool big_tiles(int size) {
+  return sizeof(T) == 4 && size >= 2048;
+}
+
+template <typename T, int NU, int TS, int P>
+hipError_t launch_synth(const T* ll, const T* det, T* dst, int64_t M, int k, int trans, const Tables<T>& t,
+                        hipStream_t st) {
+  const int half = 1 << k, size = 2 * half;
+  if (size % TS) return hipErrorInvalidValue;
+  const int nr = max_synth_window<NU>(half, TS);
+  if (2 * nr > 2 * (TS / 2 + NU + 2)) return hipErrorInvalidValue;  // the kernel's load window
+  const size_t smem = (size_t(2 * nr) * (2 * nr + 1) + size_t(2 * nr) * (TS + 1)) * sizeof(T);
+  const int ntile = size / TS;
+  hipLaunchKernelGGL((k_synth2d_tile<T, NU, TS, P>), dim3(unsigned(ntile * ntile)), dim3(256), smem, st, ll, M, det,
+                     M, dst, M, k, trans, t);
+  return hipGetLastError();
+}
+
+template <typename T, int NU, int TH, int P>
+hipError_t launch_analysis(const T* src, int trans, T* dst, T* x, int64_t M, int k, const Tables<T>& t,
+                           hipStream_t st) {
+  const int half = 1 << k;
+  if (half % TH) return hipErrorInvalidValue;
+  const int nr = max_analysis_window<NU>(half, TH);
+  if (nr > 2 * TH + 2 * NU + 4) return hipErrorInvalidValue;  // the kernel's load window
+  const size_t smem = (size_t(nr) * (nr + 1) + size_t(nr) * (2 * TH + 1)) * sizeof(T);
+  const int ntile = half / TH;
+  hipLaunchKernelGGL((k_analysis2d_tile<T, NU, TH, P>), dim3(unsigned(ntile * ntile)), dim3(256), smem, st, src, M,
+                     trans, dst, M, x, M, k, t);
+  return hipGetLastError();
 }
 
 template <typename T, int NU>
@@ -557,17 +710,14 @@ hipError_t idwt2d_impl(const T* x, T* outT, T* s0, T* s1, int64_t M, int j0, int
     e = hipGetLastError();
     if (e != hipSuccess || last) return e;
   }
-  constexpr int TS = sizeof(T) == 4 ? 64 : 32;
-  const int nrmax = TS / 2 + NU + 2;
-  const size_t smem_t = (size_t(2 * nrmax) * (2 * nrmax + 1) + size_t(2 * nrmax) * (TS + 1)) * sizeof(T);
   const T* ll = coarse ? s0 : x;
   for (int k = kc; k < j; ++k) {
     const bool fin = k == j - 1;
     T* dst = fin ? outT : (ll == s0 ? s1 : s0);
-    const int ntile = (2 << k) / TS;
-    hipLaunchKernelGGL((k_synth2d_tile<T, NU, TS>), dim3(unsigned(ntile * ntile)), dim3(256), smem_t, st, ll, M, x,
-                       M, dst, M, k, fin ? 1 : 0, t);
-    e = hipGetLastError();
+    if (big_tiles<T>(2 << k))
+      e = launch_synth<T, NU, 64, 8>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
+    else
+      e = launch_synth<T, NU, 32, 2>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
     if (e != hipSuccess) return e;
     ll = dst;
   }
@@ -580,19 +730,16 @@ hipError_t dwt2d_impl(const T* inT, T* x, T* s0, T* s1, int64_t M, int j0, int j
   const bool coarse = j0 < coarse_limit<T>();
   const int kc = coarse ? (j < coarse_limit<T>() ? j : coarse_limit<T>()) : j0;
   const int S = 1 << kc;
-  constexpr int TH = sizeof(T) == 4 ? 32 : 16;
-  const int nrmax = 2 * TH + 2 * NU + 4;
-  const size_t smem_t = (size_t(nrmax) * (nrmax + 1) + size_t(nrmax) * (2 * TH + 1)) * sizeof(T);
   hipError_t e = hipSuccess;
   const T* src = inT;
   int trans = 1;
   for (int k = j - 1; k >= kc; --k) {
     // without a coarse stage the last tiled level writes LL_{j0} into x itself
     T* dst = (!coarse && k == kc) ? x : ((src == s0) ? s1 : s0);
-    const int ntile = (1 << k) / TH;
-    hipLaunchKernelGGL((k_analysis2d_tile<T, NU, TH>), dim3(unsigned(ntile * ntile)), dim3(256), smem_t, st, src, M,
-                       trans, dst, M, x, M, k, t);
-    e = hipGetLastError();
+    if (big_tiles<T>(2 << k))
+      e = launch_analysis<T, NU, 32, 8>(src, trans, dst, x, M, k, t, st);
+    else
+      e = launch_analysis<T, NU, 16, 2>(src, trans, dst, x, M, k, t, st);
     if (e != hipSuccess) return e;
     src = dst;
     trans = 0;
@@ -608,18 +755,17 @@ hipError_t dwt2d_impl(const T* inT, T* x, T* s0, T* s1, int64_t M, int j0, int j
 template <typename T, int NU>
 hipError_t prepare_impl() {
   // 160 KB per workgroup, less the static table each kernel keeps in LDS
-  const int lim = 160 * 1024 - int((4 * NU + 2 * (3 * NU - 1) * 2 * NU) * sizeof(T));
-  hipError_t e = hipFuncSetAttribute((const void*)k_synth2d_coarse<T, NU>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_analysis2d_coarse<T, NU>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_synth2d_tile<T, NU, sizeof(T) == 4 ? 64 : 32>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_analysis2d_tile<T, NU, sizeof(T) == 4 ? 32 : 16>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  return e;
+  const int lim = 160 * 1024 - int(tab_lds_size<NU>() * sizeof(T));
+  const void* kernels[] = {
+      (const void*)k_synth2d_coarse<T, NU>,         (const void*)k_analysis2d_coarse<T, NU>,
+      (const void*)k_synth2d_tile<T, NU, 64, 8>,    (const void*)k_synth2d_tile<T, NU, 32, 2>,
+      (const void*)k_analysis2d_tile<T, NU, 32, 8>, (const void*)k_analysis2d_tile<T, NU, 16, 2>,
+  };
+  for (const void* f : kernels) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 #define WH2WAV_DWT_NUS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
