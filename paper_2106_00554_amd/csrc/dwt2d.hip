@@ -222,6 +222,197 @@ __device__ __forceinline__ void analysis_run(const T* __restrict__ px, int strid
   }
 }
 
+// Any run of P synthesis pairs i0 .. i0+P-1, boundary functions included.
+// The line's a(m) is pa[(m - wlo) * stride] and d(m) is pd[(m - wlo) * stride]
+// for m in the window [wlo, whi], which holds every coefficient the run reads.
+// Interior taps see the boundary coefficients as zero; the boundary blocks
+// then add the contributions of the nu left and nu right boundary functions.
+template <typename T, int NU, int P>
+__device__ __forceinline__ void synth_run_edge(const T* __restrict__ pa, const T* __restrict__ pd, int stride, int wlo,
+                                               int whi, int i0, int half, const T (&hr)[2 * NU],
+                                               const T (&gr)[2 * NU], const T* __restrict__ sL,
+                                               const T* __restrict__ sR, T (&e)[P], T (&o)[P]) {
+  constexpr int LO = synth_lo<NU>(), L = P + synth_hi<NU>() - LO, ROWS = 3 * NU - 1;
+  const int size = 2 * half;
+  T a[L], d[L];
+#pragma unroll
+  for (int u = 0; u < L; ++u) {
+    const int m = i0 + LO + u;
+    const bool inside = m >= NU && m <= half - NU - 1;
+    const int mc = (m < wlo ? wlo : (m > whi ? whi : m)) - wlo;
+    const T va = pa[mc * stride], vd = pd[mc * stride];
+    a[u] = inside ? va : T(0);
+    d[u] = inside ? vd : T(0);
+  }
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    T ae = T(0), ao = T(0);
+#pragma unroll
+    for (int c = -NU + 1; c <= NU; ++c) {
+      const int idx = p + synth_off<NU>(c) - LO;
+      if (((c % 2) + 2) % 2 == 0) {
+        ae = fma(a[idx], hr[c + NU - 1], ae);
+        ae = fma(d[idx], gr[c + NU - 1], ae);
+      } else {
+        ao = fma(a[idx], hr[c + NU - 1], ao);
+        ao = fma(d[idx], gr[c + NU - 1], ao);
+      }
+    }
+    e[p] = ae;
+    o[p] = ao;
+  }
+  if (2 * i0 < ROWS) {  // left boundary functions, positions 0 .. nu-1
+    T bl[NU], bd[NU];
+#pragma unroll
+    for (int cc = 0; cc < NU; ++cc) {
+      const int mc = (cc > whi ? whi : cc) - wlo;
+      const T va = pa[mc * stride], vd = pd[mc * stride];
+      bl[cc] = cc < half ? va : T(0);
+      bd[cc] = cc < half ? vd : T(0);
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+#pragma unroll
+      for (int sdx = 0; sdx < 2; ++sdx) {
+        const int n = 2 * (i0 + p) + sdx;
+        if (n < ROWS) {
+          T acc = sdx ? o[p] : e[p];
+#pragma unroll
+          for (int cc = 0; cc < NU; ++cc) {
+            acc = fma(sL[n * 2 * NU + cc], bl[cc], acc);
+            acc = fma(sL[n * 2 * NU + NU + cc], bd[cc], acc);
+          }
+          if (sdx) o[p] = acc; else e[p] = acc;
+        }
+      }
+    }
+  }
+  if (2 * (i0 + P) > size - ROWS) {  // right boundary functions, positions half-1-cc
+    const int right_first = half - NU > NU ? half - NU : NU;
+    T br[NU], bd[NU];
+#pragma unroll
+    for (int cc = 0; cc < NU; ++cc) {
+      const int pos = half - 1 - cc;
+      const int mc = (pos < wlo ? wlo : pos) - wlo;
+      const T va = pa[mc * stride], vd = pd[mc * stride];
+      br[cc] = pos >= right_first ? va : T(0);
+      bd[cc] = pos >= right_first ? vd : T(0);
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+#pragma unroll
+      for (int sdx = 0; sdx < 2; ++sdx) {
+        const int n = 2 * (i0 + p) + sdx;
+        if (n >= size - ROWS && n < size) {
+          const int i = n - (size - ROWS);
+          T acc = sdx ? o[p] : e[p];
+#pragma unroll
+          for (int cc = 0; cc < NU; ++cc) {
+            acc = fma(sR[i * 2 * NU + cc], br[cc], acc);
+            acc = fma(sR[i * 2 * NU + NU + cc], bd[cc], acc);
+          }
+          if (sdx) o[p] = acc; else e[p] = acc;
+        }
+      }
+    }
+  }
+}
+
+// Any run of P analysis outputs m0 .. m0+P-1 (scaling and wavelet coefficient
+// of each), boundary functions included.  x(n) is px[(n - wlo) * stride] for
+// n in the window [wlo, whi].
+template <typename T, int NU, int P>
+__device__ __forceinline__ void analysis_run_edge(const T* __restrict__ px, int stride, int wlo, int whi, int m0,
+                                                  int half, const T (&hr)[2 * NU], const T (&gr)[2 * NU],
+                                                  const T* __restrict__ sL, const T* __restrict__ sR, T (&a)[P],
+                                                  T (&d)[P]) {
+  constexpr int L = 2 * P + 2 * NU - 2, ROWS = 3 * NU - 1;
+  const int size = 2 * half;
+  const int right_first = half - NU > NU ? half - NU : NU;
+  T v[L];
+#pragma unroll
+  for (int u = 0; u < L; ++u) {
+    const int n = 2 * m0 - NU + 1 + u;
+    v[u] = px[((n < wlo ? wlo : (n > whi ? whi : n)) - wlo) * stride];
+  }
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    T sa = T(0), sd = T(0);
+#pragma unroll
+    for (int c = 0; c < 2 * NU; ++c) {
+      sa = fma(hr[c], v[2 * p + c], sa);
+      sd = fma(gr[c], v[2 * p + c], sd);
+    }
+    a[p] = sa;
+    d[p] = sd;
+  }
+  if (m0 < NU) {  // left boundary functions read x(0 .. 3nu-2)
+    T xl[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) xl[r] = px[((r > whi ? whi : r) - wlo) * stride];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int m = m0 + p;
+      if (m < NU) {
+        T sa = T(0), sd = T(0);
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+          sa = fma(sL[r * 2 * NU + m], xl[r], sa);
+          sd = fma(sL[r * 2 * NU + NU + m], xl[r], sd);
+        }
+        a[p] = sa;
+        d[p] = sd;
+      }
+    }
+  }
+  if (m0 + P > right_first) {  // right boundary functions read x(size-3nu+1 .. size-1)
+    T xr[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      const int n = size - ROWS + r;
+      xr[r] = px[((n < wlo ? wlo : n) - wlo) * stride];
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int m = m0 + p;
+      if (m >= right_first && m >= NU && m < half) {
+        const int cc = half - 1 - m;
+        T sa = T(0), sd = T(0);
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+          sa = fma(sR[r * 2 * NU + cc], xr[r], sa);
+          sd = fma(sR[r * 2 * NU + NU + cc], xr[r], sd);
+        }
+        a[p] = sa;
+        d[p] = sd;
+      }
+    }
+  }
+}
+
+// Tile t of an n x n grid: the ring of tiles along the edges (which hold the
+// boundary functions and take longest) is dispatched first.
+__device__ __forceinline__ void tile_of(int t, int n, int& tr, int& tc) {
+  if (n <= 2) {
+    tr = t / n;
+    tc = t % n;
+    return;
+  }
+  const int E = 4 * n - 4;
+  if (t < n) {
+    tr = 0, tc = t;
+  } else if (t < 2 * n) {
+    tr = n - 1, tc = t - n;
+  } else if (t < 3 * n - 2) {
+    tr = t - 2 * n + 1, tc = 0;
+  } else if (t < E) {
+    tr = t - (3 * n - 2) + 1, tc = n - 1;
+  } else {
+    const int r = t - E;
+    tr = 1 + r / (n - 2), tc = 1 + r % (n - 2);
+  }
+}
+
 template <typename T>
 struct TileLds {
   T* hs;
@@ -266,7 +457,9 @@ __global__ void __launch_bounds__(256) k_synth2d_tile(const T* __restrict__ ll, 
   const TileLds<T> tl = load_tables<T, NU>(t, tab_lds, hr, gr);
   const int half = 1 << k, size = 2 * half;
   const int ntile = size / TS;
-  const int r0 = int(blockIdx.x / ntile) * TS, c0 = int(blockIdx.x % ntile) * TS;
+  int tr, tc;
+  tile_of(int(blockIdx.x), ntile, tr, tc);
+  const int r0 = tr * TS, c0 = tc * TS;
   int rlo, rhi, clo, chi;
   synth_input_range<NU>(r0, r0 + TS, half, rlo, rhi);
   synth_input_range<NU>(c0, c0 + TS, half, clo, chi);
@@ -318,12 +511,10 @@ __global__ void __launch_bounds__(256) k_synth2d_tile(const T* __restrict__ ll, 
 #pragma unroll
       for (int p = 0; p < P; ++p) yr[2 * p] = e[p], yr[2 * p + 1] = o[p];
     } else {
-      auto A = [&](int m) { return xr[m - clo]; };
-      auto D = [&](int m) { return xr[nc + m - clo]; };
-      for (int p = 0; p < P; ++p) {
-        yr[2 * p] = synth_at<T, NU>(2 * (i0 + p), half, tl.hs, tl.gs, tl.sLs, tl.sRs, A, D);
-        yr[2 * p + 1] = synth_at<T, NU>(2 * (i0 + p) + 1, half, tl.hs, tl.gs, tl.sLs, tl.sRs, A, D);
-      }
+      T e[P], o[P];
+      synth_run_edge<T, NU, P>(xr, xr + nc, 1, clo, chi, i0, half, hr, gr, tl.sLs, tl.sRs, e, o);
+#pragma unroll
+      for (int p = 0; p < P; ++p) yr[2 * p] = e[p], yr[2 * p + 1] = o[p];
     }
   }
   __syncthreads();
@@ -339,12 +530,10 @@ __global__ void __launch_bounds__(256) k_synth2d_tile(const T* __restrict__ ll, 
 #pragma unroll
       for (int p = 0; p < P; ++p) oc[2 * p * YW] = e[p], oc[(2 * p + 1) * YW] = o[p];
     } else {
-      auto A = [&](int m) { return Ys[(m - rlo) * YW + cc]; };
-      auto D = [&](int m) { return Ys[(nr + m - rlo) * YW + cc]; };
-      for (int p = 0; p < P; ++p) {
-        oc[2 * p * YW] = synth_at<T, NU>(2 * (i0 + p), half, tl.hs, tl.gs, tl.sLs, tl.sRs, A, D);
-        oc[(2 * p + 1) * YW] = synth_at<T, NU>(2 * (i0 + p) + 1, half, tl.hs, tl.gs, tl.sLs, tl.sRs, A, D);
-      }
+      T e[P], o[P];
+      synth_run_edge<T, NU, P>(Ys + cc, Ys + nr * YW + cc, YW, rlo, rhi, i0, half, hr, gr, tl.sLs, tl.sRs, e, o);
+#pragma unroll
+      for (int p = 0; p < P; ++p) oc[2 * p * YW] = e[p], oc[(2 * p + 1) * YW] = o[p];
     }
   }
   __syncthreads();
@@ -371,7 +560,9 @@ __global__ void __launch_bounds__(256) k_analysis2d_tile(const T* __restrict__ i
   const TileLds<T> tl = load_tables<T, NU>(t, tab_lds, hr, gr);
   const int half = 1 << k;
   const int ntile = half / TH;
-  const int a0 = int(blockIdx.x / ntile) * TH, b0 = int(blockIdx.x % ntile) * TH;
+  int tr, tc;
+  tile_of(int(blockIdx.x), ntile, tr, tc);
+  const int a0 = tr * TH, b0 = tc * TH;
   int rlo, rhi, clo, chi;
   analysis_input_range<NU>(a0, a0 + TH, half, rlo, rhi);
   analysis_input_range<NU>(b0, b0 + TH, half, clo, chi);
@@ -425,11 +616,10 @@ __global__ void __launch_bounds__(256) k_analysis2d_tile(const T* __restrict__ i
 #pragma unroll
       for (int p = 0; p < P; ++p) yr[p] = a[p], yr[TH + p] = d[p];
     } else {
-      auto X = [&](int n) { return xr[n - clo]; };
-      for (int p = 0; p < P; ++p) {
-        yr[p] = analysis_at<T, NU>(m0 + p, half, tl.hs, tl.gs, tl.sLs, tl.sRs, X);
-        yr[TH + p] = analysis_at<T, NU>(half + m0 + p, half, tl.hs, tl.gs, tl.sLs, tl.sRs, X);
-      }
+      T a[P], d[P];
+      analysis_run_edge<T, NU, P>(xr, 1, clo, chi, m0, half, hr, gr, tl.sLs, tl.sRs, a, d);
+#pragma unroll
+      for (int p = 0; p < P; ++p) yr[p] = a[p], yr[TH + p] = d[p];
     }
   }
   __syncthreads();
@@ -444,11 +634,10 @@ __global__ void __launch_bounds__(256) k_analysis2d_tile(const T* __restrict__ i
 #pragma unroll
       for (int p = 0; p < P; ++p) Os[(u * P + p) * YW + oc] = a[p], Os[(TH + u * P + p) * YW + oc] = d[p];
     } else {
-      auto X = [&](int n) { return Ys[(n - rlo) * YW + oc]; };
-      for (int p = 0; p < P; ++p) {
-        Os[(u * P + p) * YW + oc] = analysis_at<T, NU>(m0 + p, half, tl.hs, tl.gs, tl.sLs, tl.sRs, X);
-        Os[(TH + u * P + p) * YW + oc] = analysis_at<T, NU>(half + m0 + p, half, tl.hs, tl.gs, tl.sLs, tl.sRs, X);
-      }
+      T a[P], d[P];
+      analysis_run_edge<T, NU, P>(Ys + oc, YW, rlo, rhi, m0, half, hr, gr, tl.sLs, tl.sRs, a, d);
+#pragma unroll
+      for (int p = 0; p < P; ++p) Os[(u * P + p) * YW + oc] = a[p], Os[(TH + u * P + p) * YW + oc] = d[p];
     }
   }
   __syncthreads();
@@ -512,6 +701,11 @@ __global__ void __launch_bounds__(1024) k_synth2d_coarse(const T* __restrict__ x
         synth_run<T, NU, CP>(xr + i0 + LO, xr + half + i0 + LO, 1, hr, gr, e, o);
 #pragma unroll
         for (int p = 0; p < CP; ++p) yr[2 * p] = e[p], yr[2 * p + 1] = o[p];
+      } else if (half >= CP) {
+        T e[CP], o[CP];
+        synth_run_edge<T, NU, CP>(xr, xr + half, 1, 0, half - 1, i0, half, hr, gr, tl.sLs, tl.sRs, e, o);
+#pragma unroll
+        for (int p = 0; p < CP; ++p) yr[2 * p] = e[p], yr[2 * p + 1] = o[p];
       } else {
         auto A = [&](int m) { return xr[m]; };
         auto D = [&](int m) { return xr[half + m]; };
@@ -529,6 +723,11 @@ __global__ void __launch_bounds__(1024) k_synth2d_coarse(const T* __restrict__ x
       if (pair_is_interior<NU>(i0, half) && pair_is_interior<NU>(i0 + CP - 1, half)) {
         T e[CP], o[CP];
         synth_run<T, NU, CP>(tmp + (i0 + LO) * P + c, tmp + (half + i0 + LO) * P + c, P, hr, gr, e, o);
+#pragma unroll
+        for (int p = 0; p < CP; ++p) oc[2 * p * P] = e[p], oc[(2 * p + 1) * P] = o[p];
+      } else if (half >= CP) {
+        T e[CP], o[CP];
+        synth_run_edge<T, NU, CP>(tmp + c, tmp + half * P + c, P, 0, half - 1, i0, half, hr, gr, tl.sLs, tl.sRs, e, o);
 #pragma unroll
         for (int p = 0; p < CP; ++p) oc[2 * p * P] = e[p], oc[(2 * p + 1) * P] = o[p];
       } else {
@@ -598,6 +797,11 @@ __global__ void __launch_bounds__(1024) k_analysis2d_coarse(const T* __restrict_
         analysis_run<T, NU, CP>(xr + 2 * m0 - NU + 1, 1, hr, gr, a, d);
 #pragma unroll
         for (int p = 0; p < CP; ++p) yr[p] = a[p], yr[half + p] = d[p];
+      } else if (half >= CP) {
+        T a[CP], d[CP];
+        analysis_run_edge<T, NU, CP>(xr, 1, 0, size - 1, m0, half, hr, gr, tl.sLs, tl.sRs, a, d);
+#pragma unroll
+        for (int p = 0; p < CP; ++p) yr[p] = a[p], yr[half + p] = d[p];
       } else {
         auto X = [&](int n) { return xr[n]; };
         for (int p = 0; p < CP && m0 + p < half; ++p) {
@@ -613,6 +817,11 @@ __global__ void __launch_bounds__(1024) k_analysis2d_coarse(const T* __restrict_
       if (m0 >= NU && m0 + CP - 1 < half - NU) {
         T a[CP], d[CP];
         analysis_run<T, NU, CP>(tmp + (2 * m0 - NU + 1) * P + c, P, hr, gr, a, d);
+#pragma unroll
+        for (int p = 0; p < CP; ++p) blk[(m0 + p) * P + c] = a[p], blk[(half + m0 + p) * P + c] = d[p];
+      } else if (half >= CP) {
+        T a[CP], d[CP];
+        analysis_run_edge<T, NU, CP>(tmp + c, P, 0, size - 1, m0, half, hr, gr, tl.sLs, tl.sRs, a, d);
 #pragma unroll
         for (int p = 0; p < CP; ++p) blk[(m0 + p) * P + c] = a[p], blk[(half + m0 + p) * P + c] = d[p];
       } else {
