@@ -21,14 +21,13 @@ struct Tables {
 };
 
 struct Omega {
-  const uint32_t* mask;    // N rows of wpr words; NULL when every sample is taken
-  const int64_t* row_ptr;  // N + 1 offsets into y
-  int64_t wpr;             // words per row (N / 32)
-  int full;
+  const uint16_t* pos;     // natural position of every sample in its phase line (m entries)
+  const int64_t* seg_ptr;  // N Q + 1 offsets into y, one per (row, phase)
+  int full;                // every sample taken: y is the whole N x N array
 };
 
-// True when the wave kernels cover (element size, log2 M, nu).
-bool supported(int elem_bytes, int logm, int nu);
+// True when the wave kernels cover (element size, log2 M, nu, q).
+bool supported(int elem_bytes, int logm, int nu, int q);
 
 // Forward row pass: rows r of Z (N x M, natural row order) -> y (gather on Omega).
 template <typename T>

@@ -66,21 +66,6 @@ __device__ __forceinline__ double read_lane(double v, int l) {
   return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
-__device__ __forceinline__ int wave_sum(int x) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
-  return x;
-}
-__device__ __forceinline__ int wave_exclusive_scan(int x, int lane) {
-  int inc = x;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int t = __shfl_up(inc, d);
-    if (lane >= d) inc += t;
-  }
-  return inc - x;
-}
-
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -232,8 +217,10 @@ __device__ __forceinline__ void line_forward(const T (&xi)[R], T (&v)[R], int s,
   for (int m = 0; m < NU; ++m) {
     eL[m] = read_lane(xi[m], 0);
     eR[m] = read_lane(xi[R - 1 - m], 63);
-    if (lane == 0) x[m] = T(0);
-    if (lane == 63) x[R - 1 - m] = T(0);
+    // per-element selects (conditional stores would let the compiler merge
+    // them into one dynamically indexed store and move x to scratch)
+    x[m] = lane == 0 ? T(0) : x[m];
+    x[R - 1 - m] = lane == 63 ? T(0) : x[R - 1 - m];
   }
   T tap[2 * NU - 1];
 #pragma unroll
@@ -251,8 +238,8 @@ __device__ __forceinline__ void line_forward(const T (&xi)[R], T (&v)[R], int s,
 #pragma unroll
   for (int e = 0; e < B; ++e) {
     const T a = read_lane(bv, e), b = read_lane(bv, B + e);
-    if (lane == 0) v[e] += a;
-    if (lane == 63) v[R - B + e] += b;
+    v[e] += lane == 0 ? a : T(0);
+    v[R - B + e] += lane == 63 ? b : T(0);
   }
   fwht_wave<T, R>(v, lane);
 }
@@ -293,8 +280,8 @@ __device__ __forceinline__ void place_edges(T (&acc)[R], T eacc, int lane) {
 #pragma unroll
   for (int m = 0; m < NU; ++m) {
     const T a = read_lane(eacc, m), b = read_lane(eacc, NU + m);
-    if (lane == 0) acc[m] = a;
-    if (lane == 63) acc[R - 1 - m] = b;
+    acc[m] = lane == 0 ? a : acc[m];
+    acc[R - 1 - m] = lane == 63 ? b : acc[R - 1 - m];
   }
 }
 
@@ -305,7 +292,7 @@ __device__ __forceinline__ int buf_addr(int k, int log_r) {
 
 // ------------------------------------------------------------- row passes
 template <typename T, int LOGM, int NU>
-__global__ void __launch_bounds__(256) k_rowpass_fwd(const T* __restrict__ Z, T* __restrict__ y, Tables<T> t,
+__global__ void __launch_bounds__(1024) k_rowpass_fwd(const T* __restrict__ Z, T* __restrict__ y, Tables<T> t,
                                                      Omega om) {
   constexpr int M = 1 << LOGM, LOG_R = LOGM - 6, R = 1 << LOG_R;
   constexpr int BUF = M + 4 * (M >> LOG_R);
@@ -315,18 +302,14 @@ __global__ void __launch_bounds__(256) k_rowpass_fwd(const T* __restrict__ Z, T*
   const int nw = int(blockDim.x) >> 6;
   const int Q = t.Q;
   T* buf = reinterpret_cast<T*>(smem_raw) + wave * BUF;
-  uint32_t* mrow = reinterpret_cast<uint32_t*>(reinterpret_cast<T*>(smem_raw) + nw * BUF);
   const int64_t r = blockIdx.x;
   T xi[R];
   load_line<T, R>(Z + r * M + lane * R, xi);
   const uint32_t s1 = uint32_t(r >> LOGM), k1 = uint32_t(r & (M - 1));
   const int64_t n1 = int64_t(s1) * M + sequency_of(k1, s1, LOGM);
   const int64_t N = int64_t(M) * Q;
-  if (!om.full) {
-    for (int w = int(threadIdx.x); w < int(om.wpr); w += int(blockDim.x)) mrow[w] = om.mask[n1 * om.wpr + w];
-    __syncthreads();
-  }
-  for (int s = wave; s < Q; s += nw) {
+  {  // one wave per phase: the workgroup has Q waves
+    const int s = wave;
     T v[R];
     line_forward<T, R, NU>(xi, v, s, t, lane);
     store_line<T, R>(buf + lane * (R + 4), v);
@@ -338,29 +321,22 @@ __global__ void __launch_bounds__(256) k_rowpass_fwd(const T* __restrict__ Z, T*
         yrow[b] = buf[buf_addr<R>(int(k), LOG_R)];
       }
     } else {
-      constexpr int WPP = M / 32, WPL = (WPP + 63) / 64;
-      int before = 0;
-      for (int w = lane; w < s * WPP; w += 64) before += __popc(mrow[w]);
-      before = wave_sum(before);
-      uint32_t wv[WPL];
-      int cnt = 0;
+      // the samples of this phase line are y[o .. o + cnt), in sequency order;
+      // pos holds each one's natural position (coalesced reads and writes)
+      const int64_t o = om.seg_ptr[n1 * Q + s];
+      const int cnt = int(om.seg_ptr[n1 * Q + s + 1] - o);
+      const uint16_t* __restrict__ ps = om.pos + o;
+      T* __restrict__ ys = y + o;
+      for (int t0 = 0; t0 < cnt; t0 += 256) {
+        int kk[4];
 #pragma unroll
-      for (int i = 0; i < WPL; ++i) {
-        const int w = lane * WPL + i;
-        wv[i] = w < WPP ? mrow[s * WPP + w] : 0u;
-        cnt += __popc(wv[i]);
-      }
-      int64_t o = om.row_ptr[n1] + before + wave_exclusive_scan(cnt, lane);
-#pragma unroll
-      for (int i = 0; i < WPL; ++i) {
-        uint32_t bits = wv[i];
-        const uint32_t wb = uint32_t(lane * WPL + i) * 32u;
-        while (bits) {
-          const int bit = __ffs(bits) - 1;
-          bits &= bits - 1;
-          const uint32_t k = natural_of(wb + uint32_t(bit), uint32_t(s), LOGM);
-          y[o++] = buf[buf_addr<R>(int(k), LOG_R)];
+        for (int u = 0; u < 4; ++u) {
+          const int tt = t0 + lane + 64 * u;
+          kk[u] = tt < cnt ? int(ps[tt]) : -1;
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (kk[u] >= 0) ys[t0 + lane + 64 * u] = buf[buf_addr<R>(kk[u], LOG_R)];
       }
     }
     wave_sync();
@@ -368,7 +344,7 @@ __global__ void __launch_bounds__(256) k_rowpass_fwd(const T* __restrict__ Z, T*
 }
 
 template <typename T, int LOGM, int NU>
-__global__ void __launch_bounds__(256) k_rowpass_adj(const T* __restrict__ y, T* __restrict__ Zt, Tables<T> t,
+__global__ void __launch_bounds__(1024) k_rowpass_adj(const T* __restrict__ y, T* __restrict__ Zt, Tables<T> t,
                                                      Omega om) {
   constexpr int M = 1 << LOGM, LOG_R = LOGM - 6, R = 1 << LOG_R;
   constexpr int BUF = M + 4 * (M >> LOG_R);
@@ -379,20 +355,16 @@ __global__ void __launch_bounds__(256) k_rowpass_adj(const T* __restrict__ y, T*
   const int Q = t.Q;
   T* bufs = reinterpret_cast<T*>(smem_raw);
   T* buf = bufs + wave * BUF;
-  uint32_t* mrow = reinterpret_cast<uint32_t*>(bufs + nw * BUF);
   const int64_t r = blockIdx.x;
   const uint32_t s1 = uint32_t(r >> LOGM), k1 = uint32_t(r & (M - 1));
   const int64_t n1 = int64_t(s1) * M + sequency_of(k1, s1, LOGM);
   const int64_t N = int64_t(M) * Q;
-  if (!om.full) {
-    for (int w = int(threadIdx.x); w < int(om.wpr); w += int(blockDim.x)) mrow[w] = om.mask[n1 * om.wpr + w];
-    __syncthreads();
-  }
   T acc[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) acc[i] = T(0);
   T eacc = T(0);
-  for (int s = wave; s < Q; s += nw) {
+  {  // one wave per phase: the workgroup has Q waves
+    const int s = wave;
     T v[R];
     if (om.full) {
       const T* yrow = y + n1 * N + int64_t(s) * M;
@@ -409,47 +381,24 @@ __global__ void __launch_bounds__(256) k_rowpass_adj(const T* __restrict__ y, T*
 #pragma unroll
       for (int i = 0; i < R; ++i) v[i] = T(0);
       store_line<T, R>(buf + lane * (R + 4), v);
-      constexpr int WPP = M / 32, WPL = (WPP + 63) / 64;
-      int before = 0;
-      for (int w = lane; w < s * WPP; w += 64) before += __popc(mrow[w]);
-      before = wave_sum(before);
-      uint32_t wv[WPL];
-      int cnt = 0;
-#pragma unroll
-      for (int i = 0; i < WPL; ++i) {
-        const int w = lane * WPL + i;
-        wv[i] = w < WPP ? mrow[s * WPP + w] : 0u;
-        cnt += __popc(wv[i]);
-      }
-      const int64_t o0 = om.row_ptr[n1] + before + wave_exclusive_scan(cnt, lane);
+      const int64_t o = om.seg_ptr[n1 * Q + s];
+      const int cnt = int(om.seg_ptr[n1 * Q + s + 1] - o);
+      const uint16_t* __restrict__ ps = om.pos + o;
+      const T* __restrict__ ys = y + o;
       wave_sync();  // zero fill of buf before the scatter
-      // scatter in batches of 8 samples per lane: loads issued before the stores
-      int o = 0;
+      // coalesced reads of this phase line's samples and their positions
+      for (int t0 = 0; t0 < cnt; t0 += 256) {
+        int kk[4];
+        T rv[4];
 #pragma unroll
-      for (int i = 0; i < WPL; ++i) {
-        uint32_t bits = wv[i];
-        const uint32_t wb = uint32_t(lane * WPL + i) * 32u;
-        while (bits) {
-          T rv[8];
-          int kk[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            kk[u] = -1;
-            if (bits) {
-              const int bit = __ffs(bits) - 1;
-              bits &= bits - 1;
-              kk[u] = int(natural_of(wb + uint32_t(bit), uint32_t(s), LOGM));
-              rv[u] = y[o0 + o + u];
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            if (kk[u] >= 0) {
-              buf[buf_addr<R>(kk[u], LOG_R)] = rv[u];
-              ++o;
-            }
-          }
+        for (int u = 0; u < 4; ++u) {
+          const int tt = t0 + lane + 64 * u;
+          kk[u] = tt < cnt ? int(ps[tt]) : -1;
+          rv[u] = tt < cnt ? ys[tt] : T(0);
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (kk[u] >= 0) buf[buf_addr<R>(kk[u], LOG_R)] = rv[u];
       }
     }
     wave_sync();
@@ -578,8 +527,8 @@ __global__ void __launch_bounds__(256) k_transpose(const T* __restrict__ in, T* 
 template <typename T, int LOGM, int NU>
 hipError_t launch_rowpass_fwd(const T* Z, T* y, const Tables<T>& t, const Omega& om, hipStream_t st) {
   constexpr int M = 1 << LOGM, R = M / 64;
-  const int nw = t.Q < 4 ? t.Q : 4;
-  const size_t smem = size_t(nw) * (M + 4 * (M / R)) * sizeof(T) + size_t(om.wpr) * sizeof(uint32_t);
+  const int nw = t.Q;  // one wave per phase
+  const size_t smem = size_t(nw) * (M + 4 * (M / R)) * sizeof(T);
   const int64_t rows = int64_t(M) * t.Q;
   hipLaunchKernelGGL((k_rowpass_fwd<T, LOGM, NU>), dim3(unsigned(rows)), dim3(64 * nw), smem, st, Z, y, t, om);
   return hipGetLastError();
@@ -587,8 +536,8 @@ hipError_t launch_rowpass_fwd(const T* Z, T* y, const Tables<T>& t, const Omega&
 template <typename T, int LOGM, int NU>
 hipError_t launch_rowpass_adj(const T* y, T* Zt, const Tables<T>& t, const Omega& om, hipStream_t st) {
   constexpr int M = 1 << LOGM, R = M / 64;
-  const int nw = t.Q < 4 ? t.Q : 4;
-  const size_t smem = size_t(nw) * (M + 4 * (M / R)) * sizeof(T) + size_t(om.wpr) * sizeof(uint32_t);
+  const int nw = t.Q;  // one wave per phase
+  const size_t smem = size_t(nw) * (M + 4 * (M / R)) * sizeof(T);
   const int64_t rows = int64_t(M) * t.Q;
   hipLaunchKernelGGL((k_rowpass_adj<T, LOGM, NU>), dim3(unsigned(rows)), dim3(64 * nw), smem, st, y, Zt, t, om);
   return hipGetLastError();
@@ -616,8 +565,10 @@ hipError_t launch_colpass_adj(const T* Zt, T* xiT, const Tables<T>& t, hipStream
 
 }  // namespace
 
-bool supported(int elem_bytes, int logm, int nu) {
-  (void)elem_bytes;
+bool supported(int elem_bytes, int logm, int nu, int q) {
+  // row passes: one wave (and one LDS line buffer) per phase
+  const long long phases = 1LL << q, m = 1LL << logm;
+  if (q > 4 || phases * (m + 4 * 64) * elem_bytes > 160 * 1024) return false;
 #define X(L, V) if (logm == L && nu == V) return true;
   WH2WAV_FAST_CASES(X)
 #undef X

@@ -701,6 +701,24 @@ int build_host_plan(const wh2wav_desc* d, HostPlan* P, std::string* err) {
     for (int64_t r = 0; r < P->rows; ++r) P->row_ptr[r + 1] = P->N;
   }
   for (int64_t r = 0; r < P->rows; ++r) P->row_ptr[r + 1] += P->row_ptr[r];
+  P->pos16.clear();
+  P->seg_ptr.clear();
+  if (d->dim == 2 && !P->full_omega && P->M <= 65536) {
+    const int64_t Q = P->Q, M = P->M;
+    P->seg_ptr.assign((size_t)(P->N * Q + 1), 0);
+    P->pos16.resize((size_t)d->m);
+    for (int64_t i = 0; i < d->m; ++i) {
+      const int64_t v = d->omega[i];
+      const int64_t n1 = v / P->N, n2 = v % P->N;
+      const int64_t s = n2 / M, b = n2 % M;
+      P->seg_ptr[(size_t)(n1 * Q + s + 1)]++;
+      const uint64_t g = (uint64_t)(b ^ (b >> 1));
+      uint64_t k = 0;
+      for (int bit = 0; bit < d->j; ++bit) k |= ((g >> bit) & 1u) << (d->j - 1 - bit);
+      P->pos16[(size_t)i] = (uint16_t)(k ^ (uint64_t)(s & 1));
+    }
+    for (size_t e = 1; e < P->seg_ptr.size(); ++e) P->seg_ptr[e] += P->seg_ptr[e - 1];
+  }
   return WH2WAV_OK;
 }
 

@@ -48,6 +48,13 @@ struct HostPlan {
   int64_t words_per_row = 0; // ceil(N / 32)
   std::vector<uint32_t> mask;        // rows * words_per_row
   std::vector<int64_t> row_ptr;      // rows + 1
+  // 2D sample list for the line kernels (only when Omega is not full).  A
+  // row n1 of the N x N Walsh array splits into Q phase lines n2 = s M + b;
+  // seg_ptr[n1 * Q + s] is the offset in y of the first sample of that phase
+  // line (N Q + 1 entries) and pos16[i] the natural-order position
+  // k = bitrev(gray(b)) xor (s & 1) of sample i within its phase line.
+  std::vector<uint16_t> pos16;
+  std::vector<int64_t> seg_ptr;
 };
 
 // Validates the descriptor and fills the plan.  Returns a WH2WAV_* status;

@@ -399,6 +399,8 @@ struct wh2wav_plan_s {
   void* d_tables = nullptr;   // element type = dtype
   uint32_t* d_mask = nullptr;
   int64_t* d_row_ptr = nullptr;
+  uint16_t* d_pos16 = nullptr;
+  int64_t* d_seg_ptr = nullptr;
   size_t off_h = 0, off_g = 0, off_T = 0, off_BL = 0, off_BR = 0, off_SL = 0, off_SR = 0;
 };
 
@@ -432,16 +434,15 @@ wh2wav_fast::Tables<T> fast_tables_of(const wh2wav_plan_s* p) {
 
 wh2wav_fast::Omega fast_omega_of(const wh2wav_plan_s* p) {
   wh2wav_fast::Omega o;
-  o.mask = p->d_mask;
-  o.row_ptr = p->d_row_ptr;
-  o.wpr = p->host.words_per_row;
+  o.pos = p->d_pos16;
+  o.seg_ptr = p->d_seg_ptr;
   o.full = p->host.full_omega ? 1 : 0;
   return o;
 }
 
 bool use_fast(const wh2wav_plan_s* p) {
   const auto& H = p->host;
-  return H.dim == 2 && wh2wav_fast::supported(H.dtype == WH2WAV_F64 ? 8 : 4, H.j, H.nu);
+  return H.dim == 2 && wh2wav_fast::supported(H.dtype == WH2WAV_F64 ? 8 : 4, H.j, H.nu, H.q);
 }
 
 OmegaDev omega_of(const wh2wav_plan_s* p) {
@@ -655,6 +656,8 @@ void release(wh2wav_plan_s* p) {
   if (!p) return;
   if (p->d_tables) (void)hipFree(p->d_tables);
   if (p->d_mask) (void)hipFree(p->d_mask);
+  if (p->d_pos16) (void)hipFree(p->d_pos16);
+  if (p->d_seg_ptr) (void)hipFree(p->d_seg_ptr);
   if (p->d_row_ptr) (void)hipFree(p->d_row_ptr);
   delete p;
 }
@@ -718,6 +721,8 @@ int wh2wav_plan(const wh2wav_desc* desc, wh2wav_plan_t* out) {
   };
   rc = upload((void**)&p->d_row_ptr, H.row_ptr.data(), sizeof(int64_t) * H.row_ptr.size());
   if (rc == WH2WAV_OK) rc = upload((void**)&p->d_mask, H.mask.data(), sizeof(uint32_t) * H.mask.size());
+  if (rc == WH2WAV_OK) rc = upload((void**)&p->d_pos16, H.pos16.data(), sizeof(uint16_t) * H.pos16.size());
+  if (rc == WH2WAV_OK) rc = upload((void**)&p->d_seg_ptr, H.seg_ptr.data(), sizeof(int64_t) * H.seg_ptr.size());
   if (rc != WH2WAV_OK) {
     std::string m = g_last_error;
     release(p);
