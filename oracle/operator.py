@@ -213,3 +213,32 @@ def adjoint_entries_2d(cfg, y, omega, positions):
         a2 = walsh_column(cfg, *f2)
         out.append(np.dot(a1[n1] * a2[n2], y))
     return np.array(out)
+
+
+def forward_entries_1d(cfg, x, ns, C=None):
+    """y_n = sum_c A[n, c] x_c for each n in ns, as sum_i w_n(i/N) f[i] with f = C x
+    the cell integrals of the function sum_c x_c r_c (plain sums, no fast transform)."""
+    C = basis.multiscale(cfg.nu, cfg.j, cfg.j0, cfg.J) if C is None else C
+    f = C @ np.asarray(x, dtype=np.float64)
+    ns = np.asarray(ns)
+    out = np.empty(ns.size)
+    step = 64
+    for a in range(0, ns.size, step):
+        H = walsh.walsh_matrix_bits(cfg.J, rows=ns[a:a + step], cols=np.arange(cfg.N))
+        out[a:a + step] = H @ f
+    return out
+
+
+def adjoint_entries_1d(cfg, y, omega, cs, C=None):
+    """(A[omega]^T y)_c for each position c in cs: the column of one basis function
+    restricted to omega, against y (plain sums)."""
+    C = basis.multiscale(cfg.nu, cfg.j, cfg.j0, cfg.J) if C is None else C
+    omega = np.arange(cfg.N) if omega is None else np.asarray(omega)
+    out = []
+    for c in cs:
+        col = C[:, int(c)]
+        cells = col.indices
+        H = walsh.walsh_matrix_bits(cfg.J, rows=omega, cols=cells)
+        out.append(np.dot(H @ col.data, y))
+    return np.array(out)
+

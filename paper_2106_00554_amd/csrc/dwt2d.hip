@@ -13,382 +13,13 @@
 //   * The last synthesis level writes xi^T (the layout the column pass reads);
 //     the first analysis level reads xi'^T (the layout the adjoint column pass
 //     writes) and stores the detail bands straight into x.
-#include "fast2d.h"
+#include "dwt_lines.h"
 
 namespace wh2wav_fast {
 namespace {
 
-// Synthesis of output n of one line: a(m) = A(m), d(m) = D(m), m < half.
-template <typename T, int NU, class FA, class FD>
-__device__ __forceinline__ T synth_at(int n, int half, const T* __restrict__ h, const T* __restrict__ g,
-                                      const T* __restrict__ synL, const T* __restrict__ synR, FA A, FD D) {
-  constexpr int ROWS = 3 * NU - 1;
-  const int size = 2 * half;
-  const int right_first = half - NU > NU ? half - NU : NU;
-  T acc = T(0);
-  int mlo = n - NU + 1 > 0 ? (n - NU + 1) >> 1 : 0;
-  if (mlo < NU) mlo = NU;
-  int mhi = (n + NU - 1) >> 1;
-  if (mhi > half - NU - 1) mhi = half - NU - 1;
-  for (int m = mlo; m <= mhi; ++m) {
-    const int c = n - 2 * m + NU - 1;
-    acc = fma(A(m), h[c], acc);
-    acc = fma(D(m), g[c], acc);
-  }
-  if (n < ROWS) {
-#pragma unroll
-    for (int cc = 0; cc < NU; ++cc) {
-      if (cc >= half) break;
-      acc = fma(synL[n * 2 * NU + cc], A(cc), acc);
-      acc = fma(synL[n * 2 * NU + NU + cc], D(cc), acc);
-    }
-  }
-  if (n >= size - ROWS) {
-    const int i = n - (size - ROWS);
-#pragma unroll
-    for (int cc = 0; cc < NU; ++cc) {
-      const int pos = half - 1 - cc;
-      if (pos < right_first) continue;
-      acc = fma(synR[i * 2 * NU + cc], A(pos), acc);
-      acc = fma(synR[i * 2 * NU + NU + cc], D(pos), acc);
-    }
-  }
-  return acc;
-}
+using namespace lines;
 
-// Analysis output o of one line (o < half: scaling coefficient, else wavelet).
-template <typename T, int NU, class FX>
-__device__ __forceinline__ T analysis_at(int o, int half, const T* __restrict__ h, const T* __restrict__ g,
-                                         const T* __restrict__ synL, const T* __restrict__ synR, FX X) {
-  constexpr int ROWS = 3 * NU - 1;
-  const int size = 2 * half;
-  const int kind = o >= half ? 1 : 0;
-  const int m = o - kind * half;
-  const int right_first = half - NU > NU ? half - NU : NU;
-  T acc = T(0);
-  if (m >= NU && m < right_first) {
-    const T* taps = kind ? g : h;
-#pragma unroll
-    for (int c = 0; c < 2 * NU; ++c) acc = fma(taps[c], X(2 * m + c - NU + 1), acc);
-  } else if (m < NU) {
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) acc = fma(synL[r * 2 * NU + kind * NU + m], X(r), acc);
-  } else {
-    const int cc = half - 1 - m;
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) acc = fma(synR[r * 2 * NU + kind * NU + cc], X(size - ROWS + r), acc);
-  }
-  return acc;
-}
-
-// Index range of a-part (or d-part) inputs m that synthesis outputs
-// [n0, n1) read, boundary columns included.
-template <int NU>
-__host__ __device__ __forceinline__ void synth_input_range(int n0, int n1, int half, int& lo, int& hi) {
-  constexpr int ROWS = 3 * NU - 1;
-  lo = n0 - NU > 0 ? (n0 - NU) >> 1 : 0;
-  hi = (n1 - 1 + NU) >> 1;
-  if (hi > half - 1) hi = half - 1;
-  if (n0 < ROWS) lo = 0;
-  if (n1 > 2 * half - ROWS) hi = half - 1;
-}
-
-// Index range of inputs n that analysis outputs m in [m0, m1) (of either half) read.
-template <int NU>
-__host__ __device__ __forceinline__ void analysis_input_range(int m0, int m1, int half, int& lo, int& hi) {
-  constexpr int ROWS = 3 * NU - 1;
-  const int size = 2 * half;
-  lo = 2 * m0 - NU + 1;
-  hi = 2 * (m1 - 1) + NU;
-  if (lo < 0) lo = 0;
-  if (hi > size - 1) hi = size - 1;
-  if (m0 < NU) lo = 0;
-  if (m1 > half - NU) hi = size - 1;
-  (void)ROWS;
-}
-
-// Interior synthesis pair: outputs 2i and 2i+1 when every filter tap lands on
-// an interior coefficient (3nu-1 <= 2i and 2i+1 <= size-3nu).  With
-// c = n - 2m in [-nu+1, nu]: even n uses the even taps, odd n the odd taps.
-template <typename T, int NU, class FA, class FD>
-__device__ __forceinline__ void synth_pair(int i, const T* __restrict__ h, const T* __restrict__ g, FA A, FD D,
-                                           T& e, T& o) {
-  T ae = T(0), ao = T(0);
-#pragma unroll
-  for (int c = -NU + 1; c <= NU; ++c) {
-    if (((c % 2) + 2) % 2 == 0) {
-      const int m = i - c / 2;
-      ae = fma(A(m), h[c + NU - 1], ae);
-      ae = fma(D(m), g[c + NU - 1], ae);
-    } else {
-      const int m = i - (c - 1) / 2;  // c - 1 is even: exact
-      ao = fma(A(m), h[c + NU - 1], ao);
-      ao = fma(D(m), g[c + NU - 1], ao);
-    }
-  }
-  e = ae;
-  o = ao;
-}
-
-template <int NU>
-__device__ __forceinline__ bool pair_is_interior(int i, int half) {
-  return 2 * i >= 3 * NU - 1 && 2 * i + 1 <= 2 * half - 3 * NU;
-}
-
-// Analysis pair (a[m], d[m]) for an interior m (nu <= m < half - nu).
-template <typename T, int NU, class FX>
-__device__ __forceinline__ void analysis_pair(int m, const T* __restrict__ h, const T* __restrict__ g, FX X, T& a,
-                                              T& d) {
-  T sa = T(0), sd = T(0);
-#pragma unroll
-  for (int c = 0; c < 2 * NU; ++c) {
-    const T v = X(2 * m + c - NU + 1);
-    sa = fma(h[c], v, sa);
-    sd = fma(g[c], v, sd);
-  }
-  a = sa;
-  d = sd;
-}
-
-// Offsets m - i of the inputs that interior synthesis pair i reads.
-template <int NU>
-__host__ __device__ constexpr int synth_off(int c) {
-  return (((c % 2) + 2) % 2 == 0) ? -c / 2 : -(c - 1) / 2;
-}
-template <int NU>
-__host__ __device__ constexpr int synth_lo() {
-  int v = 0;
-  for (int c = -NU + 1; c <= NU; ++c) v = synth_off<NU>(c) < v ? synth_off<NU>(c) : v;
-  return v;
-}
-template <int NU>
-__host__ __device__ constexpr int synth_hi() {
-  int v = 0;
-  for (int c = -NU + 1; c <= NU; ++c) v = synth_off<NU>(c) > v ? synth_off<NU>(c) : v;
-  return v;
-}
-
-// P consecutive interior synthesis pairs i0 .. i0+P-1 of one line.  pa points
-// at a(i0 + lo), pd at d(i0 + lo); consecutive m are `stride` elements apart.
-// Inputs are read once into registers and reused by every tap.
-template <typename T, int NU, int P>
-__device__ __forceinline__ void synth_run(const T* __restrict__ pa, const T* __restrict__ pd, int stride,
-                                          const T (&hr)[2 * NU], const T (&gr)[2 * NU], T (&e)[P], T (&o)[P]) {
-  constexpr int LO = synth_lo<NU>(), L = P + synth_hi<NU>() - LO;
-  T a[L], d[L];
-#pragma unroll
-  for (int u = 0; u < L; ++u) {
-    a[u] = pa[u * stride];
-    d[u] = pd[u * stride];
-  }
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
-    T ae = T(0), ao = T(0);
-#pragma unroll
-    for (int c = -NU + 1; c <= NU; ++c) {
-      const int idx = p + synth_off<NU>(c) - LO;
-      if (((c % 2) + 2) % 2 == 0) {
-        ae = fma(a[idx], hr[c + NU - 1], ae);
-        ae = fma(d[idx], gr[c + NU - 1], ae);
-      } else {
-        ao = fma(a[idx], hr[c + NU - 1], ao);
-        ao = fma(d[idx], gr[c + NU - 1], ao);
-      }
-    }
-    e[p] = ae;
-    o[p] = ao;
-  }
-}
-
-// P consecutive interior analysis outputs m0 .. m0+P-1 (scaling and wavelet
-// coefficient of each); px points at x(2 m0 - nu + 1).
-template <typename T, int NU, int P>
-__device__ __forceinline__ void analysis_run(const T* __restrict__ px, int stride, const T (&hr)[2 * NU],
-                                             const T (&gr)[2 * NU], T (&a)[P], T (&d)[P]) {
-  constexpr int L = 2 * P + 2 * NU - 2;
-  T v[L];
-#pragma unroll
-  for (int u = 0; u < L; ++u) v[u] = px[u * stride];
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
-    T sa = T(0), sd = T(0);
-#pragma unroll
-    for (int c = 0; c < 2 * NU; ++c) {
-      sa = fma(hr[c], v[2 * p + c], sa);
-      sd = fma(gr[c], v[2 * p + c], sd);
-    }
-    a[p] = sa;
-    d[p] = sd;
-  }
-}
-
-// Any run of P synthesis pairs i0 .. i0+P-1, boundary functions included.
-// The line's a(m) is pa[(m - wlo) * stride] and d(m) is pd[(m - wlo) * stride]
-// for m in the window [wlo, whi], which holds every coefficient the run reads.
-// Interior taps see the boundary coefficients as zero; the boundary blocks
-// then add the contributions of the nu left and nu right boundary functions.
-template <typename T, int NU, int P>
-__device__ __forceinline__ void synth_run_edge(const T* __restrict__ pa, const T* __restrict__ pd, int stride, int wlo,
-                                               int whi, int i0, int half, const T (&hr)[2 * NU],
-                                               const T (&gr)[2 * NU], const T* __restrict__ sL,
-                                               const T* __restrict__ sR, T (&e)[P], T (&o)[P]) {
-  constexpr int LO = synth_lo<NU>(), L = P + synth_hi<NU>() - LO, ROWS = 3 * NU - 1;
-  const int size = 2 * half;
-  T a[L], d[L];
-#pragma unroll
-  for (int u = 0; u < L; ++u) {
-    const int m = i0 + LO + u;
-    const bool inside = m >= NU && m <= half - NU - 1;
-    const int mc = (m < wlo ? wlo : (m > whi ? whi : m)) - wlo;
-    const T va = pa[mc * stride], vd = pd[mc * stride];
-    a[u] = inside ? va : T(0);
-    d[u] = inside ? vd : T(0);
-  }
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
-    T ae = T(0), ao = T(0);
-#pragma unroll
-    for (int c = -NU + 1; c <= NU; ++c) {
-      const int idx = p + synth_off<NU>(c) - LO;
-      if (((c % 2) + 2) % 2 == 0) {
-        ae = fma(a[idx], hr[c + NU - 1], ae);
-        ae = fma(d[idx], gr[c + NU - 1], ae);
-      } else {
-        ao = fma(a[idx], hr[c + NU - 1], ao);
-        ao = fma(d[idx], gr[c + NU - 1], ao);
-      }
-    }
-    e[p] = ae;
-    o[p] = ao;
-  }
-  if (2 * i0 < ROWS) {  // left boundary functions, positions 0 .. nu-1
-    T bl[NU], bd[NU];
-#pragma unroll
-    for (int cc = 0; cc < NU; ++cc) {
-      const int mc = (cc > whi ? whi : cc) - wlo;
-      const T va = pa[mc * stride], vd = pd[mc * stride];
-      bl[cc] = cc < half ? va : T(0);
-      bd[cc] = cc < half ? vd : T(0);
-    }
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-#pragma unroll
-      for (int sdx = 0; sdx < 2; ++sdx) {
-        const int n = 2 * (i0 + p) + sdx;
-        if (n < ROWS) {
-          T acc = sdx ? o[p] : e[p];
-#pragma unroll
-          for (int cc = 0; cc < NU; ++cc) {
-            acc = fma(sL[n * 2 * NU + cc], bl[cc], acc);
-            acc = fma(sL[n * 2 * NU + NU + cc], bd[cc], acc);
-          }
-          if (sdx) o[p] = acc; else e[p] = acc;
-        }
-      }
-    }
-  }
-  if (2 * (i0 + P) > size - ROWS) {  // right boundary functions, positions half-1-cc
-    const int right_first = half - NU > NU ? half - NU : NU;
-    T br[NU], bd[NU];
-#pragma unroll
-    for (int cc = 0; cc < NU; ++cc) {
-      const int pos = half - 1 - cc;
-      const int mc = (pos < wlo ? wlo : pos) - wlo;
-      const T va = pa[mc * stride], vd = pd[mc * stride];
-      br[cc] = pos >= right_first ? va : T(0);
-      bd[cc] = pos >= right_first ? vd : T(0);
-    }
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-#pragma unroll
-      for (int sdx = 0; sdx < 2; ++sdx) {
-        const int n = 2 * (i0 + p) + sdx;
-        if (n >= size - ROWS && n < size) {
-          const int i = n - (size - ROWS);
-          T acc = sdx ? o[p] : e[p];
-#pragma unroll
-          for (int cc = 0; cc < NU; ++cc) {
-            acc = fma(sR[i * 2 * NU + cc], br[cc], acc);
-            acc = fma(sR[i * 2 * NU + NU + cc], bd[cc], acc);
-          }
-          if (sdx) o[p] = acc; else e[p] = acc;
-        }
-      }
-    }
-  }
-}
-
-// Any run of P analysis outputs m0 .. m0+P-1 (scaling and wavelet coefficient
-// of each), boundary functions included.  x(n) is px[(n - wlo) * stride] for
-// n in the window [wlo, whi].
-template <typename T, int NU, int P>
-__device__ __forceinline__ void analysis_run_edge(const T* __restrict__ px, int stride, int wlo, int whi, int m0,
-                                                  int half, const T (&hr)[2 * NU], const T (&gr)[2 * NU],
-                                                  const T* __restrict__ sL, const T* __restrict__ sR, T (&a)[P],
-                                                  T (&d)[P]) {
-  constexpr int L = 2 * P + 2 * NU - 2, ROWS = 3 * NU - 1;
-  const int size = 2 * half;
-  const int right_first = half - NU > NU ? half - NU : NU;
-  T v[L];
-#pragma unroll
-  for (int u = 0; u < L; ++u) {
-    const int n = 2 * m0 - NU + 1 + u;
-    v[u] = px[((n < wlo ? wlo : (n > whi ? whi : n)) - wlo) * stride];
-  }
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
-    T sa = T(0), sd = T(0);
-#pragma unroll
-    for (int c = 0; c < 2 * NU; ++c) {
-      sa = fma(hr[c], v[2 * p + c], sa);
-      sd = fma(gr[c], v[2 * p + c], sd);
-    }
-    a[p] = sa;
-    d[p] = sd;
-  }
-  if (m0 < NU) {  // left boundary functions read x(0 .. 3nu-2)
-    T xl[ROWS];
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) xl[r] = px[((r > whi ? whi : r) - wlo) * stride];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const int m = m0 + p;
-      if (m < NU) {
-        T sa = T(0), sd = T(0);
-#pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-          sa = fma(sL[r * 2 * NU + m], xl[r], sa);
-          sd = fma(sL[r * 2 * NU + NU + m], xl[r], sd);
-        }
-        a[p] = sa;
-        d[p] = sd;
-      }
-    }
-  }
-  if (m0 + P > right_first) {  // right boundary functions read x(size-3nu+1 .. size-1)
-    T xr[ROWS];
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-      const int n = size - ROWS + r;
-      xr[r] = px[((n < wlo ? wlo : n) - wlo) * stride];
-    }
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const int m = m0 + p;
-      if (m >= right_first && m >= NU && m < half) {
-        const int cc = half - 1 - m;
-        T sa = T(0), sd = T(0);
-#pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-          sa = fma(sR[r * 2 * NU + cc], xr[r], sa);
-          sd = fma(sR[r * 2 * NU + NU + cc], xr[r], sd);
-        }
-        a[p] = sa;
-        d[p] = sd;
-      }
-    }
-  }
-}
 
 // Tile t of an n x n grid: the ring of tiles along the edges (which hold the
 // boundary functions and take longest) is dispatched first.
@@ -411,36 +42,6 @@ __device__ __forceinline__ void tile_of(int t, int n, int& tr, int& tc) {
     const int r = t - E;
     tr = 1 + r / (n - 2), tc = 1 + r % (n - 2);
   }
-}
-
-template <typename T>
-struct TileLds {
-  T* hs;
-  T* gs;
-  T* sLs;
-  T* sRs;
-};
-
-// Filters and boundary blocks: taps in registers for the interior runs, a
-// copy in LDS for the runtime-indexed boundary outputs.
-template <typename T, int NU>
-__device__ __forceinline__ TileLds<T> load_tables(const Tables<T>& t, T* tab_lds, T (&hr)[2 * NU], T (&gr)[2 * NU]) {
-#pragma unroll
-  for (int c = 0; c < 2 * NU; ++c) hr[c] = t.h[c], gr[c] = t.g[c];
-  TileLds<T> L;
-  L.hs = tab_lds;
-  L.gs = L.hs + 2 * NU;
-  L.sLs = L.gs + 2 * NU;
-  L.sRs = L.sLs + (3 * NU - 1) * 2 * NU;
-  for (int e = int(threadIdx.x); e < 2 * NU; e += int(blockDim.x)) L.hs[e] = t.h[e], L.gs[e] = t.g[e];
-  for (int e = int(threadIdx.x); e < (3 * NU - 1) * 2 * NU; e += int(blockDim.x))
-    L.sLs[e] = t.synL[e], L.sRs[e] = t.synR[e];
-  return L;
-}
-
-template <int NU>
-constexpr int tab_lds_size() {
-  return 4 * NU + 2 * (3 * NU - 1) * 2 * NU;
 }
 
 // ---------------------------------------------------------- tiled levels

@@ -58,4 +58,28 @@ hipError_t prepare_dwt2d(int nu);
 template <typename T>
 hipError_t transpose(const T* in, T* out, int64_t n, hipStream_t st);
 
+
+// ------------------------------------------------ one-dimensional path
+// True when the 1D kernels cover (element size, log2 M, nu, q).
+bool supported1d(int elem_bytes, int logm, int nu, int q);
+// Multilevel inverse DWT of x (M = 2^j values, C_{psi,j} order) into xi;
+// s0 is an M-element scratch line.
+template <typename T>
+hipError_t idwt1d(const T* x, T* xi, T* s0, int j0, int j, const Tables<T>& t, hipStream_t st);
+// Its transpose: xi (overwritten) -> x; s0 scratch.
+template <typename T>
+hipError_t dwt1d(T* xi, T* x, T* s0, int j0, int j, const Tables<T>& t, hipStream_t st);
+// Table product, natural-order transform and gather (pos: flat natural index
+// of every sample in L; full: every sample taken, m = N).  L: Q M scratch.
+template <typename T>
+hipError_t line1d_fwd(const T* xi, T* L, T* y, int j, const Tables<T>& t, const int32_t* pos, int64_t m, int full,
+                      hipStream_t st);
+// Its transpose: y -> xi.
+template <typename T>
+hipError_t line1d_adj(const T* y, T* L, T* xi, int j, const Tables<T>& t, const int32_t* pos, int64_t m, int full,
+                      hipStream_t st);
+// One-time setup (dynamic LDS limits) of the 1D wavelet kernels of order nu.
+template <typename T>
+hipError_t prepare_1d(int nu);
+
 }  // namespace wh2wav_fast

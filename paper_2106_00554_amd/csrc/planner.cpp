@@ -719,6 +719,18 @@ int build_host_plan(const wh2wav_desc* d, HostPlan* P, std::string* err) {
     }
     for (size_t e = 1; e < P->seg_ptr.size(); ++e) P->seg_ptr[e] += P->seg_ptr[e - 1];
   }
+  P->pos32.clear();
+  if (d->dim == 1 && !P->full_omega && P->N <= ((int64_t)1 << 30)) {
+    const int64_t M = P->M;
+    P->pos32.resize((size_t)d->m);
+    for (int64_t i = 0; i < d->m; ++i) {
+      const int64_t v = d->omega[i], s = v / M, b = v % M;
+      const uint64_t g = (uint64_t)(b ^ (b >> 1));
+      uint64_t k = 0;
+      for (int bit = 0; bit < d->j; ++bit) k |= ((g >> bit) & 1u) << (d->j - 1 - bit);
+      P->pos32[(size_t)i] = (int32_t)(s * M + (int64_t)(k ^ (uint64_t)(s & 1)));
+    }
+  }
   return WH2WAV_OK;
 }
 

@@ -55,6 +55,9 @@ struct HostPlan {
   // k = bitrev(gray(b)) xor (s & 1) of sample i within its phase line.
   std::vector<uint16_t> pos16;
   std::vector<int64_t> seg_ptr;
+  // 1D sample list (only when Omega is not full): pos32[i] = s M + k, the flat
+  // natural-order index of sample n_i = s M + b, k = bitrev(gray(b)) xor (s & 1).
+  std::vector<int32_t> pos32;
 };
 
 // Validates the descriptor and fills the plan.  Returns a WH2WAV_* status;

@@ -401,6 +401,7 @@ struct wh2wav_plan_s {
   int64_t* d_row_ptr = nullptr;
   uint16_t* d_pos16 = nullptr;
   int64_t* d_seg_ptr = nullptr;
+  int32_t* d_pos32 = nullptr;
   size_t off_h = 0, off_g = 0, off_T = 0, off_BL = 0, off_BR = 0, off_SL = 0, off_SR = 0;
 };
 
@@ -438,6 +439,12 @@ wh2wav_fast::Omega fast_omega_of(const wh2wav_plan_s* p) {
   o.seg_ptr = p->d_seg_ptr;
   o.full = p->host.full_omega ? 1 : 0;
   return o;
+}
+
+bool use_fast1d(const wh2wav_plan_s* p) {
+  const auto& H = p->host;
+  const bool f64 = H.dtype == WH2WAV_F64;
+  return H.dim == 1 && wh2wav_fast::supported1d(f64 ? 8 : 4, H.j, H.nu, H.q) && H.j0 <= (f64 ? 13 : 14);
 }
 
 bool use_fast(const wh2wav_plan_s* p) {
@@ -504,6 +511,14 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
   if (H.m == 0) return WH2WAV_OK;
   T* W = static_cast<T*>(ws);
   auto run = [&](int s) { return stage < 0 || stage == s; };
+  if (H.dim == 1 && use_fast1d(p)) {
+    T* S0 = W + M;
+    T* L = S0 + M;
+    const auto ft = fast_tables_of<T>(p);
+    if (run(0)) HIP_OK(wh2wav_fast::idwt1d<T>(x, W, S0, H.j0, H.j, ft, st));
+    if (run(1)) HIP_OK(wh2wav_fast::line1d_fwd<T>(W, L, y, H.j, ft, p->d_pos32, H.m, H.full_omega ? 1 : 0, st));
+    return WH2WAV_OK;
+  }
   if (H.dim == 1) {
     T* TMP = W + M;
     if (run(0)) {
@@ -576,6 +591,14 @@ int adjoint_impl(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t
       launch_fill<T>(x, xlen, st);
       HIP_OK(hipGetLastError());
     }
+    return WH2WAV_OK;
+  }
+  if (H.dim == 1 && use_fast1d(p)) {
+    T* S0 = W + M;
+    T* L = S0 + M;
+    const auto ft = fast_tables_of<T>(p);
+    if (run(0)) HIP_OK(wh2wav_fast::line1d_adj<T>(y, L, W, H.j, ft, p->d_pos32, H.m, H.full_omega ? 1 : 0, st));
+    if (run(2)) HIP_OK(wh2wav_fast::dwt1d<T>(W, x, S0, H.j0, H.j, ft, st));
     return WH2WAV_OK;
   }
   if (H.dim == 1) {
@@ -657,6 +680,7 @@ void release(wh2wav_plan_s* p) {
   if (p->d_tables) (void)hipFree(p->d_tables);
   if (p->d_mask) (void)hipFree(p->d_mask);
   if (p->d_pos16) (void)hipFree(p->d_pos16);
+  if (p->d_pos32) (void)hipFree(p->d_pos32);
   if (p->d_seg_ptr) (void)hipFree(p->d_seg_ptr);
   if (p->d_row_ptr) (void)hipFree(p->d_row_ptr);
   delete p;
@@ -686,7 +710,8 @@ int wh2wav_plan(const wh2wav_desc* desc, wh2wav_plan_t* out) {
     return fail(WH2WAV_EUNSUPPORTED, "j must be >= 1");
   }
   const size_t elem = H.dtype == WH2WAV_F64 ? 8 : 4;
-  if (2 * size_t(H.M) * elem + sizeof(int) * (size_t(H.words_per_row) + kThreads) > kMaxLds) {
+  if (!use_fast(p) && !use_fast1d(p) &&
+      2 * size_t(H.M) * elem + sizeof(int) * (size_t(H.words_per_row) + kThreads) > kMaxLds) {
     delete p;
     return fail(WH2WAV_EUNSUPPORTED, "M too large for the LDS line kernels");
   }
@@ -702,6 +727,14 @@ int wh2wav_plan(const wh2wav_desc* desc, wh2wav_plan_t* out) {
     if (e == hipSuccess)
       e = H.dtype == WH2WAV_F64 ? wh2wav_fast::prepare_lines<double>(H.j, H.nu)
                                 : wh2wav_fast::prepare_lines<float>(H.j, H.nu);
+    if (e != hipSuccess) {
+      delete p;
+      return fail(WH2WAV_EHIP, std::string("kernel setup: ") + hipGetErrorString(e));
+    }
+  }
+  if (use_fast1d(p)) {
+    hipError_t e = H.dtype == WH2WAV_F64 ? wh2wav_fast::prepare_1d<double>(H.nu)
+                                         : wh2wav_fast::prepare_1d<float>(H.nu);
     if (e != hipSuccess) {
       delete p;
       return fail(WH2WAV_EHIP, std::string("kernel setup: ") + hipGetErrorString(e));
@@ -723,6 +756,7 @@ int wh2wav_plan(const wh2wav_desc* desc, wh2wav_plan_t* out) {
   if (rc == WH2WAV_OK) rc = upload((void**)&p->d_mask, H.mask.data(), sizeof(uint32_t) * H.mask.size());
   if (rc == WH2WAV_OK) rc = upload((void**)&p->d_pos16, H.pos16.data(), sizeof(uint16_t) * H.pos16.size());
   if (rc == WH2WAV_OK) rc = upload((void**)&p->d_seg_ptr, H.seg_ptr.data(), sizeof(int64_t) * H.seg_ptr.size());
+  if (rc == WH2WAV_OK) rc = upload((void**)&p->d_pos32, H.pos32.data(), sizeof(int32_t) * H.pos32.size());
   if (rc != WH2WAV_OK) {
     std::string m = g_last_error;
     release(p);
@@ -737,7 +771,7 @@ int wh2wav_workspace_size(wh2wav_plan_t p, size_t* bytes) {
   const auto& H = p->host;
   const size_t elem = H.dtype == WH2WAV_F64 ? 8 : 4;
   if (H.dim == 1)
-    *bytes = 2 * size_t(H.M) * elem;
+    *bytes = (2 + size_t(H.Q)) * size_t(H.M) * elem;
   else
     *bytes = (2 * size_t(H.M) * size_t(H.M) + size_t(H.N) * size_t(H.M)) * elem;
   return WH2WAV_OK;

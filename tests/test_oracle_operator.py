@@ -4,6 +4,7 @@ import pytest
 
 from oracle import basis, cascade, halfline, walsh
 from oracle import operator as op
+from tests import inputs
 from tests.conftest import read_golden
 
 
@@ -166,3 +167,16 @@ def test_sampled_rows_match_full():
     alpha = op.forward_2d_full(full, X)
     sub = op._forward_2d(part, full, X, None)
     assert np.abs(sub - alpha[rows]).max() < 1e-14
+
+
+def test_sampled_1d_entries_equal_dense_products():
+    """The sampled 1D forward / adjoint entries equal the dense product A x and A[omega]^T y."""
+    cfg = op.Config(4, 7, 2, 3)
+    A = op.matrix_1d(cfg)
+    x = inputs.coefficients_1d(cfg.j, cfg.j0, 51)
+    omega = inputs.uniform_omega(cfg.N, 0.3, 52)
+    yv = inputs.sample_vector(omega.size, 53)
+    ns = np.array([0, 1, 5, cfg.N // 2, cfg.N - 1, 77, 300])
+    np.testing.assert_allclose(op.forward_entries_1d(cfg, x, ns), (A @ x)[ns], rtol=0, atol=1e-13)
+    cs = np.array([0, 3, 8, 9, 15, 16, 64, 100, 127])
+    np.testing.assert_allclose(op.adjoint_entries_1d(cfg, yv, omega, cs), (A[omega].T @ yv)[cs], rtol=0, atol=1e-13)
