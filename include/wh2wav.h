@@ -115,6 +115,55 @@ int wh2wav_destroy(wh2wav_plan_t plan);
 /* Message describing the last failure on this thread ("" if none). */
 const char* wh2wav_last_error(void);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent operators of the kind above (each with its own size,
+ * wavelet order, q, element type and Omega) computed together: the
+ * reconstructions in the paper solve one problem per image, and a serving
+ * loop or a parameter sweep runs many at once.  Every instance computes
+ * exactly what wh2wav_forward / wh2wav_adjoint compute for its descriptor.
+ *
+ * Each wh2wav_forward_batch / wh2wav_adjoint_batch call is ONE hipGraph
+ * launch on `stream`: the graph forks into B concurrent branches, the
+ * instances' kernels are dealt to the branches in the schedule's order, and
+ * the branches join before the graph ends.  The graph for a given set of
+ * pointers (xs, ys, ws) is captured on its first use and replayed afterwards;
+ * the batch keeps the graphs of its 8 most recent pointer sets.
+ *
+ * Ownership and errors follow the single-plan rules: descriptors are copied,
+ * pointer arrays are read during the call only (the device buffers they name
+ * must stay valid while a graph that captured them may be replayed), one
+ * batch must not be used from two threads at once, and instance i uses bytes
+ * [off_i, off_i + size_i) of ws (sizes rounded up to 256 B). */
+typedef struct wh2wav_batch_s* wh2wav_batch_t;
+
+/* Plan `count` instances; *out receives the handle.  Fails (and releases every
+ * plan made so far) if any descriptor fails; the message names the instance. */
+int wh2wav_plan_batch(const wh2wav_desc* descs, int count, wh2wav_batch_t* out);
+
+/* Bytes of device workspace the batch needs (sum of the instances'). */
+int wh2wav_batch_workspace_size(wh2wav_batch_t b, size_t* bytes);
+
+/* ys[i] = P_Omega_i A_i xs[i] for every instance (arrays of `count` device pointers). */
+int wh2wav_forward_batch(wh2wav_batch_t b, const void* const* xs, void* const* ys, void* ws, void* stream);
+
+/* xs[i] = A_i^T P_Omega_i^T ys[i] for every instance. */
+int wh2wav_adjoint_batch(wh2wav_batch_t b, const void* const* ys, void* const* xs, void* ws, void* stream);
+
+/* Schedule: `branches` concurrent graph branches (1..8) and instance `order`
+ * (0: as given, 1: largest first).  Default 4 and 1. */
+int wh2wav_batch_schedule(wh2wav_batch_t b, int* branches, int* order);
+int wh2wav_batch_set_schedule(wh2wav_batch_t b, int branches, int order);
+
+/* Autotuner: times forward(xs -> ys) followed by adjoint(ys -> xa), `reps`
+ * times per candidate schedule (branches 1, 2, 4, 8 x both orders) on
+ * `stream`, keeps the fastest schedule and writes its time per pair of graph
+ * launches in ms to *best_ms (may be NULL).  Synchronises `stream`. */
+int wh2wav_batch_tune(wh2wav_batch_t b, const void* const* xs, void* const* ys, void* const* xa, void* ws,
+                      void* stream, int reps, float* best_ms);
+
+/* Release the batch, its graphs and its plans.  NULL is accepted. */
+int wh2wav_destroy_batch(wh2wav_batch_t b);
+
 /* Host-side introspection (no GPU needed): the float64 tables a plan for
  * `desc` would upload.  `which` selects the table; at most `capacity`
  * values are written to `out` and the full length goes to *count.

@@ -28,7 +28,10 @@ TABLES = {"h": 0, "g": 1, "T": 2, "band_l": 3, "band_r": 4, "syn_l": 5, "syn_r":
 # every symbol the header declares
 EXPORTS = ("wh2wav_plan", "wh2wav_workspace_size", "wh2wav_forward", "wh2wav_adjoint",
            "wh2wav_stage_count", "wh2wav_forward_stage", "wh2wav_adjoint_stage",
-           "wh2wav_destroy", "wh2wav_last_error", "wh2wav_host_table")
+           "wh2wav_destroy", "wh2wav_last_error", "wh2wav_host_table",
+           "wh2wav_plan_batch", "wh2wav_batch_workspace_size", "wh2wav_forward_batch",
+           "wh2wav_adjoint_batch", "wh2wav_batch_schedule", "wh2wav_batch_set_schedule",
+           "wh2wav_batch_tune", "wh2wav_destroy_batch")
 
 
 class wh2wav_desc(ctypes.Structure):
@@ -79,6 +82,15 @@ def _load():
     lib.wh2wav_last_error.restype = ctypes.c_char_p
     lib.wh2wav_host_table.argtypes = [ctypes.POINTER(wh2wav_desc), ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_double), sz, ctypes.POINTER(sz)]
+    pp = ctypes.POINTER(vp)
+    lib.wh2wav_plan_batch.argtypes = [ctypes.POINTER(wh2wav_desc), ctypes.c_int, ctypes.POINTER(vp)]
+    lib.wh2wav_batch_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.wh2wav_forward_batch.argtypes = [vp, pp, pp, vp, vp]
+    lib.wh2wav_adjoint_batch.argtypes = [vp, pp, pp, vp, vp]
+    lib.wh2wav_batch_schedule.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.wh2wav_batch_set_schedule.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    lib.wh2wav_batch_tune.argtypes = [vp, pp, pp, pp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]
+    lib.wh2wav_destroy_batch.argtypes = [vp]
     for name in EXPORTS:
         if name != "wh2wav_last_error":
             getattr(lib, name).restype = ctypes.c_int
@@ -144,3 +156,50 @@ def wh2wav_host_table(desc, which):
     buf = (ctypes.c_double * max(count.value, 1))()
     _check(LIB.wh2wav_host_table(ctypes.byref(desc), idx, buf, count.value, ctypes.byref(count)))
     return list(buf[:count.value])
+
+
+def _ptr_array(ptrs):
+    return (ctypes.c_void_p * max(len(ptrs), 1))(*[ctypes.c_void_p(int(p)) for p in ptrs])
+
+
+def wh2wav_plan_batch(descs):
+    arr = (wh2wav_desc * len(descs))(*descs)
+    handle = ctypes.c_void_p()
+    _check(LIB.wh2wav_plan_batch(arr, len(descs), ctypes.byref(handle)))
+    return handle
+
+
+def wh2wav_batch_workspace_size(batch):
+    n = ctypes.c_size_t()
+    _check(LIB.wh2wav_batch_workspace_size(batch, ctypes.byref(n)))
+    return n.value
+
+
+def wh2wav_forward_batch(batch, x_ptrs, y_ptrs, ws_ptr, stream_ptr):
+    return _check(LIB.wh2wav_forward_batch(batch, _ptr_array(x_ptrs), _ptr_array(y_ptrs), ws_ptr, stream_ptr))
+
+
+def wh2wav_adjoint_batch(batch, y_ptrs, x_ptrs, ws_ptr, stream_ptr):
+    return _check(LIB.wh2wav_adjoint_batch(batch, _ptr_array(y_ptrs), _ptr_array(x_ptrs), ws_ptr, stream_ptr))
+
+
+def wh2wav_batch_schedule(batch):
+    b, o = ctypes.c_int(), ctypes.c_int()
+    _check(LIB.wh2wav_batch_schedule(batch, ctypes.byref(b), ctypes.byref(o)))
+    return b.value, o.value
+
+
+def wh2wav_batch_set_schedule(batch, branches, order):
+    return _check(LIB.wh2wav_batch_set_schedule(batch, branches, order))
+
+
+def wh2wav_batch_tune(batch, x_ptrs, y_ptrs, xa_ptrs, ws_ptr, stream_ptr, reps):
+    best = ctypes.c_float()
+    _check(LIB.wh2wav_batch_tune(batch, _ptr_array(x_ptrs), _ptr_array(y_ptrs), _ptr_array(xa_ptrs), ws_ptr,
+                                 stream_ptr, reps, ctypes.byref(best)))
+    return best.value
+
+
+def wh2wav_destroy_batch(batch):
+    return _check(LIB.wh2wav_destroy_batch(batch))
+

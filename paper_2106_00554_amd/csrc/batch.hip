@@ -1,0 +1,295 @@
+// Batched execution of many independent operators (uneven sizes, wavelet
+// orders, q and element types) as one hipGraph launch per direction.
+//
+// The graph forks from the launch stream into B concurrent branches; the
+// instances are dealt to the branches in a chosen order, each instance being
+// its own stage kernels (the same kernels as the single-plan entry points), and
+// the branches join before the graph ends.  Independent branches let small
+// instances fill the CUs that a large one leaves idle and remove the per-launch
+// host cost.  A graph is captured once per set of pointers and replayed; the
+// schedule (B, order) is a batch property that wh2wav_batch_tune picks by
+// timing every candidate on the caller's buffers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/wh2wav.h"
+#include "abi_internal.h"
+
+namespace {
+
+constexpr int kMaxBranches = 8;
+constexpr size_t kAlign = 256;
+constexpr size_t kMaxGraphs = 8;
+
+struct GraphEntry {
+  int dir, branches, order;
+  const void* ws;
+  std::vector<const void*> in, out;
+  hipGraphExec_t exec;
+};
+
+}  // namespace
+
+struct wh2wav_batch_s {
+  std::vector<wh2wav_plan_t> plans;
+  std::vector<wh2wav::PlanShape> shape;
+  std::vector<size_t> ws_off;
+  size_t ws_total = 0;
+  int branches = 4;
+  int order = 1;  // 0: as given, 1: largest first
+  hipStream_t cap = nullptr;
+  hipStream_t side[kMaxBranches] = {};
+  hipEvent_t fork = nullptr, join[kMaxBranches] = {};
+  std::vector<GraphEntry> graphs;
+};
+
+namespace {
+
+int fail(int code, const std::string& msg) { return wh2wav::set_error(code, msg); }
+
+#define HIP_B(call)                                                              \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      return fail(WH2WAV_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+double cost_of(const wh2wav::PlanShape& s) {
+  const double n = s.dim == 1 ? double(s.N) : double(s.N) * double(s.N);
+  const double e = s.dtype == WH2WAV_F64 ? 2.0 : 1.0;
+  return n * e;
+}
+
+std::vector<int> schedule_order(const wh2wav_batch_s* b) {
+  std::vector<int> idx(b->plans.size());
+  std::iota(idx.begin(), idx.end(), 0);
+  if (b->order == 1)
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](int a, int c) { return cost_of(b->shape[a]) > cost_of(b->shape[c]); });
+  return idx;
+}
+
+void release_batch(wh2wav_batch_s* b) {
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+  b->graphs.clear();
+  for (auto* p : b->plans) wh2wav_destroy(p);
+  b->plans.clear();
+  for (int k = 0; k < kMaxBranches; ++k) {
+    if (b->side[k]) (void)hipStreamDestroy(b->side[k]);
+    if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+}
+
+// Captures the instances' stage kernels into one executable graph.
+int capture(wh2wav_batch_s* b, int dir, const void* const* in, void* const* out, void* ws, hipGraphExec_t* exec) {
+  const int nb = std::max(1, std::min(b->branches, kMaxBranches));
+  HIP_B(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+  int rc = WH2WAV_OK;
+  hipError_t he = hipEventRecord(b->fork, b->cap);
+  for (int k = 0; k < nb && he == hipSuccess; ++k) he = hipStreamWaitEvent(b->side[k], b->fork, 0);
+  if (he != hipSuccess) rc = fail(WH2WAV_EHIP, std::string("batch fork: ") + hipGetErrorString(he));
+  const std::vector<int> idx = schedule_order(b);
+  for (size_t t = 0; t < idx.size() && rc == WH2WAV_OK; ++t) {
+    const int i = idx[t];
+    void* wsi = static_cast<char*>(ws) + b->ws_off[i];
+    hipStream_t st = b->side[t % nb];
+    rc = dir == 0 ? wh2wav_forward(b->plans[i], in[i], out[i], wsi, st)
+                  : wh2wav_adjoint(b->plans[i], in[i], out[i], wsi, st);
+  }
+  // join every branch even after a failure, so that no stream is left capturing
+  for (int k = 0; k < nb; ++k) {
+    he = hipEventRecord(b->join[k], b->side[k]);
+    if (he == hipSuccess) he = hipStreamWaitEvent(b->cap, b->join[k], 0);
+    if (he != hipSuccess && rc == WH2WAV_OK)
+      rc = fail(WH2WAV_EHIP, std::string("batch join: ") + hipGetErrorString(he));
+  }
+  hipGraph_t g = nullptr;
+  he = hipStreamEndCapture(b->cap, &g);
+  if (rc != WH2WAV_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (he != hipSuccess) return fail(WH2WAV_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(he));
+  he = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (he != hipSuccess) return fail(WH2WAV_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(he));
+  return WH2WAV_OK;
+}
+
+int check_ptrs(const wh2wav_batch_s* b, int dir, const void* const* in, void* const* out, void* ws) {
+  if (!in || !out) return fail(WH2WAV_EINVAL, "pointer arrays are NULL");
+  if (!ws && b->ws_total) return fail(WH2WAV_EINVAL, "workspace is NULL");
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    const auto& s = b->shape[i];
+    const int64_t xlen = s.dim == 1 ? s.M : s.M * s.M;
+    const int64_t inlen = dir == 0 ? xlen : s.m, outlen = dir == 0 ? s.m : xlen;
+    if ((inlen && !in[i]) || (outlen && !out[i]))
+      return fail(WH2WAV_EINVAL, "instance " + std::to_string(i) + ": NULL input or output");
+  }
+  return WH2WAV_OK;
+}
+
+int run(wh2wav_batch_s* b, int dir, const void* const* in, void* const* out, void* ws, void* stream) {
+  int rc = check_ptrs(b, dir, in, out, ws);
+  if (rc) return rc;
+  const size_t n = b->plans.size();
+  GraphEntry* hit = nullptr;
+  for (auto& g : b->graphs) {
+    if (g.dir != dir || g.branches != b->branches || g.order != b->order || g.ws != ws) continue;
+    if (std::equal(g.in.begin(), g.in.end(), in) && std::equal(g.out.begin(), g.out.end(), out)) {
+      hit = &g;
+      break;
+    }
+  }
+  if (!hit) {
+    if (b->graphs.size() >= kMaxGraphs) {
+      (void)hipGraphExecDestroy(b->graphs.front().exec);
+      b->graphs.erase(b->graphs.begin());
+    }
+    GraphEntry e;
+    e.dir = dir, e.branches = b->branches, e.order = b->order, e.ws = ws;
+    e.in.assign(in, in + n);
+    e.out.assign(out, out + n);
+    rc = capture(b, dir, in, out, ws, &e.exec);
+    if (rc) return rc;
+    b->graphs.push_back(std::move(e));
+    hit = &b->graphs.back();
+  }
+  HIP_B(hipGraphLaunch(hit->exec, static_cast<hipStream_t>(stream)));
+  return WH2WAV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wh2wav_plan_batch(const wh2wav_desc* descs, int count, wh2wav_batch_t* out) {
+  if (!out) return fail(WH2WAV_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!descs || count <= 0) return fail(WH2WAV_EINVAL, "need at least one descriptor");
+  auto* b = new (std::nothrow) wh2wav_batch_s();
+  if (!b) return fail(WH2WAV_ENOMEM, "host allocation failed");
+  for (int i = 0; i < count; ++i) {
+    wh2wav_plan_t p = nullptr;
+    int rc = wh2wav_plan(&descs[i], &p);
+    if (rc != WH2WAV_OK) {
+      const std::string msg = "instance " + std::to_string(i) + ": " + wh2wav_last_error();
+      release_batch(b);
+      delete b;
+      return fail(rc, msg);
+    }
+    b->plans.push_back(p);
+    b->shape.push_back(wh2wav::plan_shape(p));
+    size_t bytes = 0;
+    wh2wav_workspace_size(p, &bytes);
+    b->ws_off.push_back(b->ws_total);
+    b->ws_total += (bytes + kAlign - 1) / kAlign * kAlign;
+  }
+  hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  for (int k = 0; k < kMaxBranches && e == hipSuccess; ++k) {
+    e = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    release_batch(b);
+    delete b;
+    return fail(WH2WAV_EHIP, std::string("batch streams: ") + hipGetErrorString(e));
+  }
+  *out = b;
+  return WH2WAV_OK;
+}
+
+int wh2wav_batch_workspace_size(wh2wav_batch_t b, size_t* bytes) {
+  if (!b || !bytes) return fail(WH2WAV_EINVAL, "NULL argument");
+  *bytes = b->ws_total;
+  return WH2WAV_OK;
+}
+
+int wh2wav_forward_batch(wh2wav_batch_t b, const void* const* xs, void* const* ys, void* ws, void* stream) {
+  if (!b) return fail(WH2WAV_EINVAL, "batch is NULL");
+  return run(b, 0, xs, ys, ws, stream);
+}
+
+int wh2wav_adjoint_batch(wh2wav_batch_t b, const void* const* ys, void* const* xs, void* ws, void* stream) {
+  if (!b) return fail(WH2WAV_EINVAL, "batch is NULL");
+  return run(b, 1, ys, xs, ws, stream);
+}
+
+int wh2wav_batch_schedule(wh2wav_batch_t b, int* branches, int* order) {
+  if (!b || !branches || !order) return fail(WH2WAV_EINVAL, "NULL argument");
+  *branches = b->branches;
+  *order = b->order;
+  return WH2WAV_OK;
+}
+
+int wh2wav_batch_set_schedule(wh2wav_batch_t b, int branches, int order) {
+  if (!b) return fail(WH2WAV_EINVAL, "batch is NULL");
+  if (branches < 1 || branches > kMaxBranches || (order != 0 && order != 1))
+    return fail(WH2WAV_EINVAL, "branches must be 1..8 and order 0 or 1");
+  b->branches = branches;
+  b->order = order;
+  return WH2WAV_OK;
+}
+
+int wh2wav_batch_tune(wh2wav_batch_t b, const void* const* xs, void* const* ys, void* const* xa, void* ws,
+                      void* stream, int reps, float* best_ms) {
+  if (!b) return fail(WH2WAV_EINVAL, "batch is NULL");
+  if (reps < 1) return fail(WH2WAV_EINVAL, "reps must be >= 1");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  HIP_B(hipEventCreate(&t0));
+  hipError_t he = hipEventCreate(&t1);
+  if (he != hipSuccess) {
+    (void)hipEventDestroy(t0);
+    return fail(WH2WAV_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(he));
+  }
+  const int cand_b[] = {1, 2, 4, 8};
+  float best = -1.f;
+  int bb = b->branches, bo = b->order, rc = WH2WAV_OK;
+  for (int order = 0; order < 2 && rc == WH2WAV_OK; ++order) {
+    for (int nb : cand_b) {
+      b->branches = nb;
+      b->order = order;
+      // first pair captures and warms up; then `reps` timed pairs
+      rc = run(b, 0, xs, ys, ws, stream);
+      if (rc == WH2WAV_OK) rc = run(b, 1, ys, xa, ws, stream);
+      if (rc) break;
+      he = hipEventRecord(t0, st);
+      for (int r = 0; r < reps && rc == WH2WAV_OK && he == hipSuccess; ++r) {
+        rc = run(b, 0, xs, ys, ws, stream);
+        if (rc == WH2WAV_OK) rc = run(b, 1, ys, xa, ws, stream);
+      }
+      if (he == hipSuccess) he = hipEventRecord(t1, st);
+      if (he == hipSuccess) he = hipEventSynchronize(t1);
+      float ms = 0.f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, t0, t1);
+      if (he != hipSuccess) rc = fail(WH2WAV_EHIP, std::string("tune timing: ") + hipGetErrorString(he));
+      if (rc) break;
+      ms /= float(reps);
+      if (best < 0.f || ms < best) best = ms, bb = nb, bo = order;
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  b->branches = bb;
+  b->order = bo;
+  if (best_ms) *best_ms = best;
+  return rc;
+}
+
+int wh2wav_destroy_batch(wh2wav_batch_t b) {
+  if (!b) return WH2WAV_OK;
+  release_batch(b);
+  delete b;
+  return WH2WAV_OK;
+}
+
+}  // extern "C"

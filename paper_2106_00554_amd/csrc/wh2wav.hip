@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "../../include/wh2wav.h"
+#include "abi_internal.h"
 #include "fast2d.h"
 #include "planner.h"
 
@@ -687,6 +688,14 @@ void release(wh2wav_plan_s* p) {
 }
 
 }  // namespace
+
+namespace wh2wav {
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+PlanShape plan_shape(wh2wav_plan_t p) {
+  const auto& H = p->host;
+  return PlanShape{H.dim, H.j, H.q, H.nu, H.dtype, H.M, H.N, H.m};
+}
+}  // namespace wh2wav
 
 extern "C" {
 

@@ -89,3 +89,93 @@ class Wh2Wav:
             self.close()
         except Exception:
             pass
+
+
+class Wh2WavBatch:
+    """Many independent operators, one graph launch per direction.
+
+    `specs` is a list of dicts with the keys of `Wh2Wav` (dim, j, q, nu and
+    optionally j0, dtype, omega).  `forward(xs)` returns the list of
+    P_Omega_i A_i xs[i]; `adjoint(ys)` the list of A_i^T P_Omega_i^T ys[i].
+    Calls with the same tensors replay a captured graph (see
+    wh2wav_forward_batch); `tune` runs the schedule autotuner.
+    """
+
+    def __init__(self, specs, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        descs, keeps = [], []
+        self.x_shapes, self.ms, self.dtypes = [], [], []
+        for sp in specs:
+            dtype = sp.get("dtype", torch.float64)
+            d, k = make_desc(sp["dim"], sp["j"], sp["q"], sp["nu"], sp.get("j0"), dtype, sp.get("omega"))
+            descs.append(d)
+            keeps.append(k)
+            M = 1 << sp["j"]
+            self.x_shapes.append((M,) if sp["dim"] == 1 else (M, M))
+            self.ms.append(int(d.m))
+            self.dtypes.append(dtype)
+        with torch.cuda.device(self.device):
+            self._batch = _abi.wh2wav_plan_batch(descs)
+        del keeps
+        nbytes = _abi.wh2wav_batch_workspace_size(self._batch)
+        self.workspace = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=self.device)
+
+    def __len__(self):
+        return len(self.ms)
+
+    def _stream(self):
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    def _check(self, ts, shapes, name):
+        if len(ts) != len(self):
+            raise ValueError(f"{name}: expected {len(self)} tensors, got {len(ts)}")
+        for i, (t, shp, dt) in enumerate(zip(ts, shapes, self.dtypes)):
+            if t.device != self.device or t.dtype != dt or not t.is_contiguous() or tuple(t.shape) != tuple(shp):
+                raise ValueError(f"{name}[{i}] must be a contiguous {dt} tensor of shape {tuple(shp)} on "
+                                 f"{self.device}")
+
+    def new_outputs(self, direction):
+        shapes = [(m,) for m in self.ms] if direction == 0 else self.x_shapes
+        return [torch.empty(s, dtype=dt, device=self.device) for s, dt in zip(shapes, self.dtypes)]
+
+    def forward(self, xs, ys=None):
+        ys = self.new_outputs(0) if ys is None else ys
+        self._check(xs, self.x_shapes, "xs")
+        self._check(ys, [(m,) for m in self.ms], "ys")
+        _abi.wh2wav_forward_batch(self._batch, [t.data_ptr() for t in xs], [t.data_ptr() for t in ys],
+                                  self.workspace.data_ptr(), self._stream())
+        return ys
+
+    def adjoint(self, ys, xs=None):
+        xs = self.new_outputs(1) if xs is None else xs
+        self._check(ys, [(m,) for m in self.ms], "ys")
+        self._check(xs, self.x_shapes, "xs")
+        _abi.wh2wav_adjoint_batch(self._batch, [t.data_ptr() for t in ys], [t.data_ptr() for t in xs],
+                                  self.workspace.data_ptr(), self._stream())
+        return xs
+
+    def schedule(self):
+        return _abi.wh2wav_batch_schedule(self._batch)
+
+    def set_schedule(self, branches, order):
+        _abi.wh2wav_batch_set_schedule(self._batch, branches, order)
+
+    def tune(self, xs, ys, xa, reps=5):
+        """Time every schedule on these buffers, keep the fastest; returns its ms per pair."""
+        self._check(xs, self.x_shapes, "xs")
+        self._check(ys, [(m,) for m in self.ms], "ys")
+        self._check(xa, self.x_shapes, "xa")
+        return _abi.wh2wav_batch_tune(self._batch, [t.data_ptr() for t in xs], [t.data_ptr() for t in ys],
+                                      [t.data_ptr() for t in xa], self.workspace.data_ptr(), self._stream(), reps)
+
+    def close(self):
+        if getattr(self, "_batch", None) is not None:
+            _abi.wh2wav_destroy_batch(self._batch)
+            self._batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

@@ -1,0 +1,142 @@
+"""Batched execution (one hipGraph launch per direction) through the C ABI.
+
+* every instance of a mixed batch (1D and 2D, Haar to db8, q = 1..3, FP32 and
+  FP64, empty / full / sparse Omega) equals its single-plan product bit for
+  bit, and a small instance equals the oracle;
+* graph replays: the same buffers are replayed several times with eager work,
+  new input values and synchronisations in between, each replay checked;
+* every schedule (branches, order) and the autotuner give the same results;
+* a new set of pointers captures a new graph.
+"""
+import numpy as np
+import pytest
+
+from oracle import operator as op
+from tests import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+F32, F64 = torch.float32, torch.float64
+
+SPECS = [
+    # dim, nu, j, q, j0, dtype, omega density (None: all, 0: empty)
+    (1, 4, 10, 1, 3, F64, None),
+    (1, 2, 12, 2, 2, F32, 0.2),
+    (1, 8, 15, 1, 4, F32, 0.1),
+    (1, 1, 6, 3, 2, F64, 0.4),
+    (1, 3, 5, 1, 3, F64, 0.5),
+    (2, 2, 5, 1, 2, F64, 0.25),
+    (2, 4, 9, 1, 3, F32, 0.25),
+    (2, 8, 10, 1, 4, F32, 0.15),
+    (2, 2, 9, 2, 2, F64, None),
+    (2, 4, 7, 2, 3, F32, 0.3),
+    (2, 6, 10, 1, 4, F32, 0),
+]
+
+
+def _instances():
+    specs, xs_np = [], []
+    for i, (dim, nu, j, q, j0, dt, dens) in enumerate(SPECS):
+        N = 1 << (j + q)
+        seed = 9000 + 37 * i
+        if dim == 1:
+            x = inputs.coefficients_1d(j, j0, seed)
+            omega = None if dens is None else (np.zeros(0, np.int64) if dens == 0 else
+                                               inputs.multilevel_omega_1d(N, dens, seed + 1))
+        else:
+            x = inputs.coefficients_2d(j, j0, seed)
+            omega = None if dens is None else (np.zeros(0, np.int64) if dens == 0 else
+                                               inputs.multilevel_omega_2d(N, dens, seed + 1, core=8))
+        specs.append(dict(dim=dim, nu=nu, j=j, q=q, j0=j0, dtype=dt, omega=omega))
+        xs_np.append(x)
+    return specs, xs_np
+
+
+@pytest.fixture(scope="module")
+def setup():
+    from paper_2106_00554_amd.operator import Wh2Wav, Wh2WavBatch
+    specs, xs_np = _instances()
+    print(f"[gpu] batch of {len(specs)} instances", flush=True)
+    batch = Wh2WavBatch(specs)
+    singles = [Wh2Wav(s["dim"], s["j"], s["q"], s["nu"], s["j0"], s["dtype"], s["omega"]) for s in specs]
+    xs = [torch.tensor(x, dtype=s["dtype"], device="cuda") for x, s in zip(xs_np, specs)]
+    return specs, xs_np, batch, singles, xs
+
+
+def _eager(singles, xs):
+    ys = [s.forward(x) for s, x in zip(singles, xs)]
+    xa = [s.adjoint(y) for s, y in zip(singles, ys)]
+    torch.cuda.synchronize()
+    return ys, xa
+
+
+def _same(a, b):
+    return all(torch.equal(u, v) for u, v in zip(a, b))
+
+
+def test_batch_equals_single_plans(setup):
+    specs, xs_np, batch, singles, xs = setup
+    ys_ref, xa_ref = _eager(singles, xs)
+    ys = batch.forward(xs)
+    xa = batch.adjoint(ys)
+    torch.cuda.synchronize()
+    assert _same(ys, ys_ref) and _same(xa, xa_ref)
+    # oracle tie-in: the small 2D FP64 instance
+    i = 5
+    s = specs[i]
+    cfg = op.Config(s["nu"], s["j"], s["q"], s["j0"])
+    blocks = op.Blocks2D(cfg)
+    y_ref = op.forward_2d_full(blocks, xs_np[i], s["omega"]).reshape(-1)
+    assert np.linalg.norm(ys[i].cpu().numpy() - y_ref) <= 1e-12 * np.linalg.norm(y_ref)
+
+
+def test_graph_replays_with_eager_work_between(setup):
+    specs, xs_np, batch, singles, xs = setup
+    ys = batch.new_outputs(0)
+    xa = batch.new_outputs(1)
+    for r in range(4):
+        if r:
+            for x in xs:
+                x.mul_(-1.5)  # eager work that changes the inputs between replays
+        batch.forward(xs, ys)
+        batch.adjoint(ys, xa)
+        torch.cuda.synchronize()
+        ys_ref, xa_ref = _eager(singles, xs)
+        assert _same(ys, ys_ref), f"forward replay {r}"
+        assert _same(xa, xa_ref), f"adjoint replay {r}"
+        _ = [torch.sum(y) for y in ys_ref]  # unrelated eager kernels
+        torch.cuda.synchronize()
+
+
+def test_schedules_and_tuner(setup):
+    specs, xs_np, batch, singles, xs = setup
+    ys_ref, xa_ref = _eager(singles, xs)
+    for branches, order in [(1, 0), (2, 1), (8, 0), (3, 1)]:
+        batch.set_schedule(branches, order)
+        assert batch.schedule() == (branches, order)
+        ys = batch.forward(xs)  # fresh output tensors: a new pointer set
+        xa = batch.adjoint(ys)
+        torch.cuda.synchronize()
+        assert _same(ys, ys_ref) and _same(xa, xa_ref), (branches, order)
+    ys = batch.new_outputs(0)
+    xa = batch.new_outputs(1)
+    best = batch.tune(xs, ys, xa, reps=3)
+    assert best > 0
+    b, o = batch.schedule()
+    assert b in (1, 2, 4, 8) and o in (0, 1)
+    batch.forward(xs, ys)
+    batch.adjoint(ys, xa)
+    torch.cuda.synchronize()
+    assert _same(ys, ys_ref) and _same(xa, xa_ref)
+
+
+def test_batch_errors():
+    from paper_2106_00554_amd import _abi
+    from paper_2106_00554_amd.operator import Wh2WavBatch
+    with pytest.raises(_abi.Wh2WavError, match="instance 1"):
+        Wh2WavBatch([dict(dim=2, nu=4, j=5, q=1, j0=3), dict(dim=2, nu=4, j=5, q=0, j0=3)])
+    b = Wh2WavBatch([dict(dim=1, nu=2, j=6, q=1, j0=2)])
+    with pytest.raises(_abi.Wh2WavError):
+        b.set_schedule(9, 0)
+    b.close()
