@@ -8,13 +8,23 @@ This is the HBM-roofline configuration of the method; inputs are synthetic
 (seeded image-like wavelet coefficients, see tests/inputs.py).
 
 One step = one forward y = P_Omega A x followed by one adjoint A^T P_Omega^T y
-of that y, inputs resident in HBM.  The path runs stage by stage through the
-C ABI (wh2wav_forward_stage / wh2wav_adjoint_stage, which together are
-exactly wh2wav_forward / wh2wav_adjoint) with HIP events recorded between the
-stages on the launch stream, so the per-kernel durations used for the
-roofline are measured inside the timed region.
+of that y, inputs resident in HBM.  The path runs through the C ABI stage by
+stage (wh2wav_forward_stage / wh2wav_adjoint_stage, which together are exactly
+wh2wav_forward / wh2wav_adjoint).  During warm-up every stage is timed once
+with HIP events; in the timed region two events per step bracket the
+dominant stage only, on the launch stream, which gives the per-launch
+duration used for the roofline.
+
+Two more legs are reported in the same JSON line (skip with --no-extras):
+* "autograd": the 1024^2 db4 q=1 FP32 operator (25 % Omega) through the
+  torch.autograd.Function (gradient of 0.5 ||P A x - y||^2 by backward), the
+  plain pair on the same operator, and 200 FISTA iterations;
+* "batched": 96 uneven instances (1D 2^12..2^16, 2D 128^2..512^2 and 1024^2,
+  db2/db4/db8, q = 1, 2, 10-30 % Omega, FP32) as one graph launch per
+  direction after the schedule autotuner, against per-instance plain calls.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,12 +38,13 @@ HBM_PEAK_GBS = 8000.0
 
 def stage_bytes(w, m, elem):
     """Algorithmic HBM bytes per launch of each 2D stage (reads + writes, once each)."""
-    M, N = 1 << w["j"], 1 << (w["j"] + w["q"])
-    omega_bytes = (0 if m == N * N else N * N // 8) + 8 * (N + 1)
+    M, N, Q = 1 << w["j"], 1 << (w["j"] + w["q"]), 1 << w["q"]
+    # sample list: a 16-bit natural position per sample and an offset per (row, phase)
+    omega_bytes = 0 if m == N * N else 2 * m + 8 * (N * Q + 1)
     return {
         ("fwd", 0): 2 * M * M * elem,                       # x in, B_phi coefficients out
         ("fwd", 1): (M * M + M * N) * elem,                 # column pass: xi in, N x M intermediate out
-        ("fwd", 2): (M * N + m) * elem + omega_bytes,       # row pass: intermediate in, y out, Omega mask
+        ("fwd", 2): (M * N + m) * elem + omega_bytes,       # row pass: intermediate in, y out, sample list
         ("adj", 0): (m + N * M) * elem + omega_bytes,       # row pass: y in, intermediate out
         ("adj", 1): (N * M + M * M) * elem,                 # column pass
         ("adj", 2): 2 * M * M * elem,                       # DWT
@@ -42,6 +53,33 @@ def stage_bytes(w, m, elem):
 
 STAGE_NAMES = {("fwd", 0): "idwt", ("fwd", 1): "column_pass_fwd", ("fwd", 2): "row_pass_fwd_gather",
                ("adj", 0): "row_pass_adj_scatter", ("adj", 1): "column_pass_adj", ("adj", 2): "dwt"}
+# the kernel each 2D stage launches (the wavelet stages launch one kernel per level)
+STAGE_KERNELS = {("fwd", 1): "k_colpass_fwd", ("fwd", 2): "k_rowpass_fwd", ("adj", 0): "k_rowpass_adj",
+                 ("adj", 1): "k_colpass_adj"}
+
+
+def source_digest():
+    """Digest of the kernel sources: traffic counters are only valid for the code they measured."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2106_00554_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel, workload):
+    """HBM bytes per launch from the committed counter summary, if it matches these sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_digest") != source_digest() or rec.get("workload") != workload:
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
 
 
 def cpu_baseline(name, X, omega, budget_s):
@@ -78,6 +116,98 @@ def cpu_baseline(name, X, omega, budget_s):
                       f"per-entry times ({tf * 1e3:.2f} ms, {ta:.2f} s)"}
 
 
+def timed(fn, steps, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def autograd_leg(torch, steps):
+    from paper_2106_00554_amd import autograd as ag
+    from paper_2106_00554_amd.operator import Wh2Wav
+    from tests import inputs
+
+    name = "2d_db4_j10_q1_25pct"
+    w = inputs.WORKLOADS[name]
+    Xt, omega = inputs.workload_inputs(name)
+    opr = Wh2Wav(2, w["j"], w["q"], w["nu"], w["j0"], torch.float32, omega)
+    xt = torch.tensor(Xt, dtype=torch.float32, device="cuda")
+    y0 = opr.forward(xt)
+    noise = torch.tensor(inputs.sample_vector(opr.m, 4001), dtype=torch.float32, device="cuda")
+    y = y0 + 0.01 * y0.norm() / noise.norm() * noise
+    x = torch.zeros(opr.x_shape, dtype=torch.float32, device="cuda", requires_grad=True)
+    ybuf = torch.empty_like(y)
+    xbuf = torch.empty_like(xt)
+
+    def plain():
+        opr.forward(xt, out=ybuf)
+        opr.adjoint(ybuf, out=xbuf)
+
+    def grad():
+        r = ag.forward(opr, x) - y
+        loss = 0.5 * torch.dot(r, r)
+        loss.backward()
+
+    for _ in range(3):
+        plain()
+        grad()
+    t_plain = timed(plain, steps, torch)
+    t_grad = timed(grad, steps, torch)
+    lam = 0.01 * float(opr.adjoint(y).abs().max())
+    ag.fista(opr, y, lam, 3)  # warm-up
+    torch.cuda.synchronize()
+    iters = 200
+    t0 = time.perf_counter()
+    xr = ag.fista(opr, y, lam, iters)
+    torch.cuda.synchronize()
+    t_fista = time.perf_counter() - t0
+    err = float((xr - xt).norm() / xt.norm())
+    return {"workload": name, "plain_pairs_per_s": 1.0 / t_plain, "autograd_grads_per_s": 1.0 / t_grad,
+            "fista_iters": iters, "fista_iters_per_s": iters / t_fista, "fista_lambda": lam,
+            "fista_rel_error_vs_x_true": err}
+
+
+def batched_leg(torch, steps):
+    from paper_2106_00554_amd.operator import Wh2Wav, Wh2WavBatch
+    from tests import inputs
+
+    specs = inputs.batch_specs()
+    full = []
+    for sp in specs:
+        x, omega = inputs.batch_instance(sp)
+        full.append((dict(dim=sp["dim"], nu=sp["nu"], j=sp["j"], q=sp["q"], j0=sp["j0"],
+                          dtype=torch.float32, omega=omega), x))
+    batch = Wh2WavBatch([f for f, _ in full])
+    singles = [Wh2Wav(f["dim"], f["j"], f["q"], f["nu"], f["j0"], f["dtype"], f["omega"]) for f, _ in full]
+    xs = [torch.tensor(x, dtype=torch.float32, device="cuda") for _, x in full]
+    ys = batch.new_outputs(0)
+    xa = batch.new_outputs(1)
+    best_ms = batch.tune(xs, ys, xa, reps=2)
+    sched = batch.schedule()
+
+    def batched():
+        batch.forward(xs, ys)
+        batch.adjoint(ys, xa)
+
+    def plain():
+        for s, x, y, z in zip(singles, xs, ys, xa):
+            s.forward(x, out=y)
+            s.adjoint(y, out=z)
+
+    batched()
+    plain()
+    t_b = timed(batched, steps, torch)
+    t_p = timed(plain, max(1, steps // 2), torch)
+    n = len(specs)
+    return {"instances": n, "groups": "32 x 1D 2^12..2^16, 32 x 2D 128^2..512^2, 32 x 2D 1024^2",
+            "pairs_per_s": n / t_b, "plain_pairs_per_s": n / t_p, "speedup_vs_plain": t_p / t_b,
+            "ms_per_batch_pair": t_b * 1e3, "schedule": {"branches": sched[0], "order": sched[1]},
+            "tuned_ms": best_ms}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +216,7 @@ def main():
     ap.add_argument("--workload", default="2d_db8_j11_q2_12.5pct")
     ap.add_argument("--dtype", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -118,31 +249,45 @@ def main():
     na = _abi.wh2wav_stage_count(opr._plan, 1)
     keys = [("fwd", s) for s in range(nf)] + [("adj", s) for s in range(na)]
 
-    def step(events=None):
-        for i, (d, s) in enumerate(keys):
-            if events is not None:
-                events[i].record(stream)
-            if d == "fwd":
-                _abi.wh2wav_forward_stage(opr._plan, s, x.data_ptr(), y.data_ptr(), ws, sp)
-            else:
-                _abi.wh2wav_adjoint_stage(opr._plan, s, y.data_ptr(), xa.data_ptr(), ws, sp)
-        if events is not None:
-            events[-1].record(stream)
+    def run_stage(key):
+        d, s = key
+        if d == "fwd":
+            _abi.wh2wav_forward_stage(opr._plan, s, x.data_ptr(), y.data_ptr(), ws, sp)
+        else:
+            _abi.wh2wav_adjoint_stage(opr._plan, s, y.data_ptr(), xa.data_ptr(), ws, sp)
 
-    for _ in range(args.warmup):
-        step()
+    # warm-up; the last warm-up step times every stage to find the dominant one
+    for _ in range(max(0, args.warmup - 1)):
+        for key in keys:
+            run_stage(key)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(keys) + 1)]
+    for i, key in enumerate(keys):
+        evs[i].record(stream)
+        run_stage(key)
+    evs[-1].record(stream)
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(keys) + 1)] for _ in range(args.steps)]
+    warm_stage = {key: evs[i].elapsed_time(evs[i + 1]) for i, key in enumerate(keys)}
+    dom = max(warm_stage, key=warm_stage.get)
+
+    begin = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    end = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(evs[k])
+        for key in keys:
+            if key == dom:
+                begin[k].record(stream)
+                run_stage(key)
+                end[k].record(stream)
+            else:
+                run_stage(key)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    per_stage = {key: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs])) for i, key in enumerate(keys)}
+    dom_ms = float(np.mean([b.elapsed_time(e) for b, e in zip(begin, end)]))
     nbytes = stage_bytes(w, opr.m, elem)
-    dom = max(per_stage, key=per_stage.get)
-    achieved = nbytes[dom] / (per_stage[dom] * 1e-3) / 1e9
+    achieved = nbytes[dom] / (dom_ms * 1e-3) / 1e9
+    kernel = STAGE_KERNELS.get(dom, STAGE_NAMES[dom])
+    traffic = traffic_for(kernel, name) if dtype == torch.float32 else None
     out = {
         "metric": "forward+adjoint matvec pairs/sec",
         "value": args.steps / elapsed,
@@ -158,11 +303,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": name, "dim": w["dim"], "wavelet": f"db{w['nu']}", "M": 1 << w["j"],
                    "N": 1 << (w["j"] + w["q"]), "q": w["q"], "omega_density": w["density"], "m": opr.m},
-        "stages_ms": {STAGE_NAMES.get(k, str(k)): round(v, 4) for k, v in per_stage.items()},
-        "roofline": {"bound": "hbm", "kernel": STAGE_NAMES.get(dom, str(dom)), "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None},
+        "stages_ms_warmup": {STAGE_NAMES[k]: round(v, 4) for k, v in warm_stage.items()},
+        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes": nbytes[dom], "launch_ms": dom_ms},
     }
+    if not args.no_extras:
+        out["autograd"] = autograd_leg(torch, max(5, args.steps // 2))
+        out["batched"] = batched_leg(torch, max(3, args.steps // 5))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(name, X, omega, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -148,3 +148,37 @@ def workload_inputs(name):
         x = coefficients_2d(w["j"], w["j0"], w["seed"])
         omega = None if w["density"] >= 1 else multilevel_omega_2d(N, w["density"], w["seed"] + 1)
     return x, omega
+
+
+def batch_specs(seed=5000, count=96):
+    """The uneven batch: instance i of three groups of count/3, FP32.
+
+    group 1: 1D, j = 12 + (i mod 5); group 2: 2D, j = 7 + (i mod 3);
+    group 3: 2D, j = 10.  Daubechies order nu = (2, 4, 8)[i mod 3],
+    q = 1 + floor(i / 3) mod 2, multilevel Omega of density ~ U[0.10, 0.30]
+    with its own seed.  Returns a list of dicts (dim, nu, j, q, j0, density,
+    seed) and leaves the arrays to `batch_instance`.
+    """
+    rng = rng_for(seed)
+    per = count // 3
+    specs = []
+    for i in range(count):
+        g = i // per
+        nu = (2, 4, 8)[i % 3]
+        q = 1 + (i // 3) % 2
+        j = (12 + i % 5) if g == 0 else (7 + i % 3) if g == 1 else 10
+        j0 = max(1, (2 * nu - 1).bit_length())
+        specs.append(dict(dim=1 if g == 0 else 2, nu=nu, j=j, q=q, j0=j0,
+                          density=float(rng.uniform(0.10, 0.30)), seed=seed + 10 * (i + 1)))
+    return specs
+
+
+def batch_instance(spec):
+    """(x, omega) of one batch instance."""
+    N = 1 << (spec["j"] + spec["q"])
+    if spec["dim"] == 1:
+        return (coefficients_1d(spec["j"], spec["j0"], spec["seed"]),
+                multilevel_omega_1d(N, spec["density"], spec["seed"] + 1))
+    return (coefficients_2d(spec["j"], spec["j0"], spec["seed"]),
+            multilevel_omega_2d(N, spec["density"], spec["seed"] + 1))
+
