@@ -218,6 +218,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="copy MIB MiB device-to-device once before the run (a kernel of known traffic "
+                         "for scaling hardware counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -255,6 +258,15 @@ def main():
             _abi.wh2wav_forward_stage(opr._plan, s, x.data_ptr(), y.data_ptr(), ws, sp)
         else:
             _abi.wh2wav_adjoint_stage(opr._plan, s, y.data_ptr(), xa.data_ptr(), ws, sp)
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # warm-up; the last warm-up step times every stage to find the dominant one
     for _ in range(max(0, args.warmup - 1)):
