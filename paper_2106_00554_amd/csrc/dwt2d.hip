@@ -5,11 +5,12 @@
 // S X S^T, S the one-level synthesis matrix (interior columns: the filters h, g
 // at stride 2; boundary columns: the dense blocks built by the planner).  The
 // transpose (the forward DWT) is S^T X S.
-//   * Coarse levels (block <= 128 x 128 in FP32, 64 x 64 in FP64) run in one
-//     workgroup with the block in LDS.
-//   * Each finer level is one launch over 2D output tiles: a tile loads the
-//     input window it depends on (both halves, both directions), filters the
-//     rows, then the columns, in LDS.
+//   * Levels with an output block of at most 8 x 8 run in one workgroup with
+//     the block in LDS.
+//   * Every larger level is one launch over 2D output tiles (16 x 16 up to
+//     64 x 64 by level size): a tile loads the input window it depends on
+//     (both halves, both directions), filters the rows, then the columns, in
+//     LDS.
 //   * The last synthesis level writes xi^T (the layout the column pass reads);
 //     the first analysis level reads xi'^T (the layout the adjoint column pass
 //     writes) and stores the detail bands straight into x.
@@ -20,6 +21,21 @@ namespace {
 
 using namespace lines;
 
+
+// Largest input window (coefficients per half and direction) of a tile.
+// Synthesis: interior tiles read TS/2 + nu + 1 coefficients; a tile that
+// holds one of the first or last 3nu-1 outputs also reads every coefficient
+// back to that end, which stays within the interior bound when 3nu-1 <= TS
+// and within TS/2 + 3nu otherwise.  Analysis: 2 TH + 2nu - 1 inside; at most
+// 2 TH + 3nu at an end when TH < nu.
+template <int NU, int TS>
+__host__ __device__ constexpr int synth_window_max() {
+  return 3 * NU - 1 <= TS ? TS / 2 + NU + 2 : TS / 2 + 3 * NU;
+}
+template <int NU, int TH>
+__host__ __device__ constexpr int analysis_window_max() {
+  return NU <= TH ? 2 * TH + 2 * NU + 4 : 2 * TH + 3 * NU;
+}
 
 // Tile t of an n x n grid: the ring of tiles along the edges (which hold the
 // boundary functions and take longest) is dispatched first.
@@ -55,7 +71,7 @@ __global__ void __launch_bounds__(256) k_synth2d_tile(const T* __restrict__ ll, 
   extern __shared__ unsigned char smem_raw[];
   __shared__ T tab_lds[tab_lds_size<NU>()];
   T hr[2 * NU], gr[2 * NU];
-  const TileLds<T> tl = load_tables<T, NU>(t, tab_lds, hr, gr);
+  TileLds<T> tl;
   const int half = 1 << k, size = 2 * half;
   const int ntile = size / TS;
   int tr, tc;
@@ -72,7 +88,7 @@ __global__ void __launch_bounds__(256) k_synth2d_tile(const T* __restrict__ ll, 
   const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
   {
     // all loads of the window are issued before any is consumed
-    constexpr int MAXR = 2 * (TS / 2 + NU + 2), RI = (MAXR + 3) / 4, CJ = (MAXR + 63) / 64;
+    constexpr int MAXR = 2 * synth_window_max<NU, TS>(), RI = (MAXR + 3) / 4, CJ = (MAXR + 63) / 64;
     T r[RI][CJ];
 #pragma unroll
     for (int ii = 0; ii < RI; ++ii) {
@@ -88,6 +104,8 @@ __global__ void __launch_bounds__(256) k_synth2d_tile(const T* __restrict__ ll, 
         r[ii][jj] = v;
       }
     }
+    // the tables load while the window loads are in flight
+    tl = load_tables<T, NU>(t, tab_lds, hr, gr);
 #pragma unroll
     for (int ii = 0; ii < RI; ++ii) {
       const int i = wave + 4 * ii;
@@ -158,7 +176,7 @@ __global__ void __launch_bounds__(256) k_analysis2d_tile(const T* __restrict__ i
   extern __shared__ unsigned char smem_raw[];
   __shared__ T tab_lds[tab_lds_size<NU>()];
   T hr[2 * NU], gr[2 * NU];
-  const TileLds<T> tl = load_tables<T, NU>(t, tab_lds, hr, gr);
+  TileLds<T> tl;
   const int half = 1 << k;
   const int ntile = half / TH;
   int tr, tc;
@@ -175,7 +193,7 @@ __global__ void __launch_bounds__(256) k_analysis2d_tile(const T* __restrict__ i
   const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
   {
     // outer index over waves, inner over lanes (the contiguous direction of `in`)
-    constexpr int MAXR = 2 * TH + 2 * NU + 4, OI = (MAXR + 3) / 4, IJ = (MAXR + 63) / 64;
+    constexpr int MAXR = analysis_window_max<NU, TH>(), OI = (MAXR + 3) / 4, IJ = (MAXR + 63) / 64;
     const int no = trans ? nc : nr, ni = trans ? nr : nc;
     const int64_t ob = trans ? clo : rlo, ib = trans ? rlo : clo;
     T r[OI][IJ];
@@ -188,6 +206,8 @@ __global__ void __launch_bounds__(256) k_analysis2d_tile(const T* __restrict__ i
         r[u][v] = (a < no && b < ni) ? in[(ob + a) * ld_in + ib + b] : T(0);
       }
     }
+    // the tables load while the window loads are in flight
+    tl = load_tables<T, NU>(t, tab_lds, hr, gr);
 #pragma unroll
     for (int u = 0; u < OI; ++u) {
       const int a = wave + 4 * u;
@@ -441,7 +461,10 @@ __global__ void __launch_bounds__(1024) k_analysis2d_coarse(const T* __restrict_
 
 template <typename T>
 constexpr int coarse_limit() {
-  return sizeof(T) == 4 ? 7 : 6;  // log2 of the largest block kept in LDS
+  // log2 of the largest block the one-workgroup kernel handles: every level
+  // with a 16 x 16 or larger output runs as a multi-workgroup tile launch,
+  // since one workgroup issues from a single CU
+  return 3;
 }
 
 // Largest input window (rows of one half) over the tiles of a level, from
@@ -469,9 +492,18 @@ int max_analysis_window(int half, int th) {
 
 // Tile shapes: large tiles with long register runs where a level has enough
 // tiles to fill the chip, small tiles (more workgroups) on coarser levels.
+// Tile shapes per level: large tiles with long register runs where a level
+// has enough tiles to fill the chip, smaller ones (more workgroups) on
+// coarser levels.
 template <typename T>
-constexpr bool big_tiles(int size) {
-  return sizeof(T) == 4 && size >= 2048;
+constexpr int synth_tile(int size) {
+  if (sizeof(T) == 4) return size >= 2048 ? 64 : size >= 256 ? 32 : 16;
+  return size >= 256 ? 32 : 16;
+}
+template <typename T>
+constexpr int analysis_tile(int half) {
+  if (sizeof(T) == 4) return half >= 1024 ? 32 : half >= 128 ? 16 : 8;
+  return half >= 128 ? 16 : 8;
 }
 
 template <typename T, int NU, int TS, int P>
@@ -480,7 +512,7 @@ hipError_t launch_synth(const T* ll, const T* det, T* dst, int64_t M, int k, int
   const int half = 1 << k, size = 2 * half;
   if (size % TS) return hipErrorInvalidValue;
   const int nr = max_synth_window<NU>(half, TS);
-  if (2 * nr > 2 * (TS / 2 + NU + 2)) return hipErrorInvalidValue;  // the kernel's load window
+  if (nr > synth_window_max<NU, TS>()) return hipErrorInvalidValue;  // the kernel's load window
   const size_t smem = (size_t(2 * nr) * (2 * nr + 1) + size_t(2 * nr) * (TS + 1)) * sizeof(T);
   const int ntile = size / TS;
   hipLaunchKernelGGL((k_synth2d_tile<T, NU, TS, P>), dim3(unsigned(ntile * ntile)), dim3(256), smem, st, ll, M, det,
@@ -494,7 +526,7 @@ hipError_t launch_analysis(const T* src, int trans, T* dst, T* x, int64_t M, int
   const int half = 1 << k;
   if (half % TH) return hipErrorInvalidValue;
   const int nr = max_analysis_window<NU>(half, TH);
-  if (nr > 2 * TH + 2 * NU + 4) return hipErrorInvalidValue;  // the kernel's load window
+  if (nr > analysis_window_max<NU, TH>()) return hipErrorInvalidValue;  // the kernel's load window
   const size_t smem = (size_t(nr) * (nr + 1) + size_t(nr) * (2 * TH + 1)) * sizeof(T);
   const int ntile = half / TH;
   hipLaunchKernelGGL((k_analysis2d_tile<T, NU, TH, P>), dim3(unsigned(ntile * ntile)), dim3(256), smem, st, src, M,
@@ -524,10 +556,13 @@ hipError_t idwt2d_impl(const T* x, T* outT, T* s0, T* s1, int64_t M, int j0, int
   for (int k = kc; k < j; ++k) {
     const bool fin = k == j - 1;
     T* dst = fin ? outT : (ll == s0 ? s1 : s0);
-    if (big_tiles<T>(2 << k))
+    const int ts = synth_tile<T>(2 << k);
+    if (ts == 64)
       e = launch_synth<T, NU, 64, 8>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
-    else
+    else if (ts == 32)
       e = launch_synth<T, NU, 32, 2>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
+    else
+      e = launch_synth<T, NU, 16, 2>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
     if (e != hipSuccess) return e;
     ll = dst;
   }
@@ -546,10 +581,13 @@ hipError_t dwt2d_impl(const T* inT, T* x, T* s0, T* s1, int64_t M, int j0, int j
   for (int k = j - 1; k >= kc; --k) {
     // without a coarse stage the last tiled level writes LL_{j0} into x itself
     T* dst = (!coarse && k == kc) ? x : ((src == s0) ? s1 : s0);
-    if (big_tiles<T>(2 << k))
+    const int th = analysis_tile<T>(1 << k);
+    if (th == 32)
       e = launch_analysis<T, NU, 32, 8>(src, trans, dst, x, M, k, t, st);
-    else
+    else if (th == 16)
       e = launch_analysis<T, NU, 16, 2>(src, trans, dst, x, M, k, t, st);
+    else
+      e = launch_analysis<T, NU, 8, 2>(src, trans, dst, x, M, k, t, st);
     if (e != hipSuccess) return e;
     src = dst;
     trans = 0;
@@ -569,7 +607,8 @@ hipError_t prepare_impl() {
   const void* kernels[] = {
       (const void*)k_synth2d_coarse<T, NU>,         (const void*)k_analysis2d_coarse<T, NU>,
       (const void*)k_synth2d_tile<T, NU, 64, 8>,    (const void*)k_synth2d_tile<T, NU, 32, 2>,
-      (const void*)k_analysis2d_tile<T, NU, 32, 8>, (const void*)k_analysis2d_tile<T, NU, 16, 2>,
+      (const void*)k_synth2d_tile<T, NU, 16, 2>,    (const void*)k_analysis2d_tile<T, NU, 32, 8>,
+      (const void*)k_analysis2d_tile<T, NU, 16, 2>, (const void*)k_analysis2d_tile<T, NU, 8, 2>,
   };
   for (const void* f : kernels) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
