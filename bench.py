@@ -217,6 +217,8 @@ def main():
     ap.add_argument("--dtype", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--only", choices=["batched", "autograd"], default=None,
+                    help="run one extra leg alone (for profiling) and print its JSON")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy MIB MiB device-to-device once before the run (a kernel of known traffic "
@@ -230,6 +232,11 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.only:
+        leg = batched_leg if args.only == "batched" else autograd_leg
+        print(json.dumps({args.only: leg(torch, max(3, args.steps // 5))}), flush=True)
+        return
 
     from paper_2106_00554_amd import _abi
     from paper_2106_00554_amd.operator import Wh2Wav
