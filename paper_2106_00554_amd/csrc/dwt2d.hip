@@ -534,9 +534,20 @@ hipError_t launch_analysis(const T* src, int trans, T* dst, T* x, int64_t M, int
   return hipGetLastError();
 }
 
+// No wavelet level (j0 == j): the coefficients are the scaling coefficients
+// themselves; `out` = `in` transposed (the layout the line passes use).
+template <typename T, int NU>
+hipError_t copy_transposed(const T* in, T* out, int64_t M, int j, const Tables<T>& t, hipStream_t st) {
+  if (M >= 32) return transpose<T>(in, out, M, st);
+  const size_t smem = 2 * size_t(M) * (M + 1) * sizeof(T);
+  hipLaunchKernelGGL((k_synth2d_coarse<T, NU>), dim3(1), dim3(1024), smem, st, in, M, out, M, j, j, 1, t);
+  return hipGetLastError();
+}
+
 template <typename T, int NU>
 hipError_t idwt2d_impl(const T* x, T* outT, T* s0, T* s1, int64_t M, int j0, int j, const Tables<T>& t,
                        hipStream_t st) {
+  if (j0 == j) return copy_transposed<T, NU>(x, outT, M, j, t, st);
   // Coarse levels in one workgroup, unless the coarsest block is already too
   // large for LDS (then the first tiled level reads LL_{j0} from x).
   const bool coarse = j0 < coarse_limit<T>();
@@ -572,6 +583,7 @@ hipError_t idwt2d_impl(const T* x, T* outT, T* s0, T* s1, int64_t M, int j0, int
 template <typename T, int NU>
 hipError_t dwt2d_impl(const T* inT, T* x, T* s0, T* s1, int64_t M, int j0, int j, const Tables<T>& t,
                       hipStream_t st) {
+  if (j0 == j) return copy_transposed<T, NU>(inT, x, M, j, t, st);
   const bool coarse = j0 < coarse_limit<T>();
   const int kc = coarse ? (j < coarse_limit<T>() ? j : coarse_limit<T>()) : j0;
   const int S = 1 << kc;

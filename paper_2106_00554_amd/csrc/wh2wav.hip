@@ -542,18 +542,8 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
   T* TMP = W + M * M;
   T* Z = TMP + M * M;
   const bool fast = use_fast(p);
-  if (fast && run(0))  // xi^T into TMP; W and Z serve as scratch
+  if (run(0))  // xi^T into TMP (tiled 2D wavelet kernels, every shape); W and Z serve as scratch
     HIP_OK(wh2wav_fast::idwt2d<T>(x, TMP, W, Z, M, H.j0, H.j, fast_tables_of<T>(p), st));
-  if (!fast && run(0)) {
-    HIP_OK(hipMemcpyAsync(W, x, sizeof(T) * M * M, hipMemcpyDeviceToDevice, st));
-    for (int k = H.j0; k < H.j; ++k) {
-      const int64_t size = int64_t(2) << k;
-      int rc = launch_synth<T>(p, W, TMP, size, M, 1, k, false, false, st);  // rows
-      if (rc) return rc;
-      rc = launch_synth<T>(p, TMP, W, size, 1, M, k, true, false, st);      // columns
-      if (rc) return rc;
-    }
-  }
   if (fast) {
     if (run(1)) HIP_OK(wh2wav_fast::colpass_fwd<T>(TMP, Z, H.j, fast_tables_of<T>(p), st));
     if (run(2)) HIP_OK(wh2wav_fast::rowpass_fwd<T>(Z, y, H.j, fast_tables_of<T>(p), fast_omega_of(p), st));
@@ -561,9 +551,9 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
   }
   int rc = check_and_set_smem<T>((const void*)k_fwd_lines<T>, line_smem(p, sizeof(T), true));
   if (rc) return rc;
-  if (run(1)) {  // column pass: G along the first index; Z[r, m2] with r natural
+  if (run(1)) {  // column pass: G along the first index (rows of xi^T); Z[r, m2] with r natural
     size_t smem0 = line_smem(p, sizeof(T), false);
-    hipLaunchKernelGGL(k_fwd_lines<T>, dim3(unsigned(M)), dim3(kThreads), smem0, st, W, 1, M, Z, 1, M, H.j, 0,
+    hipLaunchKernelGGL(k_fwd_lines<T>, dim3(unsigned(M)), dim3(kThreads), smem0, st, TMP, M, 1, Z, 1, M, H.j, 0,
                        0, t, om);
     HIP_OK(hipGetLastError());
   }
@@ -637,22 +627,13 @@ int adjoint_impl(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t
                        t, om);
     HIP_OK(hipGetLastError());
   }
-  if (run(1)) {
+  if (run(1)) {  // column pass, transposed: xi'^T into TMP
     size_t smem0 = line_smem(p, sizeof(T), false);
-    hipLaunchKernelGGL(k_adj_lines<T>, dim3(unsigned(M)), dim3(kThreads), smem0, st, Z, 1, M, W, 1, M, H.j, 0,
+    hipLaunchKernelGGL(k_adj_lines<T>, dim3(unsigned(M)), dim3(kThreads), smem0, st, Z, 1, M, TMP, M, 1, H.j, 0,
                        0, t, om);
     HIP_OK(hipGetLastError());
   }
-  if (run(2)) {
-    for (int k = H.j - 1; k >= H.j0; --k) {
-      const int64_t size = int64_t(2) << k;
-      rc = launch_synth<T>(p, W, TMP, size, 1, M, k, true, true, st);  // columns
-      if (rc) return rc;
-      rc = launch_synth<T>(p, TMP, W, size, M, 1, k, false, true, st);  // rows
-      if (rc) return rc;
-    }
-    HIP_OK(hipMemcpyAsync(x, W, sizeof(T) * M * M, hipMemcpyDeviceToDevice, st));
-  }
+  if (run(2)) HIP_OK(wh2wav_fast::dwt2d<T>(TMP, x, W, Z, M, H.j0, H.j, fast_tables_of<T>(p), st));
   return WH2WAV_OK;
 }
 
@@ -730,10 +711,10 @@ int wh2wav_plan(const wh2wav_desc* desc, wh2wav_plan_t* out) {
     delete p;
     return fail(rc, m);
   }
-  if (use_fast(p)) {
+  if (H.dim == 2) {
     hipError_t e = H.dtype == WH2WAV_F64 ? wh2wav_fast::prepare_dwt2d<double>(H.nu)
                                          : wh2wav_fast::prepare_dwt2d<float>(H.nu);
-    if (e == hipSuccess)
+    if (e == hipSuccess && use_fast(p))
       e = H.dtype == WH2WAV_F64 ? wh2wav_fast::prepare_lines<double>(H.j, H.nu)
                                 : wh2wav_fast::prepare_lines<float>(H.j, H.nu);
     if (e != hipSuccess) {

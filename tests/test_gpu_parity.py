@@ -68,6 +68,7 @@ CASES_2D = [
     (2, 2, 1, 2, None), (2, 4, 1, 2, 0.25), (2, 5, 2, 2, 0.1),
     (3, 3, 2, 3, 0.5), (4, 3, 1, 3, None), (4, 5, 1, 3, 0.25),
     (6, 5, 1, 4, 0.3), (8, 4, 2, 4, 0.2), (8, 6, 1, 4, 0.125),
+    (2, 5, 1, 5, 0.3),  # no wavelet level (j0 = j) at M = 32
 ]
 
 
