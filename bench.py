@@ -170,6 +170,41 @@ def autograd_leg(torch, steps):
             "fista_rel_error_vs_x_true": err}
 
 
+def small_configs_leg(torch, steps):
+    """The 1D db4 2^10 q=1 FP64 and 2D db4 512^2 q=1 (25 % Omega) workloads: us per pair and
+    effective GB/s (algorithmic bytes of a pair over its time; these working sets fit in the
+    last-level cache, so this is not an HBM figure)."""
+    from paper_2106_00554_amd.operator import Wh2Wav
+    from tests import inputs
+
+    out = {}
+    for name, dtype in (("1d_db4_j10_q1", torch.float64), ("2d_db4_j9_q1_25pct", torch.float32),
+                        ("2d_db4_j9_q1_25pct", torch.float64)):
+        w = inputs.WORKLOADS[name]
+        X, omega = inputs.workload_inputs(name)
+        opr = Wh2Wav(w["dim"], w["j"], w["q"], w["nu"], w["j0"], dtype, omega)
+        x = torch.tensor(X, dtype=dtype, device="cuda")
+        y = torch.empty(opr.m, dtype=dtype, device="cuda")
+        xa = torch.empty_like(x)
+
+        def pair():
+            opr.forward(x, out=y)
+            opr.adjoint(y, out=xa)
+
+        for _ in range(5):
+            pair()
+        t = timed(pair, max(20, steps), torch)
+        elem = 8 if dtype == torch.float64 else 4
+        M, N = opr.M, opr.N
+        if w["dim"] == 1:
+            nbytes = 2 * (M + opr.m) * elem
+        else:
+            nbytes = 2 * (M * M + opr.m + 2 * M * N + 2 * M * M) * elem
+        out[f"{name}_{'f64' if elem == 8 else 'f32'}"] = {"us_per_pair": t * 1e6, "pairs_per_s": 1.0 / t,
+                                                            "effective_GBs": nbytes / t / 1e9}
+    return out
+
+
 def batched_leg(torch, steps):
     from paper_2106_00554_amd.operator import Wh2Wav, Wh2WavBatch
     from tests import inputs
@@ -217,7 +252,7 @@ def main():
     ap.add_argument("--dtype", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--only", choices=["batched", "autograd"], default=None,
+    ap.add_argument("--only", choices=["batched", "autograd", "small"], default=None,
                     help="run one extra leg alone (for profiling) and print its JSON")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -234,7 +269,7 @@ def main():
     import torch
 
     if args.only:
-        leg = batched_leg if args.only == "batched" else autograd_leg
+        leg = {"batched": batched_leg, "autograd": autograd_leg, "small": small_configs_leg}[args.only]
         print(json.dumps({args.only: leg(torch, max(3, args.steps // 5))}), flush=True)
         return
 
@@ -330,6 +365,7 @@ def main():
     if not args.no_extras:
         out["autograd"] = autograd_leg(torch, max(5, args.steps // 2))
         out["batched"] = batched_leg(torch, max(3, args.steps // 5))
+        out["small_configs"] = small_configs_leg(torch, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(name, X, omega, args.cpu_budget)
     print(json.dumps(out), flush=True)
