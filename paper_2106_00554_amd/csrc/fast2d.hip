@@ -24,18 +24,21 @@ namespace {
 
 using namespace wave;
 
-// Halo: window w[0 .. R+2H) with w[H + r] = x[r]; neighbours' values from the
-// adjacent lanes, zero beyond the ends of the line.
+// Halo: window w[0 .. R+2H) with w[H + r] = x[r]; the H values on each side
+// come from the neighbouring lanes (from several lanes when H > R), zero
+// beyond the ends of the line.  Position p of the line is register p % R of
+// lane p / R.
 template <typename T, int R, int H>
 __device__ __forceinline__ void make_window(const T (&x)[R], T (&w)[R + 2 * H], int lane) {
 #pragma unroll
   for (int r = 0; r < R; ++r) w[H + r] = x[r];
 #pragma unroll
   for (int e = 0; e < H; ++e) {
-    const T a = shfl_from(x[R - 1 - e], (lane - 1) & 63);
-    const T b = shfl_from(x[e], (lane + 1) & 63);
-    w[H - 1 - e] = lane == 0 ? T(0) : a;
-    w[H + R + e] = lane == 63 ? T(0) : b;
+    const int dl = 1 + e / R;  // lane distance of position lane R - 1 - e (left) / lane R + R + e (right)
+    const T a = shfl_from(x[R - 1 - e % R], (lane - dl) & 63);
+    const T b = shfl_from(x[e % R], (lane + dl) & 63);
+    w[H - 1 - e] = lane < dl ? T(0) : a;
+    w[H + R + e] = lane + dl > 63 ? T(0) : b;
   }
 }
 
@@ -82,12 +85,14 @@ __device__ __forceinline__ void line_forward(const T (&xi)[R], T (&v)[R], int s,
   T eL[NU], eR[NU];
 #pragma unroll
   for (int m = 0; m < NU; ++m) {
-    eL[m] = read_lane(xi[m], 0);
-    eR[m] = read_lane(xi[R - 1 - m], 63);
+    // position m: register m % R of lane m / R; position M-1-m: register
+    // R-1-m % R of lane 63 - m / R
+    eL[m] = read_lane(xi[m % R], m / R);
+    eR[m] = read_lane(xi[R - 1 - m % R], 63 - m / R);
     // per-element selects (conditional stores would let the compiler merge
     // them into one dynamically indexed store and move x to scratch)
-    x[m] = lane == 0 ? T(0) : x[m];
-    x[R - 1 - m] = lane == 63 ? T(0) : x[R - 1 - m];
+    x[m % R] = lane == m / R ? T(0) : x[m % R];
+    x[R - 1 - m % R] = lane == 63 - m / R ? T(0) : x[R - 1 - m % R];
   }
   T tap[2 * NU - 1];
 #pragma unroll
@@ -105,8 +110,10 @@ __device__ __forceinline__ void line_forward(const T (&xi)[R], T (&v)[R], int s,
 #pragma unroll
   for (int e = 0; e < B; ++e) {
     const T a = read_lane(bv, e), b = read_lane(bv, B + e);
-    v[e] += lane == 0 ? a : T(0);
-    v[R - B + e] += lane == 63 ? b : T(0);
+    constexpr int M = 64 * R;
+    const int pr = M - B + e;  // right band position
+    v[e % R] += lane == e / R ? a : T(0);
+    v[pr % R] += lane == pr / R ? b : T(0);
   }
   fwht_wave<T, R>(v, lane);
 }
@@ -127,8 +134,10 @@ __device__ __forceinline__ void line_adjoint(T (&v)[R], T (&acc)[R], T& eacc, in
   T rl[B], rr[B];
 #pragma unroll
   for (int e = 0; e < B; ++e) {
-    rl[e] = read_lane(v[e], 0);
-    rr[e] = read_lane(v[R - B + e], 63);
+    constexpr int M = 64 * R;
+    const int pr = M - B + e;
+    rl[e] = read_lane(v[e % R], e / R);
+    rr[e] = read_lane(v[pr % R], pr / R);
   }
   T el = T(0);
   if (lane < NU) {
@@ -147,8 +156,8 @@ __device__ __forceinline__ void place_edges(T (&acc)[R], T eacc, int lane) {
 #pragma unroll
   for (int m = 0; m < NU; ++m) {
     const T a = read_lane(eacc, m), b = read_lane(eacc, NU + m);
-    acc[m] = lane == 0 ? a : acc[m];
-    acc[R - 1 - m] = lane == 63 ? b : acc[R - 1 - m];
+    acc[m % R] = lane == m / R ? a : acc[m % R];
+    acc[R - 1 - m % R] = lane == 63 - m / R ? b : acc[R - 1 - m % R];
   }
 }
 
@@ -292,6 +301,7 @@ template <typename T, int LOGM, int NU>
 __global__ void __launch_bounds__(1024) k_colpass_fwd(const T* __restrict__ xiT, T* __restrict__ Z, Tables<T> t) {
   constexpr int M = 1 << LOGM, LOG_R = LOGM - 6, R = 1 << LOG_R;
   constexpr int TILE = 16, SP = 64 * 4 + 4;  // staging stride per wave (padded)
+  static_assert(R == 2 || R % 4 == 0, "column pass staging needs R = 2 or a multiple of 4");
   extern __shared__ unsigned char smem_raw[];
   T* stage = reinterpret_cast<T*>(smem_raw);
   const int lane = lane_id();
@@ -306,6 +316,21 @@ __global__ void __launch_bounds__(1024) k_colpass_fwd(const T* __restrict__ xiT,
   load_line<T, R>(xiT + int64_t(c) * M + lane * R, xi);
   line_forward<T, R, NU>(xi, v, s, t, lane);
   const int tid = int(threadIdx.x);
+  if constexpr (R == 2) {
+    // one round: the wave's 128 values, then 128 output rows x 8 column pairs
+    constexpr int SP2 = 2 * 64 + 4;
+    store_line<T, R>(stage + wave * SP2 + lane * 2, v);
+    __syncthreads();
+    const int k = tid >> 3, cp = tid & 7;
+    const T o0 = stage[(2 * cp) * SP2 + k], o1 = stage[(2 * cp + 1) * SP2 + k];
+    T* dst = Z + (int64_t(s) * M + k) * M + tile * TILE + 2 * cp;
+    if constexpr (sizeof(T) == 4) {
+      *reinterpret_cast<float2*>(dst) = make_float2(o0, o1);
+    } else {
+      *reinterpret_cast<double2*>(dst) = make_double2(o0, o1);
+    }
+    return;
+  }
   const int e = tid >> 2, qg = tid & 3;            // 256 output rows x 4 column groups
   const int le = e >> 2, te = e & 3;
 #pragma unroll
@@ -333,6 +358,7 @@ template <typename T, int LOGM, int NU>
 __global__ void __launch_bounds__(512) k_colpass_adj(const T* __restrict__ Zt, T* __restrict__ xiT, Tables<T> t) {
   constexpr int M = 1 << LOGM, LOG_R = LOGM - 6, R = 1 << LOG_R;
   constexpr int TILE = 8, SP = 64 * 4 + 4;
+  static_assert(R == 2 || R % 4 == 0, "column pass staging needs R = 2 or a multiple of 4");
   extern __shared__ unsigned char smem_raw[];
   T* stage = reinterpret_cast<T*>(smem_raw);
   const int lane = lane_id();
@@ -351,7 +377,28 @@ __global__ void __launch_bounds__(512) k_colpass_adj(const T* __restrict__ Zt, T
   T eacc = T(0);
   for (int s = 0; s < Q; ++s) {
     T v[R];
-    T o[R / 4][4];  // every load of the phase is issued before the exchange rounds
+    if constexpr (R == 2) {
+      // one round: 128 input rows x 4 column pairs
+      constexpr int SP2 = 2 * 64 + 4;
+      const int k = tid >> 2, cp = tid & 3;
+      const T* src = Zt + (int64_t(s) * M + k) * M + tile * TILE + 2 * cp;
+      T o0, o1;
+      if constexpr (sizeof(T) == 4) {
+        const float2 f = *reinterpret_cast<const float2*>(src);
+        o0 = f.x, o1 = f.y;
+      } else {
+        const double2 f = *reinterpret_cast<const double2*>(src);
+        o0 = f.x, o1 = f.y;
+      }
+      stage[(2 * cp) * SP2 + k] = o0;
+      stage[(2 * cp + 1) * SP2 + k] = o1;
+      __syncthreads();
+      load_line<T, R>(stage + wave * SP2 + lane * 2, v);
+      __syncthreads();
+      line_adjoint<T, R, NU>(v, acc, eacc, s, t, lane);
+      continue;
+    }
+    T o[R / 4 > 0 ? R / 4 : 1][4];  // every load of the phase is issued before the exchange rounds
 #pragma unroll
     for (int i = 0; i < R / 4; ++i) {
       const int k = le * R + 4 * i + te;
@@ -424,10 +471,13 @@ hipError_t launch_colpass_adj(const T* Zt, T* xiT, const Tables<T>& t, hipStream
   return hipGetLastError();
 }
 
-// Supported (log2 M, nu): R = M / 64 must hold the boundary band (R >= 2 nu - 1).
-#define WH2WAV_FAST_CASES(X) \
-  X(9, 2) X(9, 3) X(9, 4)    \
-  X(10, 2) X(10, 3) X(10, 4) X(10, 6) X(10, 8) \
+// Supported (log2 M, nu).  Lines of M = 128 .. 2048 values (R = 2 .. 32 per
+// lane); boundary values and the table-product halo may span several lanes.
+#define WH2WAV_FAST_CASES(X)                                   \
+  X(7, 2) X(7, 3) X(7, 4) X(7, 6) X(7, 8)                      \
+  X(8, 2) X(8, 3) X(8, 4) X(8, 6) X(8, 8)                      \
+  X(9, 2) X(9, 3) X(9, 4) X(9, 6) X(9, 8)                      \
+  X(10, 2) X(10, 3) X(10, 4) X(10, 6) X(10, 8)                 \
   X(11, 2) X(11, 3) X(11, 4) X(11, 6) X(11, 8)
 
 }  // namespace

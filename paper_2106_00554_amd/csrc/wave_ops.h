@@ -90,6 +90,13 @@ __device__ __forceinline__ void load_line(const T* __restrict__ src, T (&v)[R]) 
       const float4 f = p[c];
       v[4 * c] = f.x, v[4 * c + 1] = f.y, v[4 * c + 2] = f.z, v[4 * c + 3] = f.w;
     }
+  } else if constexpr (sizeof(T) == 4 && R % 2 == 0) {
+    const float2* p = reinterpret_cast<const float2*>(src);
+#pragma unroll
+    for (int c = 0; c < R / 2; ++c) {
+      const float2 f = p[c];
+      v[2 * c] = f.x, v[2 * c + 1] = f.y;
+    }
   } else if constexpr (sizeof(T) == 8 && R % 2 == 0) {
     const double2* p = reinterpret_cast<const double2*>(src);
 #pragma unroll
@@ -108,6 +115,10 @@ __device__ __forceinline__ void store_line(T* __restrict__ dst, const T (&v)[R])
     float4* p = reinterpret_cast<float4*>(dst);
 #pragma unroll
     for (int c = 0; c < R / 4; ++c) p[c] = make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
+  } else if constexpr (sizeof(T) == 4 && R % 2 == 0) {
+    float2* p = reinterpret_cast<float2*>(dst);
+#pragma unroll
+    for (int c = 0; c < R / 2; ++c) p[c] = make_float2(v[2 * c], v[2 * c + 1]);
   } else if constexpr (sizeof(T) == 8 && R % 2 == 0) {
     double2* p = reinterpret_cast<double2*>(dst);
 #pragma unroll

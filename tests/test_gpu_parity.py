@@ -215,10 +215,15 @@ def test_call_errors_are_reported():
         opr.forward(torch.zeros(16, dtype=torch.float32, device="cuda"))
 
 
-# Sizes and orders served by the wave-level kernels (M = 2^9 .. 2^11).
+# Sizes and orders served by the wave-level kernels (M = 2^7 .. 2^11).  On the
+# short lines (M = 128, 256 and db6/db8 at 512) the boundary values and the
+# table-product halo span several lanes.
 CASES_2D_WAVE = [
     (2, 9, 1, 2, 0.25), (3, 9, 2, 3, None), (4, 9, 3, 3, 0.125),
     (4, 10, 1, 3, None), (6, 10, 1, 4, 0.3), (8, 10, 1, 4, 0.2), (2, 10, 2, 2, 0.15),
+    (2, 7, 1, 2, 0.3), (8, 7, 1, 4, None), (6, 7, 2, 4, 0.25), (4, 7, 3, 3, 0.3),
+    (4, 7, 1, 7, 0.3),  # j0 = j: no wavelet level
+    (3, 8, 1, 3, 0.2), (8, 8, 2, 4, 0.15), (6, 9, 1, 4, 0.2), (8, 9, 1, 4, None),
 ]
 
 
