@@ -8,9 +8,10 @@
 //   * Levels with an output block of at most 8 x 8 run in one workgroup with
 //     the block in LDS.
 //   * Every larger level is one launch over 2D output tiles (16 x 16 up to
-//     64 x 64 by level size): a tile loads the input window it depends on
-//     (both halves, both directions), filters the rows, then the columns, in
-//     LDS.
+//     64 x 64 by level size).  Synthesis tiles, and analysis tiles of the
+//     largest size, filter in two passes: the first reads its lines straight
+//     from global memory, the second reads the once-filtered block from LDS.
+//     Smaller analysis tiles load their whole input window into LDS first.
 //   * The last synthesis level writes xi^T (the layout the column pass reads);
 //     the first analysis level reads xi'^T (the layout the adjoint column pass
 //     writes) and stores the detail bands straight into x.
@@ -22,16 +23,8 @@ namespace {
 using namespace lines;
 
 
-// Largest input window (coefficients per half and direction) of a tile.
-// Synthesis: interior tiles read TS/2 + nu + 1 coefficients; a tile that
-// holds one of the first or last 3nu-1 outputs also reads every coefficient
-// back to that end, which stays within the interior bound when 3nu-1 <= TS
-// and within TS/2 + 3nu otherwise.  Analysis: 2 TH + 2nu - 1 inside; at most
-// 2 TH + 3nu at an end when TH < nu.
-template <int NU, int TS>
-__host__ __device__ constexpr int synth_window_max() {
-  return 3 * NU - 1 <= TS ? TS / 2 + NU + 2 : TS / 2 + 3 * NU;
-}
+// Largest input window (coefficients per direction) of an analysis tile:
+// 2 TH + 2nu - 1 inside; at most 2 TH + 3nu at an end when TH < nu.
 template <int NU, int TH>
 __host__ __device__ constexpr int analysis_window_max() {
   return NU <= TH ? 2 * TH + 2 * NU + 4 : 2 * TH + 3 * NU;
@@ -61,111 +54,6 @@ __device__ __forceinline__ void tile_of(int t, int n, int& tr, int& tc) {
 }
 
 // ---------------------------------------------------------- tiled levels
-// Synthesis level k: X[r][c] = (r < half && c < half) ? ll[r][c] : det[r][c];
-// out = S X S^T (trans: out^T).  Tile: TS x TS outputs, 256 threads; each
-// thread produces runs of P output pairs.
-template <typename T, int NU, int TS, int P>
-__global__ void __launch_bounds__(256) k_synth2d_tile(const T* __restrict__ ll, int64_t ld_ll,
-                                                      const T* __restrict__ det, int64_t ld_det, T* __restrict__ out,
-                                                      int64_t ld_out, int k, int trans, Tables<T> t) {
-  extern __shared__ unsigned char smem_raw[];
-  __shared__ T tab_lds[tab_lds_size<NU>()];
-  T hr[2 * NU], gr[2 * NU];
-  TileLds<T> tl;
-  const int half = 1 << k, size = 2 * half;
-  const int ntile = size / TS;
-  int tr, tc;
-  tile_of(int(blockIdx.x), ntile, tr, tc);
-  const int r0 = tr * TS, c0 = tc * TS;
-  int rlo, rhi, clo, chi;
-  synth_input_range<NU>(r0, r0 + TS, half, rlo, rhi);
-  synth_input_range<NU>(c0, c0 + TS, half, clo, chi);
-  const int nr = rhi - rlo + 1, nc = chi - clo + 1;
-  const int W = 2 * nc + 1;                       // padded LDS row
-  T* Xs = reinterpret_cast<T*>(smem_raw);        // (2 nr) x W
-  constexpr int YW = TS + 1;
-  T* Ys = Xs + 2 * nr * W;                        // (2 nr) x YW
-  const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
-  {
-    // all loads of the window are issued before any is consumed
-    constexpr int MAXR = 2 * synth_window_max<NU, TS>(), RI = (MAXR + 3) / 4, CJ = (MAXR + 63) / 64;
-    T r[RI][CJ];
-#pragma unroll
-    for (int ii = 0; ii < RI; ++ii) {
-      const int i = wave + 4 * ii;
-      const int row = i < nr ? rlo + i : half + rlo + (i - nr);
-#pragma unroll
-      for (int jj = 0; jj < CJ; ++jj) {
-        const int j = lane + 64 * jj;
-        const int col = j < nc ? clo + j : half + clo + (j - nc);
-        T v = T(0);
-        if (i < 2 * nr && j < 2 * nc)
-          v = (row < half && col < half) ? ll[int64_t(row) * ld_ll + col] : det[int64_t(row) * ld_det + col];
-        r[ii][jj] = v;
-      }
-    }
-    // the tables load while the window loads are in flight
-    tl = load_tables<T, NU>(t, tab_lds, hr, gr);
-#pragma unroll
-    for (int ii = 0; ii < RI; ++ii) {
-      const int i = wave + 4 * ii;
-#pragma unroll
-      for (int jj = 0; jj < CJ; ++jj) {
-        const int j = lane + 64 * jj;
-        if (i < 2 * nr && j < 2 * nc) Xs[i * W + j] = r[ii][jj];
-      }
-    }
-  }
-  __syncthreads();
-  constexpr int RUNS = TS / (2 * P), LO = synth_lo<NU>();
-  // rows: work item = (window row, run of P output pairs)
-  for (int item = int(threadIdx.x); item < 2 * nr * RUNS; item += 256) {
-    const int i2 = item % (2 * nr), u = item / (2 * nr);
-    const T* xr = Xs + i2 * W;
-    const int i0 = (c0 >> 1) + u * P;
-    T* yr = Ys + i2 * YW + 2 * u * P;
-    if (pair_is_interior<NU>(i0, half) && pair_is_interior<NU>(i0 + P - 1, half)) {
-      T e[P], o[P];
-      synth_run<T, NU, P>(xr + i0 + LO - clo, xr + nc + i0 + LO - clo, 1, hr, gr, e, o);
-#pragma unroll
-      for (int p = 0; p < P; ++p) yr[2 * p] = e[p], yr[2 * p + 1] = o[p];
-    } else {
-      T e[P], o[P];
-      synth_run_edge<T, NU, P>(xr, xr + nc, 1, clo, chi, i0, half, hr, gr, tl.sLs, tl.sRs, e, o);
-#pragma unroll
-      for (int p = 0; p < P; ++p) yr[2 * p] = e[p], yr[2 * p + 1] = o[p];
-    }
-  }
-  __syncthreads();
-  // columns: work item = (output column, run of P output row pairs); result in Xs
-  T* Os = Xs;  // TS x YW
-  for (int item = int(threadIdx.x); item < TS * RUNS; item += 256) {
-    const int cc = item % TS, u = item / TS;
-    const int i0 = (r0 >> 1) + u * P;
-    T* oc = Os + 2 * u * P * YW + cc;
-    if (pair_is_interior<NU>(i0, half) && pair_is_interior<NU>(i0 + P - 1, half)) {
-      T e[P], o[P];
-      synth_run<T, NU, P>(Ys + (i0 + LO - rlo) * YW + cc, Ys + (nr + i0 + LO - rlo) * YW + cc, YW, hr, gr, e, o);
-#pragma unroll
-      for (int p = 0; p < P; ++p) oc[2 * p * YW] = e[p], oc[(2 * p + 1) * YW] = o[p];
-    } else {
-      T e[P], o[P];
-      synth_run_edge<T, NU, P>(Ys + cc, Ys + nr * YW + cc, YW, rlo, rhi, i0, half, hr, gr, tl.sLs, tl.sRs, e, o);
-#pragma unroll
-      for (int p = 0; p < P; ++p) oc[2 * p * YW] = e[p], oc[(2 * p + 1) * YW] = o[p];
-    }
-  }
-  __syncthreads();
-  for (int rr = wave; rr < TS; rr += 4) {
-    for (int cc = lane; cc < TS; cc += 64) {
-      if (trans)
-        out[int64_t(c0 + rr) * ld_out + r0 + cc] = Os[cc * YW + rr];
-      else
-        out[int64_t(r0 + rr) * ld_out + c0 + cc] = Os[rr * YW + cc];
-    }
-  }
-}
-
 // Analysis level k: input xi (size x size; trans: read in^T); output quadrants:
 // LL -> ll[a][b], other bands -> det[row][col].  Tile: TH x TH outputs in each
 // of the four quadrants at the same (a0, b0); 256 threads; runs of P outputs.
@@ -271,6 +159,205 @@ __global__ void __launch_bounds__(256) k_analysis2d_tile(const T* __restrict__ i
         ll[int64_t(o) * ld_ll + col] = v;
       else
         det[int64_t(o) * ld_det + col] = v;
+    }
+  }
+}
+
+// ------------------------------------------------- direct (two-pass) tiles
+// The first filter pass reads its input lines straight from global memory:
+// each thread owns one line of the window in the contiguous direction of the
+// array (lanes over consecutive columns) and walks it with the row stride.
+// Only the once-filtered block goes through LDS, where the second pass reads
+// it along the other direction.  Synthesis filters the columns first (S X,
+// then (S X) S^T); analysis filters along the array's rows index first.
+
+// Synthesis level k: X[r][c] = (r < half && c < half) ? ll[r][c] : det[r][c]
+// (ll and det share the row stride ld); out = S X S^T (trans: out^T).  Tile: TS x TS outputs, 256 threads, runs of P output pairs.
+template <typename T, int NU, int TS, int P>
+__global__ void __launch_bounds__(256) k_synth2d_direct(const T* __restrict__ ll, const T* __restrict__ det,
+                                                        int64_t ld, T* __restrict__ out, int64_t ld_out, int k,
+                                                        int trans, Tables<T> t) {
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ T tab_lds[tab_lds_size<NU>()];
+  T hr[2 * NU], gr[2 * NU];
+  const int half = 1 << k, size = 2 * half;
+  const int ntile = size / TS;
+  int tr, tc;
+  tile_of(int(blockIdx.x), ntile, tr, tc);
+  const int r0 = tr * TS, c0 = tc * TS;
+  int rlo, rhi, clo, chi;
+  synth_input_range<NU>(r0, r0 + TS, half, rlo, rhi);
+  synth_input_range<NU>(c0, c0 + TS, half, clo, chi);
+  const int nc = chi - clo + 1, W2 = 2 * nc;
+  const int YW = W2 + 1;                      // odd: conflict-free in both directions
+  T* Ys = reinterpret_cast<T*>(smem_raw);     // TS x YW: column-filtered rows r0 .. r0+TS-1
+  const TileLds<T> tl = load_tables<T, NU>(t, tab_lds, hr, gr);
+  constexpr int RUNS = TS / (2 * P), LO = synth_lo<NU>();
+  // pass 1, columns: item = (window column j, run u of P output row pairs)
+  for (int item = int(threadIdx.x); item < W2 * RUNS; item += 256) {
+    const int j = item % W2, u = item / W2;
+    const int col = j < nc ? clo + j : half + clo + (j - nc);
+    const T* ca = (col < half ? ll : det) + col;  // rows 0 .. half-1
+    const T* cd = det + int64_t(half) * ld + col;  // rows half .. size-1
+    const int i0 = (r0 >> 1) + u * P;
+    T e[P], o[P];
+    if (pair_is_interior<NU>(i0, half) && pair_is_interior<NU>(i0 + P - 1, half)) {
+      const int64_t off = int64_t(i0 + LO) * ld;
+      synth_run<T, NU, P>(ca + off, cd + off, int(ld), hr, gr, e, o);
+    } else {
+      // boundary blocks from global memory (the LDS copy is not yet visible)
+      const int64_t off = int64_t(rlo) * ld;
+      synth_run_edge<T, NU, P>(ca + off, cd + off, int(ld), rlo, rhi, i0, half, hr, gr, t.synL, t.synR, e, o);
+    }
+    T* yc = Ys + 2 * u * P * YW + j;
+#pragma unroll
+    for (int p = 0; p < P; ++p) yc[2 * p * YW] = e[p], yc[(2 * p + 1) * YW] = o[p];
+  }
+  __syncthreads();
+  // pass 2, rows: item = (output row r, run u of P output column pairs), at
+  // most one per thread.  The transposed output is written straight from
+  // registers with lanes over r (consecutive addresses).  Otherwise, with
+  // short runs, lanes run over u (each row segment written by consecutive
+  // lanes); with long runs the tile is staged in LDS and written row by row.
+  static_assert(TS * RUNS <= 256, "one row item per thread");
+  constexpr bool STAGE = P >= 4;
+  const int item = int(threadIdx.x);
+  const bool rfast = trans || STAGE;
+  const int r = rfast ? item % TS : item / RUNS, u = rfast ? item / TS : item % RUNS;
+  T e[P], o[P];
+  if (item < TS * RUNS) {
+    const T* yr = Ys + r * YW;
+    const int i0 = (c0 >> 1) + u * P;
+    if (pair_is_interior<NU>(i0, half) && pair_is_interior<NU>(i0 + P - 1, half))
+      synth_run<T, NU, P>(yr + i0 + LO - clo, yr + nc + i0 + LO - clo, 1, hr, gr, e, o);
+    else
+      synth_run_edge<T, NU, P>(yr, yr + nc, 1, clo, chi, i0, half, hr, gr, tl.sLs, tl.sRs, e, o);
+  }
+  if (trans) {
+    if (item < TS * RUNS) {
+      const int rr = r0 + r, cc = c0 + 2 * u * P;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        out[int64_t(cc + 2 * p) * ld_out + rr] = e[p];
+        out[int64_t(cc + 2 * p + 1) * ld_out + rr] = o[p];
+      }
+    }
+    return;
+  }
+  if constexpr (!STAGE) {
+    if (item < TS * RUNS) {
+      T* orow = out + int64_t(r0 + r) * ld_out + c0 + 2 * u * P;
+#pragma unroll
+      for (int p = 0; p < P; ++p) orow[2 * p] = e[p], orow[2 * p + 1] = o[p];
+    }
+    return;
+  }
+  constexpr int OW = TS + 1;
+  T* Os = Ys;  // TS x OW, fits in Ys (2 nc >= TS)
+  __syncthreads();
+  if (item < TS * RUNS) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) Os[r * OW + 2 * u * P + 2 * p] = e[p], Os[r * OW + 2 * u * P + 2 * p + 1] = o[p];
+  }
+  __syncthreads();
+  const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
+  for (int rr = wave; rr < TS; rr += 4)
+    for (int cc = lane; cc < TS; cc += 64) out[int64_t(r0 + rr) * ld_out + c0 + cc] = Os[rr * OW + cc];
+}
+
+// Analysis level k.  The filters run in the frame of the input array: G =
+// S^T in S when trans = 0, and G = S^T in S with in holding xi^T when trans =
+// 1, so that the coefficients are G^T (quadrants LH and HL exchange).  Tile:
+// TH x TH outputs in each quadrant of G at (A0, B0), 256 threads, runs of P.
+template <typename T, int NU, int TH, int P>
+__global__ void __launch_bounds__(256) k_analysis2d_direct(const T* __restrict__ in, int64_t ld_in, int trans,
+                                                           T* __restrict__ ll, int64_t ld_ll, T* __restrict__ det,
+                                                           int64_t ld_det, int k, Tables<T> t) {
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ T tab_lds[tab_lds_size<NU>()];
+  T hr[2 * NU], gr[2 * NU];
+  const int half = 1 << k;
+  const int ntile = half / TH;
+  int tr, tc;
+  tile_of(int(blockIdx.x), ntile, tr, tc);
+  const int A0 = tr * TH, B0 = tc * TH;
+  int plo, phi, qlo, qhi;
+  analysis_input_range<NU>(A0, A0 + TH, half, plo, phi);
+  analysis_input_range<NU>(B0, B0 + TH, half, qlo, qhi);
+  const int nq = qhi - qlo + 1;
+  const int YW = nq + 1;
+  T* Ys = reinterpret_cast<T*>(smem_raw);  // 2TH x YW: a rows, then d rows
+  const TileLds<T> tl = load_tables<T, NU>(t, tab_lds, hr, gr);
+  constexpr int RUNS = TH / P;
+  // pass 1, along the row index of `in`: item = (window column jq, run u)
+  for (int item = int(threadIdx.x); item < nq * RUNS; item += 256) {
+    const int jq = item % nq, u = item / nq;
+    const T* cx = in + qlo + jq;
+    const int m0 = A0 + u * P;
+    T a[P], d[P];
+    if (m0 >= NU && m0 + P - 1 < half - NU)
+      analysis_run<T, NU, P>(cx + int64_t(2 * m0 - NU + 1) * ld_in, int(ld_in), hr, gr, a, d);
+    else
+      analysis_run_edge<T, NU, P>(cx + int64_t(plo) * ld_in, int(ld_in), plo, phi, m0, half, hr, gr, t.synL,
+                                  t.synR, a, d);
+    T* yc = Ys + u * P * YW + jq;
+#pragma unroll
+    for (int p = 0; p < P; ++p) yc[p * YW] = a[p], yc[(TH + p) * YW] = d[p];
+  }
+  __syncthreads();
+  // pass 2, along the column index: item = (Ys row rho, run u), at most one
+  // per thread.  The result G[g_r][g_c] is coefficient (g_r, g_c) (trans = 0)
+  // or (g_c, g_r) (trans = 1).  Lanes run over rho: the transposed case is
+  // written straight from registers (consecutive addresses); otherwise the
+  // four TH x TH blocks are staged in LDS and written row by row.
+  static_assert(2 * TH * RUNS <= 256, "one row item per thread");
+  const int item = int(threadIdx.x);
+  const int rho = item % (2 * TH), u = item / (2 * TH);
+  const int m0 = B0 + u * P;
+  T a[P], d[P];
+  if (item < 2 * TH * RUNS) {
+    const T* yr = Ys + rho * YW;
+    if (m0 >= NU && m0 + P - 1 < half - NU)
+      analysis_run<T, NU, P>(yr + 2 * m0 - NU + 1 - qlo, 1, hr, gr, a, d);
+    else
+      analysis_run_edge<T, NU, P>(yr, 1, qlo, qhi, m0, half, hr, gr, tl.sLs, tl.sRs, a, d);
+  }
+  const int g_r = rho < TH ? A0 + rho : half + A0 + (rho - TH);
+  if (trans) {
+    if (item < 2 * TH * RUNS) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+#pragma unroll
+        for (int part = 0; part < 2; ++part) {
+          const int g_c = (part ? half : 0) + m0 + p;
+          const T v = part ? d[p] : a[p];
+          if (g_c < half && g_r < half)
+            ll[int64_t(g_c) * ld_ll + g_r] = v;
+          else
+            det[int64_t(g_c) * ld_det + g_r] = v;
+        }
+      }
+    }
+    return;
+  }
+  constexpr int OW = 2 * TH + 1;
+  T* Os = Ys;  // 2TH x OW: a columns then d columns; fits in Ys (nq >= 2 TH)
+  __syncthreads();
+  if (item < 2 * TH * RUNS) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) Os[rho * OW + u * P + p] = a[p], Os[rho * OW + TH + u * P + p] = d[p];
+  }
+  __syncthreads();
+  const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
+  for (int rr = wave; rr < 2 * TH; rr += 4) {
+    const int orow = rr < TH ? A0 + rr : half + A0 + (rr - TH);
+    for (int oc = lane; oc < 2 * TH; oc += 64) {
+      const int ocol = oc < TH ? B0 + oc : half + B0 + (oc - TH);
+      const T v = Os[rr * OW + oc];
+      if (orow < half && ocol < half)
+        ll[int64_t(orow) * ld_ll + ocol] = v;
+      else
+        det[int64_t(orow) * ld_det + ocol] = v;
     }
   }
 }
@@ -490,8 +577,6 @@ int max_analysis_window(int half, int th) {
   return w;
 }
 
-// Tile shapes: large tiles with long register runs where a level has enough
-// tiles to fill the chip, small tiles (more workgroups) on coarser levels.
 // Tile shapes per level: large tiles with long register runs where a level
 // has enough tiles to fill the chip, smaller ones (more workgroups) on
 // coarser levels.
@@ -507,16 +592,28 @@ constexpr int analysis_tile(int half) {
 }
 
 template <typename T, int NU, int TS, int P>
-hipError_t launch_synth(const T* ll, const T* det, T* dst, int64_t M, int k, int trans, const Tables<T>& t,
-                        hipStream_t st) {
+hipError_t launch_synth_direct(const T* ll, const T* det, T* dst, int64_t M, int k, int trans, const Tables<T>& t,
+                               hipStream_t st) {
   const int half = 1 << k, size = 2 * half;
   if (size % TS) return hipErrorInvalidValue;
-  const int nr = max_synth_window<NU>(half, TS);
-  if (nr > synth_window_max<NU, TS>()) return hipErrorInvalidValue;  // the kernel's load window
-  const size_t smem = (size_t(2 * nr) * (2 * nr + 1) + size_t(2 * nr) * (TS + 1)) * sizeof(T);
+  const int nc = max_synth_window<NU>(half, TS);
+  const size_t smem = size_t(TS) * (2 * nc + 1) * sizeof(T);
   const int ntile = size / TS;
-  hipLaunchKernelGGL((k_synth2d_tile<T, NU, TS, P>), dim3(unsigned(ntile * ntile)), dim3(256), smem, st, ll, M, det,
-                     M, dst, M, k, trans, t);
+  hipLaunchKernelGGL((k_synth2d_direct<T, NU, TS, P>), dim3(unsigned(ntile * ntile)), dim3(256), smem, st, ll, det, M,
+                     dst, M, k, trans, t);
+  return hipGetLastError();
+}
+
+template <typename T, int NU, int TH, int P>
+hipError_t launch_analysis_direct(const T* src, int trans, T* dst, T* x, int64_t M, int k, const Tables<T>& t,
+                                  hipStream_t st) {
+  const int half = 1 << k;
+  if (half % TH) return hipErrorInvalidValue;
+  const int nq = max_analysis_window<NU>(half, TH);
+  const size_t smem = size_t(2 * TH) * (nq + 1) * sizeof(T);
+  const int ntile = half / TH;
+  hipLaunchKernelGGL((k_analysis2d_direct<T, NU, TH, P>), dim3(unsigned(ntile * ntile)), dim3(256), smem, st, src, M,
+                     trans, dst, M, x, M, k, t);
   return hipGetLastError();
 }
 
@@ -569,11 +666,11 @@ hipError_t idwt2d_impl(const T* x, T* outT, T* s0, T* s1, int64_t M, int j0, int
     T* dst = fin ? outT : (ll == s0 ? s1 : s0);
     const int ts = synth_tile<T>(2 << k);
     if (ts == 64)
-      e = launch_synth<T, NU, 64, 8>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
+      e = launch_synth_direct<T, NU, 64, 8>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
     else if (ts == 32)
-      e = launch_synth<T, NU, 32, 2>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
+      e = launch_synth_direct<T, NU, 32, 2>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
     else
-      e = launch_synth<T, NU, 16, 2>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
+      e = launch_synth_direct<T, NU, 16, 2>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
     if (e != hipSuccess) return e;
     ll = dst;
   }
@@ -595,7 +692,7 @@ hipError_t dwt2d_impl(const T* inT, T* x, T* s0, T* s1, int64_t M, int j0, int j
     T* dst = (!coarse && k == kc) ? x : ((src == s0) ? s1 : s0);
     const int th = analysis_tile<T>(1 << k);
     if (th == 32)
-      e = launch_analysis<T, NU, 32, 8>(src, trans, dst, x, M, k, t, st);
+      e = launch_analysis_direct<T, NU, 32, 8>(src, trans, dst, x, M, k, t, st);
     else if (th == 16)
       e = launch_analysis<T, NU, 16, 2>(src, trans, dst, x, M, k, t, st);
     else
@@ -618,9 +715,9 @@ hipError_t prepare_impl() {
   const int lim = 160 * 1024 - int(tab_lds_size<NU>() * sizeof(T));
   const void* kernels[] = {
       (const void*)k_synth2d_coarse<T, NU>,         (const void*)k_analysis2d_coarse<T, NU>,
-      (const void*)k_synth2d_tile<T, NU, 64, 8>,    (const void*)k_synth2d_tile<T, NU, 32, 2>,
-      (const void*)k_synth2d_tile<T, NU, 16, 2>,    (const void*)k_analysis2d_tile<T, NU, 32, 8>,
       (const void*)k_analysis2d_tile<T, NU, 16, 2>, (const void*)k_analysis2d_tile<T, NU, 8, 2>,
+      (const void*)k_synth2d_direct<T, NU, 64, 8>,  (const void*)k_synth2d_direct<T, NU, 32, 2>,
+      (const void*)k_synth2d_direct<T, NU, 16, 2>,  (const void*)k_analysis2d_direct<T, NU, 32, 8>,
   };
   for (const void* f : kernels) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
