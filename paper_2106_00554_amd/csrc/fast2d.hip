@@ -161,17 +161,49 @@ __device__ __forceinline__ void place_edges(T (&acc)[R], T eacc, int lane) {
   }
 }
 
+// One line of M = 64 R values in LDS, without padding: the values of lane l
+// occupy [l R, (l + 1) R), in chunks of CW = min(R, 4) values; chunk c is
+// stored at chunk slot c ^ (l & SWZ), so that the vector accesses of
+// consecutive lanes fall on different banks.
 template <int R>
-__device__ __forceinline__ int buf_addr(int k, int log_r) {
-  return k + 4 * (k >> log_r);
-}
+struct LineBuf {
+  static constexpr int CW = R < 4 ? R : 4, NCH = R / CW, SWZ = (NCH < 8 ? NCH : 8) - 1;
+  // address of line position k
+  __device__ static __forceinline__ int addr(int k) {
+    const int l = k / R, r = k % R;
+    return l * R + (((r / CW) ^ (l & SWZ)) * CW) + r % CW;
+  }
+  template <typename T>
+  __device__ static __forceinline__ void store(T* buf, int lane, const T (&v)[R]) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      T* p = buf + lane * R + ((c ^ (lane & SWZ)) * CW);
+      T w[CW];
+#pragma unroll
+      for (int u = 0; u < CW; ++u) w[u] = v[c * CW + u];
+      store_line<T, CW>(p, w);
+    }
+  }
+  template <typename T>
+  __device__ static __forceinline__ void load(const T* buf, int lane, T (&v)[R]) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const T* p = buf + lane * R + ((c ^ (lane & SWZ)) * CW);
+      T w[CW];
+      load_line<T, CW>(p, w);
+#pragma unroll
+      for (int u = 0; u < CW; ++u) v[c * CW + u] = w[u];
+    }
+  }
+};
 
 // ------------------------------------------------------------- row passes
 template <typename T, int LOGM, int NU>
 __global__ void __launch_bounds__(1024) k_rowpass_fwd(const T* __restrict__ Z, T* __restrict__ y, Tables<T> t,
                                                      Omega om) {
   constexpr int M = 1 << LOGM, LOG_R = LOGM - 6, R = 1 << LOG_R;
-  constexpr int BUF = M + 4 * (M >> LOG_R);
+  constexpr int BUF = M;
+  using LB = LineBuf<R>;
   extern __shared__ unsigned char smem_raw[];
   const int lane = lane_id();
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
@@ -188,13 +220,13 @@ __global__ void __launch_bounds__(1024) k_rowpass_fwd(const T* __restrict__ Z, T
     const int s = wave;
     T v[R];
     line_forward<T, R, NU>(xi, v, s, t, lane);
-    store_line<T, R>(buf + lane * (R + 4), v);
+    LB::store(buf, lane, v);
     wave_sync();
     if (om.full) {
       T* yrow = y + n1 * N + int64_t(s) * M;
       for (int b = lane; b < M; b += 64) {
         const uint32_t k = natural_of(uint32_t(b), uint32_t(s), LOGM);
-        yrow[b] = buf[buf_addr<R>(int(k), LOG_R)];
+        yrow[b] = buf[LB::addr(int(k))];
       }
     } else {
       // the samples of this phase line are y[o .. o + cnt), in sequency order;
@@ -212,7 +244,7 @@ __global__ void __launch_bounds__(1024) k_rowpass_fwd(const T* __restrict__ Z, T
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          if (kk[u] >= 0) ys[t0 + lane + 64 * u] = buf[buf_addr<R>(kk[u], LOG_R)];
+          if (kk[u] >= 0) ys[t0 + lane + 64 * u] = buf[LB::addr(kk[u])];
       }
     }
     wave_sync();
@@ -223,7 +255,8 @@ template <typename T, int LOGM, int NU>
 __global__ void __launch_bounds__(1024) k_rowpass_adj(const T* __restrict__ y, T* __restrict__ Zt, Tables<T> t,
                                                      Omega om) {
   constexpr int M = 1 << LOGM, LOG_R = LOGM - 6, R = 1 << LOG_R;
-  constexpr int BUF = M + 4 * (M >> LOG_R);
+  constexpr int BUF = M;
+  using LB = LineBuf<R>;
   extern __shared__ unsigned char smem_raw[];
   const int lane = lane_id();
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
@@ -251,12 +284,12 @@ __global__ void __launch_bounds__(1024) k_rowpass_adj(const T* __restrict__ y, T
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
         const uint32_t k = natural_of(uint32_t(lane + 64 * i), uint32_t(s), LOGM);
-        buf[buf_addr<R>(int(k), LOG_R)] = rv[i];
+        buf[LB::addr(int(k))] = rv[i];
       }
     } else {
 #pragma unroll
       for (int i = 0; i < R; ++i) v[i] = T(0);
-      store_line<T, R>(buf + lane * (R + 4), v);
+      LB::store(buf, lane, v);
       const int64_t o = om.seg_ptr[n1 * Q + s];
       const int cnt = int(om.seg_ptr[n1 * Q + s + 1] - o);
       const uint16_t* __restrict__ ps = om.pos + o;
@@ -274,21 +307,21 @@ __global__ void __launch_bounds__(1024) k_rowpass_adj(const T* __restrict__ y, T
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          if (kk[u] >= 0) buf[buf_addr<R>(kk[u], LOG_R)] = rv[u];
+          if (kk[u] >= 0) buf[LB::addr(kk[u])] = rv[u];
       }
     }
     wave_sync();
-    load_line<T, R>(buf + lane * (R + 4), v);
+    LB::load(buf, lane, v);
     wave_sync();
     line_adjoint<T, R, NU>(v, acc, eacc, s, t, lane);
   }
   place_edges<T, R, NU>(acc, eacc, lane);
   // cross-wave sum (waves that had no phase contribute zeros)
-  store_line<T, R>(buf + lane * (R + 4), acc);
+  LB::store(buf, lane, acc);
   __syncthreads();
   for (int p = int(threadIdx.x); p < M; p += int(blockDim.x)) {
     T sum = T(0);
-    for (int w = 0; w < nw; ++w) sum += bufs[w * BUF + buf_addr<R>(p, LOG_R)];
+    for (int w = 0; w < nw; ++w) sum += bufs[w * BUF + LB::addr(p)];
     Zt[r * M + p] = sum;
   }
 }
@@ -353,29 +386,33 @@ __global__ void __launch_bounds__(1024) k_colpass_fwd(const T* __restrict__ xiT,
   }
 }
 
-// Adjoint: block = 8 waves = columns c0..c0+7 of the intermediate, all phases.
-template <typename T, int LOGM, int NU>
-__global__ void __launch_bounds__(512) k_colpass_adj(const T* __restrict__ Zt, T* __restrict__ xiT, Tables<T> t) {
+// Adjoint: block = columns c0..c0+7 of the intermediate x NG phase groups
+// (8 NG waves); group g takes phases g, g + NG, ...  Every group runs the
+// same number of phases, so the block-wide barriers line up; the groups'
+// partial sums are added through LDS at the end.
+template <typename T, int LOGM, int NU, int NG>
+__global__ void __launch_bounds__(512 * NG) k_colpass_adj(const T* __restrict__ Zt, T* __restrict__ xiT, Tables<T> t) {
   constexpr int M = 1 << LOGM, LOG_R = LOGM - 6, R = 1 << LOG_R;
   constexpr int TILE = 8, SP = 64 * 4 + 4;
   static_assert(R == 2 || R % 4 == 0, "column pass staging needs R = 2 or a multiple of 4");
   extern __shared__ unsigned char smem_raw[];
-  T* stage = reinterpret_cast<T*>(smem_raw);
   const int lane = lane_id();
-  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int wave_all = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int g = wave_all >> 3, wave = wave_all & 7;  // 512 threads per phase group
+  T* stage = reinterpret_cast<T*>(smem_raw) + g * TILE * SP;
   const int Q = t.Q;
   const int nblk = int(gridDim.x), bid = int(blockIdx.x);
   const int per = nblk / 8;
   const int tile = (nblk % 8 == 0) ? (bid % 8) * per + bid / 8 : bid;
   const int c = tile * TILE + wave;
-  const int tid = int(threadIdx.x);
+  const int tid = int(threadIdx.x) & 511;
   const int e = tid >> 1, half = tid & 1;          // 256 input rows x 2 halves of 4 columns
   const int le = e >> 2, te = e & 3;
   T acc[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) acc[i] = T(0);
   T eacc = T(0);
-  for (int s = 0; s < Q; ++s) {
+  for (int s = g; s < Q; s += NG) {
     T v[R];
     if constexpr (R == 2) {
       // one round: 128 input rows x 4 column pairs
@@ -423,7 +460,27 @@ __global__ void __launch_bounds__(512) k_colpass_adj(const T* __restrict__ Zt, T
     line_adjoint<T, R, NU>(v, acc, eacc, s, t, lane);
   }
   place_edges<T, R, NU>(acc, eacc, lane);
-  store_line<T, R>(xiT + int64_t(c) * M + lane * R, acc);
+  if constexpr (NG > 1) {
+    static_assert(NG == 2, "two phase groups at most");
+    // group 1 hands its partial sums to group 0, a few registers per round,
+    // through its own staging area
+    constexpr int RC = R < 4 ? R : 4;
+#pragma unroll
+    for (int i = 0; i < R / RC; ++i) {
+      if (g == 1) {
+#pragma unroll
+        for (int u = 0; u < RC; ++u) stage[wave * SP + lane * RC + u] = acc[RC * i + u];
+      }
+      __syncthreads();
+      if (g == 0) {
+        const T* other = stage + TILE * SP;
+#pragma unroll
+        for (int u = 0; u < RC; ++u) acc[RC * i + u] += other[wave * SP + lane * RC + u];
+      }
+      __syncthreads();
+    }
+  }
+  if (g == 0) store_line<T, R>(xiT + int64_t(c) * M + lane * R, acc);
 }
 
 // ------------------------------------------------------------ transpose
@@ -440,18 +497,18 @@ __global__ void __launch_bounds__(256) k_transpose(const T* __restrict__ in, T* 
 // ------------------------------------------------------------- dispatch
 template <typename T, int LOGM, int NU>
 hipError_t launch_rowpass_fwd(const T* Z, T* y, const Tables<T>& t, const Omega& om, hipStream_t st) {
-  constexpr int M = 1 << LOGM, R = M / 64;
+  constexpr int M = 1 << LOGM;
   const int nw = t.Q;  // one wave per phase
-  const size_t smem = size_t(nw) * (M + 4 * (M / R)) * sizeof(T);
+  const size_t smem = size_t(nw) * M * sizeof(T);
   const int64_t rows = int64_t(M) * t.Q;
   hipLaunchKernelGGL((k_rowpass_fwd<T, LOGM, NU>), dim3(unsigned(rows)), dim3(64 * nw), smem, st, Z, y, t, om);
   return hipGetLastError();
 }
 template <typename T, int LOGM, int NU>
 hipError_t launch_rowpass_adj(const T* y, T* Zt, const Tables<T>& t, const Omega& om, hipStream_t st) {
-  constexpr int M = 1 << LOGM, R = M / 64;
+  constexpr int M = 1 << LOGM;
   const int nw = t.Q;  // one wave per phase
-  const size_t smem = size_t(nw) * (M + 4 * (M / R)) * sizeof(T);
+  const size_t smem = size_t(nw) * M * sizeof(T);
   const int64_t rows = int64_t(M) * t.Q;
   hipLaunchKernelGGL((k_rowpass_adj<T, LOGM, NU>), dim3(unsigned(rows)), dim3(64 * nw), smem, st, y, Zt, t, om);
   return hipGetLastError();
@@ -463,11 +520,17 @@ hipError_t launch_colpass_fwd(const T* xiT, T* Z, const Tables<T>& t, hipStream_
   hipLaunchKernelGGL((k_colpass_fwd<T, LOGM, NU>), dim3(unsigned((M / 16) * t.Q)), dim3(1024), smem, st, xiT, Z, t);
   return hipGetLastError();
 }
+// Phase groups of the adjoint column pass: two where a 1024-thread block keeps
+// the line in registers (Q >= 2 always).
+template <typename T, int LOGM, int NU>
+constexpr int colpass_adj_groups() {
+  return sizeof(T) == 4 ? 2 : (LOGM <= 9 && NU <= 6 ? 2 : 1);
+}
 template <typename T, int LOGM, int NU>
 hipError_t launch_colpass_adj(const T* Zt, T* xiT, const Tables<T>& t, hipStream_t st) {
-  constexpr int M = 1 << LOGM;
-  const size_t smem = size_t(8) * (64 * 4 + 4) * sizeof(T);
-  hipLaunchKernelGGL((k_colpass_adj<T, LOGM, NU>), dim3(unsigned(M / 8)), dim3(512), smem, st, Zt, xiT, t);
+  constexpr int M = 1 << LOGM, NG = colpass_adj_groups<T, LOGM, NU>();
+  const size_t smem = size_t(NG) * 8 * (64 * 4 + 4) * sizeof(T);
+  hipLaunchKernelGGL((k_colpass_adj<T, LOGM, NU, NG>), dim3(unsigned(M / 8)), dim3(512 * NG), smem, st, Zt, xiT, t);
   return hipGetLastError();
 }
 
@@ -485,7 +548,7 @@ hipError_t launch_colpass_adj(const T* Zt, T* xiT, const Tables<T>& t, hipStream
 bool supported(int elem_bytes, int logm, int nu, int q) {
   // row passes: one wave (and one LDS line buffer) per phase
   const long long phases = 1LL << q, m = 1LL << logm;
-  if (q > 4 || phases * (m + 4 * 64) * elem_bytes > 160 * 1024) return false;
+  if (q > 4 || phases * m * elem_bytes > 160 * 1024) return false;
 #define X(L, V) if (logm == L && nu == V) return true;
   WH2WAV_FAST_CASES(X)
 #undef X
@@ -530,7 +593,8 @@ hipError_t prepare_lines_impl() {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_colpass_fwd<T, LOGM, NU>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_colpass_adj<T, LOGM, NU>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    e = hipFuncSetAttribute((const void*)k_colpass_adj<T, LOGM, NU, colpass_adj_groups<T, LOGM, NU>()>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   return e;
 }
 
