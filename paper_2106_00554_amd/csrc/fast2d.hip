@@ -327,9 +327,15 @@ __global__ void __launch_bounds__(1024) k_rowpass_adj(const T* __restrict__ y, T
 }
 
 // ---------------------------------------------------------- column passes
-// Forward: block = 16 waves = 16 rows of xi^T (columns c0..c0+15 of xi), one
-// phase s.  Blocks that share a tile are placed on the same XCD (the
-// dispatcher deals consecutive block ids round-robin over the 8 XCDs).
+// Forward: block = 16 waves = 16 rows of xi^T (columns c0..c0+15 of xi), a
+// group of consecutive phases (the grid holds M/16 tiles x the number of
+// groups); the stores of one phase drain while the next one computes.  Blocks
+// that share a tile are placed on the same XCD (the dispatcher deals
+// consecutive block ids round-robin over the 8 XCDs).
+template <typename T>
+constexpr int colpass_fwd_maxph() {
+  return sizeof(T) == 4 ? 2 : 1;  // FP64 keeps no second line in registers
+}
 template <typename T, int LOGM, int NU>
 __global__ void __launch_bounds__(1024) k_colpass_fwd(const T* __restrict__ xiT, T* __restrict__ Z, Tables<T> t) {
   constexpr int M = 1 << LOGM, LOG_R = LOGM - 6, R = 1 << LOG_R;
@@ -343,12 +349,17 @@ __global__ void __launch_bounds__(1024) k_colpass_fwd(const T* __restrict__ xiT,
   const int nblk = int(gridDim.x), bid = int(blockIdx.x);
   const int per = nblk / 8;
   const int idx = (nblk % 8 == 0) ? (bid % 8) * per + bid / 8 : bid;
-  const int tile = idx / Q, s = idx % Q;
+  const int ngrp = nblk / (M / TILE), ph = Q / ngrp;
+  const int tile = idx / ngrp, s0 = (idx % ngrp) * ph;
   const int c = tile * TILE + wave;
-  T xi[R], v[R];
+  T xi[R];
   load_line<T, R>(xiT + int64_t(c) * M + lane * R, xi);
-  line_forward<T, R, NU>(xi, v, s, t, lane);
   const int tid = int(threadIdx.x);
+  for (int i = 0; i < colpass_fwd_maxph<T>(); ++i) {
+  if (i >= ph) break;
+  const int s = s0 + i;
+  T v[R];
+  line_forward<T, R, NU>(xi, v, s, t, lane);
   if constexpr (R == 2) {
     // one round: the wave's 128 values, then 128 output rows x 8 column pairs
     constexpr int SP2 = 2 * 64 + 4;
@@ -362,7 +373,8 @@ __global__ void __launch_bounds__(1024) k_colpass_fwd(const T* __restrict__ xiT,
     } else {
       *reinterpret_cast<double2*>(dst) = make_double2(o0, o1);
     }
-    return;
+    __syncthreads();  // stage reused by the next phase
+    continue;
   }
   const int e = tid >> 2, qg = tid & 3;            // 256 output rows x 4 column groups
   const int le = e >> 2, te = e & 3;
@@ -383,6 +395,7 @@ __global__ void __launch_bounds__(1024) k_colpass_fwd(const T* __restrict__ xiT,
       reinterpret_cast<double2*>(dst)[1] = make_double2(o[2], o[3]);
     }
     __syncthreads();
+  }
   }
 }
 
@@ -412,6 +425,24 @@ __global__ void __launch_bounds__(512 * NG) k_colpass_adj(const T* __restrict__ 
 #pragma unroll
   for (int i = 0; i < R; ++i) acc[i] = T(0);
   T eacc = T(0);
+  // phase s of the tile, R/4 float4 rows per thread (the layout the exchange
+  // rounds take apart); the next phase is fetched while this one computes
+  T o[R / 4 > 0 ? R / 4 : 1][4];
+  auto fetch = [&](int s) {
+#pragma unroll
+    for (int i = 0; i < R / 4; ++i) {
+      const int k = le * R + 4 * i + te;
+      const T* src = Zt + (int64_t(s) * M + k) * M + tile * TILE + 4 * half;
+      if constexpr (sizeof(T) == 4) {
+        const float4 f = *reinterpret_cast<const float4*>(src);
+        o[i][0] = f.x, o[i][1] = f.y, o[i][2] = f.z, o[i][3] = f.w;
+      } else {
+        const double2 f0 = reinterpret_cast<const double2*>(src)[0], f1 = reinterpret_cast<const double2*>(src)[1];
+        o[i][0] = f0.x, o[i][1] = f0.y, o[i][2] = f1.x, o[i][3] = f1.y;
+      }
+    }
+  };
+  if constexpr (R >= 4) fetch(g);
   for (int s = g; s < Q; s += NG) {
     T v[R];
     if constexpr (R == 2) {
@@ -435,19 +466,6 @@ __global__ void __launch_bounds__(512 * NG) k_colpass_adj(const T* __restrict__ 
       line_adjoint<T, R, NU>(v, acc, eacc, s, t, lane);
       continue;
     }
-    T o[R / 4 > 0 ? R / 4 : 1][4];  // every load of the phase is issued before the exchange rounds
-#pragma unroll
-    for (int i = 0; i < R / 4; ++i) {
-      const int k = le * R + 4 * i + te;
-      const T* src = Zt + (int64_t(s) * M + k) * M + tile * TILE + 4 * half;
-      if constexpr (sizeof(T) == 4) {
-        const float4 f = *reinterpret_cast<const float4*>(src);
-        o[i][0] = f.x, o[i][1] = f.y, o[i][2] = f.z, o[i][3] = f.w;
-      } else {
-        const double2 f0 = reinterpret_cast<const double2*>(src)[0], f1 = reinterpret_cast<const double2*>(src)[1];
-        o[i][0] = f0.x, o[i][1] = f0.y, o[i][2] = f1.x, o[i][3] = f1.y;
-      }
-    }
 #pragma unroll
     for (int i = 0; i < R / 4; ++i) {
 #pragma unroll
@@ -457,6 +475,7 @@ __global__ void __launch_bounds__(512 * NG) k_colpass_adj(const T* __restrict__ 
       for (int u = 0; u < 4; ++u) v[4 * i + u] = stage[wave * SP + lane * 4 + u];
       __syncthreads();
     }
+    if (s + NG < Q) fetch(s + NG);
     line_adjoint<T, R, NU>(v, acc, eacc, s, t, lane);
   }
   place_edges<T, R, NU>(acc, eacc, lane);
@@ -517,14 +536,20 @@ template <typename T, int LOGM, int NU>
 hipError_t launch_colpass_fwd(const T* xiT, T* Z, const Tables<T>& t, hipStream_t st) {
   constexpr int M = 1 << LOGM;
   const size_t smem = size_t(16) * (64 * 4 + 4) * sizeof(T);
-  hipLaunchKernelGGL((k_colpass_fwd<T, LOGM, NU>), dim3(unsigned((M / 16) * t.Q)), dim3(1024), smem, st, xiT, Z, t);
+  // two phases per block where that still leaves a block per CU
+  const int ph = colpass_fwd_maxph<T>() >= 2 && (M / 16) * t.Q / 2 >= 256 ? 2 : 1;
+  hipLaunchKernelGGL((k_colpass_fwd<T, LOGM, NU>), dim3(unsigned((M / 16) * (t.Q / ph))), dim3(1024), smem, st, xiT,
+                     Z, t);
   return hipGetLastError();
 }
+#ifndef COLADJ_NG
+#define COLADJ_NG 1
+#endif
 // Phase groups of the adjoint column pass: two where a 1024-thread block keeps
 // the line in registers (Q >= 2 always).
 template <typename T, int LOGM, int NU>
 constexpr int colpass_adj_groups() {
-  return sizeof(T) == 4 ? 2 : (LOGM <= 9 && NU <= 6 ? 2 : 1);
+  return COLADJ_NG;
 }
 template <typename T, int LOGM, int NU>
 hipError_t launch_colpass_adj(const T* Zt, T* xiT, const Tables<T>& t, hipStream_t st) {
