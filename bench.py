@@ -4,8 +4,8 @@
 Workload (default): 2D, Daubechies wavelets with 8 vanishing moments and
 boundary correction, M = 2048 x 2048 coefficients, q = 2 (N = 8192 x 8192
 Walsh samples), Omega a 12.5 % multilevel variable-density subsample, FP32.
-This is the HBM-roofline configuration of the method; inputs are synthetic
-(seeded image-like wavelet coefficients, see tests/inputs.py).
+This is the largest configuration of the method measured here; inputs are
+synthetic (seeded image-like wavelet coefficients, see tests/inputs.py).
 
 One step = one forward y = P_Omega A x followed by one adjoint A^T P_Omega^T y
 of that y, inputs resident in HBM.  The path runs through the C ABI stage by
@@ -13,7 +13,10 @@ stage (wh2wav_forward_stage / wh2wav_adjoint_stage, which together are exactly
 wh2wav_forward / wh2wav_adjoint).  During warm-up every stage is timed once
 with HIP events; in the timed region two events per step bracket the
 dominant stage only, on the launch stream, which gives the per-launch
-duration used for the roofline.
+duration used for the roofline.  The line kernels are bound by vector-ALU
+issue: their roofline is algorithmic flops (table-product FMAs and FWHT
+additions per output sample) against the FP32 FMA peak without packed
+instructions, with the HBM figures alongside.
 
 Two more legs are reported in the same JSON line (skip with --no-extras):
 * "autograd": the 1024^2 db4 q=1 FP32 operator (25 % Omega) through the
@@ -34,6 +37,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector FMA peak without packed-FP32 instructions (the build disables
+# them): 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz.
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
 def stage_bytes(w, m, elem):
@@ -49,6 +55,15 @@ def stage_bytes(w, m, elem):
         ("adj", 1): (N * M + M * M) * elem,                 # column pass
         ("adj", 2): 2 * M * M * elem,                       # DWT
     }
+
+
+def stage_flops(w):
+    """Algorithmic flops per launch of the line stages: per output sample of a
+    pass, (2nu - 1) FMAs of the table product and log2 M FWHT additions; a
+    column pass produces M N samples, a row pass N^2."""
+    M, N = 1 << w["j"], 1 << (w["j"] + w["q"])
+    per = 2 * (2 * w["nu"] - 1) + w["j"]
+    return {("fwd", 1): M * N * per, ("fwd", 2): N * N * per, ("adj", 0): N * N * per, ("adj", 1): M * N * per}
 
 
 STAGE_NAMES = {("fwd", 0): "idwt", ("fwd", 1): "column_pass_fwd", ("fwd", 2): "row_pass_fwd_gather",
@@ -342,6 +357,19 @@ def main():
     achieved = nbytes[dom] / (dom_ms * 1e-3) / 1e9
     kernel = STAGE_KERNELS.get(dom, STAGE_NAMES[dom])
     traffic = traffic_for(kernel, name) if dtype == torch.float32 else None
+    flops = stage_flops(w).get(dom)
+    if flops is not None and dtype == torch.float32:
+        # the line kernels are bound by vector-ALU issue; HBM figures for context
+        tflops = flops / (dom_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": kernel, "achieved": tflops, "peak": VALU_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": tflops / VALU_PEAK_TFLOPS, "traffic": traffic,
+                    "algorithmic_flops": flops, "launch_ms": dom_ms,
+                    "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes": nbytes[dom]}}
+    else:
+        roofline = {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                    "algorithmic_bytes": nbytes[dom], "launch_ms": dom_ms}
     out = {
         "metric": "forward+adjoint matvec pairs/sec",
         "value": args.steps / elapsed,
@@ -358,9 +386,7 @@ def main():
         "config": {"workload": name, "dim": w["dim"], "wavelet": f"db{w['nu']}", "M": 1 << w["j"],
                    "N": 1 << (w["j"] + w["q"]), "q": w["q"], "omega_density": w["density"], "m": opr.m},
         "stages_ms_warmup": {STAGE_NAMES[k]: round(v, 4) for k, v in warm_stage.items()},
-        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes": nbytes[dom], "launch_ms": dom_ms},
+        "roofline": roofline,
     }
     if not args.no_extras:
         out["autograd"] = autograd_leg(torch, max(5, args.steps // 2))
