@@ -91,7 +91,11 @@ __global__ void __launch_bounds__(256) k_analysis2d_tile(const T* __restrict__ i
 #pragma unroll
       for (int v = 0; v < IJ; ++v) {
         const int b = lane + 64 * v;
-        r[u][v] = (a < no && b < ni) ? in[(ob + a) * ld_in + ib + b] : T(0);
+        // unconditional load (the window's first element when outside it), so
+        // that all loads are in flight together
+        const bool inside = a < no && b < ni;
+        const T val = in[inside ? (ob + a) * ld_in + ib + b : ob * ld_in + ib];
+        r[u][v] = inside ? val : T(0);
       }
     }
     // the tables load while the window loads are in flight

@@ -99,13 +99,16 @@ __device__ __forceinline__ void line_forward(const T (&xi)[R], T (&v)[R], int s,
   for (int li = 0; li < 2 * NU - 1; ++li) tap[li] = t.tabT[li * Q + s];
   table_product<T, R, NU>(x, v, tap, lane);
   // boundary bands (Prop. 4.2): positions p < B and p >= M - B
+  // lanes 0..B-1: left band row p = lane; lanes B..2B-1: right band row
+  // lane - B.  Loads are unconditional (clamped row) so they overlap.
   T bv = T(0);
-  if (lane < B) {
+  {
+    const bool left = lane < B;
+    const int p = left ? lane : (lane < 2 * B ? lane - B : 0);
+    const T* band = left ? t.bandL : t.bandR;
 #pragma unroll
-    for (int m = 0; m < NU; ++m) bv = fma(eL[m], t.bandL[(lane * NU + m) * Q + s], bv);
-  } else if (lane < 2 * B) {
-#pragma unroll
-    for (int m = 0; m < NU; ++m) bv = fma(eR[m], t.bandR[((lane - B) * NU + m) * Q + s], bv);
+    for (int m = 0; m < NU; ++m) bv = fma(left ? eL[m] : eR[m], band[(p * NU + m) * Q + s], bv);
+    bv = lane < 2 * B ? bv : T(0);
   }
 #pragma unroll
   for (int e = 0; e < B; ++e) {
@@ -139,13 +142,16 @@ __device__ __forceinline__ void line_adjoint(T (&v)[R], T (&acc)[R], T& eacc, in
     rl[e] = read_lane(v[e % R], e / R);
     rr[e] = read_lane(v[pr % R], pr / R);
   }
+  // lanes 0..nu-1: left boundary column m = lane; lanes nu..2nu-1: right
+  // column lane - nu (unconditional loads, clamped column)
   T el = T(0);
-  if (lane < NU) {
+  {
+    const bool left = lane < NU;
+    const int m = left ? lane : (lane < 2 * NU ? lane - NU : 0);
+    const T* band = left ? t.bandL : t.bandR;
 #pragma unroll
-    for (int p = 0; p < B; ++p) el = fma(t.bandL[(p * NU + lane) * Q + s], rl[p], el);
-  } else if (lane < 2 * NU) {
-#pragma unroll
-    for (int p = 0; p < B; ++p) el = fma(t.bandR[(p * NU + (lane - NU)) * Q + s], rr[p], el);
+    for (int p = 0; p < B; ++p) el = fma(band[(p * NU + m) * Q + s], left ? rl[p] : rr[p], el);
+    el = lane < 2 * NU ? el : T(0);
   }
   eacc += el;
 }
@@ -240,7 +246,8 @@ __global__ void __launch_bounds__(1024) k_rowpass_fwd(const T* __restrict__ Z, T
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int tt = t0 + lane + 64 * u;
-          kk[u] = tt < cnt ? int(ps[tt]) : -1;
+          const int pv = int(ps[tt < cnt ? tt : cnt - 1]);  // cnt > 0 inside the loop
+          kk[u] = tt < cnt ? pv : -1;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -302,8 +309,10 @@ __global__ void __launch_bounds__(1024) k_rowpass_adj(const T* __restrict__ y, T
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int tt = t0 + lane + 64 * u;
-          kk[u] = tt < cnt ? int(ps[tt]) : -1;
-          rv[u] = tt < cnt ? ys[tt] : T(0);
+          const int pv = int(ps[tt < cnt ? tt : cnt - 1]);  // cnt > 0 inside the loop
+          kk[u] = tt < cnt ? pv : -1;
+          const T yv = ys[tt < cnt ? tt : cnt - 1];
+          rv[u] = tt < cnt ? yv : T(0);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
