@@ -173,6 +173,34 @@ def test_2d_workload_db8_j11_q2_sampled(dtype):
     assert np.linalg.norm(y) <= np.linalg.norm(X) * (1 + 1e-6)
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_2d_j12_sampled(dtype):
+    """2D beyond the wave kernels: db4, M = 4096^2, q = 1, 10 % Omega.
+
+    Generic line kernels; the 2048^2 wavelet level runs untransposed through
+    the direct (two-pass) synthesis and analysis tiles with 64^2 / 32^2 tiles,
+    which no smaller size reaches.  Sampled forward and adjoint entries from
+    the oracle, and the adjoint identity at full size.
+    """
+    cfg = op.Config(4, 12, 1, 3)
+    X = inputs.coefficients_2d(12, 3, 1234)
+    omega = inputs.multilevel_omega_2d(cfg.N, 0.1, 1235)
+    yv = inputs.sample_vector(omega.size, 1236)
+    y, xa = gpu_pair(2, 4, 12, 1, 3, dtype, X, omega, yv)
+    rng = np.random.default_rng(7)
+    N = cfg.N
+    edge = np.flatnonzero((omega // N < 4) | (omega // N >= N - 4) | (omega % N < 4) | (omega % N >= N - 4))
+    pick = np.concatenate([rng.choice(omega.size, 48, replace=False), rng.choice(edge, min(16, edge.size), replace=False)])
+    ref = op.forward_entries_2d(cfg, X, omega[pick] // N, omega[pick] % N)
+    assert rel(y[pick], ref) < TOL[dtype], rel(y[pick], ref)
+    pos = _boundary_heavy_positions(cfg, rng, 6)
+    xref = op.adjoint_entries_2d(cfg, yv, omega, pos)
+    got = np.array([xa[c1, c2] for c1, c2 in pos])
+    assert rel(got, xref) < TOL[dtype], rel(got, xref)
+    lhs, rhs = np.dot(y.astype(np.float64), yv), np.sum(X * xa.astype(np.float64))
+    assert abs(lhs - rhs) / (np.linalg.norm(y) * np.linalg.norm(yv)) < TOL[dtype]
+
+
 def test_empty_omega():
     from paper_2106_00554_amd.operator import Wh2Wav
     for dim in (1, 2):
