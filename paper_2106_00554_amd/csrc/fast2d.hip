@@ -411,7 +411,9 @@ __global__ void __launch_bounds__(1024) k_colpass_fwd(const T* __restrict__ xiT,
 // Adjoint: block = columns c0..c0+7 of the intermediate x NG phase groups
 // (8 NG waves); group g takes phases g, g + NG, ...  Every group runs the
 // same number of phases, so the block-wide barriers line up; the groups'
-// partial sums are added through LDS at the end.
+// partial sums are added through LDS at the end.  With one group, the rows
+// of the group's next phase are fetched into registers while the current
+// phase computes (two groups have no registers to spare for that).
 template <typename T, int LOGM, int NU, int NG>
 __global__ void __launch_bounds__(512 * NG) k_colpass_adj(const T* __restrict__ Zt, T* __restrict__ xiT, Tables<T> t) {
   constexpr int M = 1 << LOGM, LOG_R = LOGM - 6, R = 1 << LOG_R;
@@ -451,7 +453,7 @@ __global__ void __launch_bounds__(512 * NG) k_colpass_adj(const T* __restrict__ 
       }
     }
   };
-  if constexpr (R >= 4) fetch(g);
+  if constexpr (R >= 4 && NG == 1) fetch(g);
   for (int s = g; s < Q; s += NG) {
     T v[R];
     if constexpr (R == 2) {
@@ -475,6 +477,7 @@ __global__ void __launch_bounds__(512 * NG) k_colpass_adj(const T* __restrict__ 
       line_adjoint<T, R, NU>(v, acc, eacc, s, t, lane);
       continue;
     }
+    if constexpr (NG > 1) fetch(s);
 #pragma unroll
     for (int i = 0; i < R / 4; ++i) {
 #pragma unroll
@@ -484,7 +487,7 @@ __global__ void __launch_bounds__(512 * NG) k_colpass_adj(const T* __restrict__ 
       for (int u = 0; u < 4; ++u) v[4 * i + u] = stage[wave * SP + lane * 4 + u];
       __syncthreads();
     }
-    if (s + NG < Q) fetch(s + NG);
+    if (NG == 1 && s + NG < Q) fetch(s + NG);
     line_adjoint<T, R, NU>(v, acc, eacc, s, t, lane);
   }
   place_edges<T, R, NU>(acc, eacc, lane);
@@ -551,14 +554,13 @@ hipError_t launch_colpass_fwd(const T* xiT, T* Z, const Tables<T>& t, hipStream_
                      Z, t);
   return hipGetLastError();
 }
-#ifndef COLADJ_NG
-#define COLADJ_NG 1
-#endif
-// Phase groups of the adjoint column pass: two where a 1024-thread block keeps
-// the line in registers (Q >= 2 always).
+// Phase groups of the adjoint column pass: two (1024 threads) on FP32 lines
+// up to 1024 values, where the grid of M/8 blocks is small and the line fits
+// the 128 registers of a 1024-thread block; otherwise one, with the
+// next-phase prefetch (Q >= 2 always).
 template <typename T, int LOGM, int NU>
 constexpr int colpass_adj_groups() {
-  return COLADJ_NG;
+  return sizeof(T) == 4 && LOGM <= 10 ? 2 : 1;
 }
 template <typename T, int LOGM, int NU>
 hipError_t launch_colpass_adj(const T* Zt, T* xiT, const Tables<T>& t, hipStream_t st) {
