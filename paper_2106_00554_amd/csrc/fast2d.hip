@@ -208,14 +208,13 @@ template <typename T, int LOGM, int NU>
 __global__ void __launch_bounds__(1024) k_rowpass_fwd(const T* __restrict__ Z, T* __restrict__ y, Tables<T> t,
                                                      Omega om) {
   constexpr int M = 1 << LOGM, LOG_R = LOGM - 6, R = 1 << LOG_R;
-  constexpr int BUF = M;
+  constexpr int HM = M / 2;  // LDS per wave: half a line
   using LB = LineBuf<R>;
   extern __shared__ unsigned char smem_raw[];
   const int lane = lane_id();
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
-  const int nw = int(blockDim.x) >> 6;
   const int Q = t.Q;
-  T* buf = reinterpret_cast<T*>(smem_raw) + wave * BUF;
+  T* buf = reinterpret_cast<T*>(smem_raw) + wave * HM;
   const int64_t r = blockIdx.x;
   T xi[R];
   load_line<T, R>(Z + r * M + lane * R, xi);
@@ -226,35 +225,45 @@ __global__ void __launch_bounds__(1024) k_rowpass_fwd(const T* __restrict__ Z, T
     const int s = wave;
     T v[R];
     line_forward<T, R, NU>(xi, v, s, t, lane);
-    LB::store(buf, lane, v);
-    wave_sync();
-    if (om.full) {
-      T* yrow = y + n1 * N + int64_t(s) * M;
-      for (int b = lane; b < M; b += 64) {
-        const uint32_t k = natural_of(uint32_t(b), uint32_t(s), LOGM);
-        yrow[b] = buf[LB::addr(int(k))];
-      }
-    } else {
-      // the samples of this phase line are y[o .. o + cnt), in sequency order;
-      // pos holds each one's natural position (coalesced reads and writes)
-      const int64_t o = om.seg_ptr[n1 * Q + s];
-      const int cnt = int(om.seg_ptr[n1 * Q + s + 1] - o);
-      const uint16_t* __restrict__ ps = om.pos + o;
-      T* __restrict__ ys = y + o;
-      for (int t0 = 0; t0 < cnt; t0 += 256) {
-        int kk[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int tt = t0 + lane + 64 * u;
-          const int pv = int(ps[tt < cnt ? tt : cnt - 1]);  // cnt > 0 inside the loop
-          kk[u] = tt < cnt ? pv : -1;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (kk[u] >= 0) ys[t0 + lane + 64 * u] = buf[LB::addr(kk[u])];
-      }
+    // The line reaches LDS in two halves (lanes 0..31 hold the positions below
+    // M/2), each followed by the reads of the samples it holds: half a line
+    // of LDS per wave, so that more workgroups fit on a CU.
+    int64_t o = 0;
+    int cnt = 0;
+    if (!om.full) {
+      o = om.seg_ptr[n1 * Q + s];
+      cnt = int(om.seg_ptr[n1 * Q + s + 1] - o);
     }
-    wave_sync();
+    for (int h = 0; h < 2; ++h) {
+      if ((lane >> 5) == h) LB::store(buf, lane & 31, v);
+      wave_sync();
+      if (om.full) {
+        T* yrow = y + n1 * N + int64_t(s) * M;
+        for (int b = lane; b < M; b += 64) {
+          const int k = int(natural_of(uint32_t(b), uint32_t(s), LOGM));
+          if ((k >> (LOGM - 1)) == h) yrow[b] = buf[LB::addr(k - h * HM)];
+        }
+      } else {
+        // the samples of this phase line are y[o .. o + cnt), in sequency
+        // order; pos holds each one's natural position (coalesced reads and
+        // writes)
+        const uint16_t* __restrict__ ps = om.pos + o;
+        T* __restrict__ ys = y + o;
+        for (int t0 = 0; t0 < cnt; t0 += 256) {
+          int kk[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int tt = t0 + lane + 64 * u;
+            const int pv = int(ps[tt < cnt ? tt : cnt - 1]);  // cnt > 0 inside the loop
+            kk[u] = tt < cnt ? pv : -1;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (kk[u] >= 0 && (kk[u] >> (LOGM - 1)) == h) ys[t0 + lane + 64 * u] = buf[LB::addr(kk[u] - h * HM)];
+        }
+      }
+      wave_sync();
+    }
   }
 }
 
@@ -529,8 +538,8 @@ __global__ void __launch_bounds__(256) k_transpose(const T* __restrict__ in, T* 
 template <typename T, int LOGM, int NU>
 hipError_t launch_rowpass_fwd(const T* Z, T* y, const Tables<T>& t, const Omega& om, hipStream_t st) {
   constexpr int M = 1 << LOGM;
-  const int nw = t.Q;  // one wave per phase
-  const size_t smem = size_t(nw) * M * sizeof(T);
+  const int nw = t.Q;  // one wave per phase, half a line of LDS each
+  const size_t smem = size_t(nw) * (M / 2) * sizeof(T);
   const int64_t rows = int64_t(M) * t.Q;
   hipLaunchKernelGGL((k_rowpass_fwd<T, LOGM, NU>), dim3(unsigned(rows)), dim3(64 * nw), smem, st, Z, y, t, om);
   return hipGetLastError();
