@@ -31,10 +31,10 @@ bool supported(int elem_bytes, int logm, int nu, int q);
 
 // Forward row pass: rows r of Z (N x M, natural row order) -> y (gather on Omega).
 template <typename T>
-hipError_t rowpass_fwd(const T* Z, T* y, int logm, const Tables<T>& t, const Omega& om, hipStream_t st);
+hipError_t rowpass_fwd(const T* Z, T* y, int logm, const Tables<T>& t, const Omega& om, int64_t rows, hipStream_t st);
 // Adjoint row pass: y (scatter from Omega) -> rows r of Zt (N x M).
 template <typename T>
-hipError_t rowpass_adj(const T* y, T* Zt, int logm, const Tables<T>& t, const Omega& om, hipStream_t st);
+hipError_t rowpass_adj(const T* y, T* Zt, int logm, const Tables<T>& t, const Omega& om, int64_t rows, hipStream_t st);
 // Forward column pass: rows of xi^T (M x M) -> Z (N x M), Z[s M + k, c] natural order.
 template <typename T>
 hipError_t colpass_fwd(const T* xiT, T* Z, int logm, const Tables<T>& t, hipStream_t st);

@@ -536,20 +536,18 @@ __global__ void __launch_bounds__(256) k_transpose(const T* __restrict__ in, T* 
 
 // ------------------------------------------------------------- dispatch
 template <typename T, int LOGM, int NU>
-hipError_t launch_rowpass_fwd(const T* Z, T* y, const Tables<T>& t, const Omega& om, hipStream_t st) {
+hipError_t launch_rowpass_fwd(const T* Z, T* y, const Tables<T>& t, const Omega& om, int64_t rows, hipStream_t st) {
   constexpr int M = 1 << LOGM;
   const int nw = t.Q;  // one wave per phase, half a line of LDS each
   const size_t smem = size_t(nw) * (M / 2) * sizeof(T);
-  const int64_t rows = int64_t(M) * t.Q;
   hipLaunchKernelGGL((k_rowpass_fwd<T, LOGM, NU>), dim3(unsigned(rows)), dim3(64 * nw), smem, st, Z, y, t, om);
   return hipGetLastError();
 }
 template <typename T, int LOGM, int NU>
-hipError_t launch_rowpass_adj(const T* y, T* Zt, const Tables<T>& t, const Omega& om, hipStream_t st) {
+hipError_t launch_rowpass_adj(const T* y, T* Zt, const Tables<T>& t, const Omega& om, int64_t rows, hipStream_t st) {
   constexpr int M = 1 << LOGM;
   const int nw = t.Q;  // one wave per phase
   const size_t smem = size_t(nw) * M * sizeof(T);
-  const int64_t rows = int64_t(M) * t.Q;
   hipLaunchKernelGGL((k_rowpass_adj<T, LOGM, NU>), dim3(unsigned(rows)), dim3(64 * nw), smem, st, y, Zt, t, om);
   return hipGetLastError();
 }
@@ -601,15 +599,17 @@ bool supported(int elem_bytes, int logm, int nu, int q) {
 }
 
 template <typename T>
-hipError_t rowpass_fwd(const T* Z, T* y, int logm, const Tables<T>& t, const Omega& om, hipStream_t st) {
-#define X(L, V) if (logm == L && t.nu == V) return launch_rowpass_fwd<T, L, V>(Z, y, t, om, st);
+hipError_t rowpass_fwd(const T* Z, T* y, int logm, const Tables<T>& t, const Omega& om, int64_t rows,
+                       hipStream_t st) {
+#define X(L, V) if (logm == L && t.nu == V) return launch_rowpass_fwd<T, L, V>(Z, y, t, om, rows, st);
   WH2WAV_FAST_CASES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 template <typename T>
-hipError_t rowpass_adj(const T* y, T* Zt, int logm, const Tables<T>& t, const Omega& om, hipStream_t st) {
-#define X(L, V) if (logm == L && t.nu == V) return launch_rowpass_adj<T, L, V>(y, Zt, t, om, st);
+hipError_t rowpass_adj(const T* y, T* Zt, int logm, const Tables<T>& t, const Omega& om, int64_t rows,
+                       hipStream_t st) {
+#define X(L, V) if (logm == L && t.nu == V) return launch_rowpass_adj<T, L, V>(y, Zt, t, om, rows, st);
   WH2WAV_FAST_CASES(X)
 #undef X
   return hipErrorInvalidValue;
@@ -659,10 +659,14 @@ hipError_t transpose(const T* in, T* out, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-template hipError_t rowpass_fwd<float>(const float*, float*, int, const Tables<float>&, const Omega&, hipStream_t);
-template hipError_t rowpass_fwd<double>(const double*, double*, int, const Tables<double>&, const Omega&, hipStream_t);
-template hipError_t rowpass_adj<float>(const float*, float*, int, const Tables<float>&, const Omega&, hipStream_t);
-template hipError_t rowpass_adj<double>(const double*, double*, int, const Tables<double>&, const Omega&, hipStream_t);
+template hipError_t rowpass_fwd<float>(const float*, float*, int, const Tables<float>&, const Omega&, int64_t,
+                                       hipStream_t);
+template hipError_t rowpass_fwd<double>(const double*, double*, int, const Tables<double>&, const Omega&, int64_t,
+                                        hipStream_t);
+template hipError_t rowpass_adj<float>(const float*, float*, int, const Tables<float>&, const Omega&, int64_t,
+                                       hipStream_t);
+template hipError_t rowpass_adj<double>(const double*, double*, int, const Tables<double>&, const Omega&, int64_t,
+                                        hipStream_t);
 template hipError_t colpass_fwd<float>(const float*, float*, int, const Tables<float>&, hipStream_t);
 template hipError_t colpass_fwd<double>(const double*, double*, int, const Tables<double>&, hipStream_t);
 template hipError_t colpass_adj<float>(const float*, float*, int, const Tables<float>&, hipStream_t);

@@ -703,13 +703,15 @@ int build_host_plan(const wh2wav_desc* d, HostPlan* P, std::string* err) {
   for (int64_t r = 0; r < P->rows; ++r) P->row_ptr[r + 1] += P->row_ptr[r];
   P->pos16.clear();
   P->seg_ptr.clear();
-  if (d->dim == 2 && !P->full_omega && P->M <= 65536) {
-    const int64_t Q = P->Q, M = P->M;
-    P->seg_ptr.assign((size_t)(P->N * Q + 1), 0);
+  // 2D, and 1D lines of at most 2048 values (one wave per phase line): the
+  // sample list per (row, phase); 1D has the single row n1 = 0
+  if ((d->dim == 2 || d->j <= 11) && !P->full_omega && P->M <= 65536) {
+    const int64_t Q = P->Q, M = P->M, nrows = d->dim == 2 ? P->N : 1;
+    P->seg_ptr.assign((size_t)(nrows * Q + 1), 0);
     P->pos16.resize((size_t)d->m);
     for (int64_t i = 0; i < d->m; ++i) {
       const int64_t v = d->omega[i];
-      const int64_t n1 = v / P->N, n2 = v % P->N;
+      const int64_t n1 = d->dim == 2 ? v / P->N : 0, n2 = d->dim == 2 ? v % P->N : v;
       const int64_t s = n2 / M, b = n2 % M;
       P->seg_ptr[(size_t)(n1 * Q + s + 1)]++;
       const uint64_t g = (uint64_t)(b ^ (b >> 1));

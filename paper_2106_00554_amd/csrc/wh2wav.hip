@@ -448,6 +448,15 @@ bool use_fast1d(const wh2wav_plan_s* p) {
   return H.dim == 1 && wh2wav_fast::supported1d(f64 ? 8 : 4, H.j, H.nu, H.q) && H.j0 <= (f64 ? 13 : 14);
 }
 
+// 1D lines of 128 .. 2048 values: the whole line transform (table product,
+// FWHT, gather / scatter) in one workgroup of Q waves, the 2D row-pass kernel
+// on the single row of the 1D operator.
+bool use_wave1d(const wh2wav_plan_s* p) {
+  const auto& H = p->host;
+  return use_fast1d(p) && H.j <= 11 && wh2wav_fast::supported(H.dtype == WH2WAV_F64 ? 8 : 4, H.j, H.nu, H.q) &&
+         (H.full_omega || !H.pos16.empty());
+}
+
 bool use_fast(const wh2wav_plan_s* p) {
   const auto& H = p->host;
   return H.dim == 2 && wh2wav_fast::supported(H.dtype == WH2WAV_F64 ? 8 : 4, H.j, H.nu, H.q);
@@ -517,7 +526,11 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
     T* L = S0 + M;
     const auto ft = fast_tables_of<T>(p);
     if (run(0)) HIP_OK(wh2wav_fast::idwt1d<T>(x, W, S0, H.j0, H.j, ft, st));
-    if (run(1)) HIP_OK(wh2wav_fast::line1d_fwd<T>(W, L, y, H.j, ft, p->d_pos32, H.m, H.full_omega ? 1 : 0, st));
+    if (use_wave1d(p)) {
+      if (run(1)) HIP_OK(wh2wav_fast::rowpass_fwd<T>(W, y, H.j, ft, fast_omega_of(p), 1, st));
+    } else if (run(1)) {
+      HIP_OK(wh2wav_fast::line1d_fwd<T>(W, L, y, H.j, ft, p->d_pos32, H.m, H.full_omega ? 1 : 0, st));
+    }
     return WH2WAV_OK;
   }
   if (H.dim == 1) {
@@ -546,7 +559,7 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
     HIP_OK(wh2wav_fast::idwt2d<T>(x, TMP, W, Z, M, H.j0, H.j, fast_tables_of<T>(p), st));
   if (fast) {
     if (run(1)) HIP_OK(wh2wav_fast::colpass_fwd<T>(TMP, Z, H.j, fast_tables_of<T>(p), st));
-    if (run(2)) HIP_OK(wh2wav_fast::rowpass_fwd<T>(Z, y, H.j, fast_tables_of<T>(p), fast_omega_of(p), st));
+    if (run(2)) HIP_OK(wh2wav_fast::rowpass_fwd<T>(Z, y, H.j, fast_tables_of<T>(p), fast_omega_of(p), N, st));
     return WH2WAV_OK;
   }
   int rc = check_and_set_smem<T>((const void*)k_fwd_lines<T>, line_smem(p, sizeof(T), true));
@@ -588,7 +601,11 @@ int adjoint_impl(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t
     T* S0 = W + M;
     T* L = S0 + M;
     const auto ft = fast_tables_of<T>(p);
-    if (run(0)) HIP_OK(wh2wav_fast::line1d_adj<T>(y, L, W, H.j, ft, p->d_pos32, H.m, H.full_omega ? 1 : 0, st));
+    if (use_wave1d(p)) {
+      if (run(0)) HIP_OK(wh2wav_fast::rowpass_adj<T>(y, W, H.j, ft, fast_omega_of(p), 1, st));
+    } else if (run(0)) {
+      HIP_OK(wh2wav_fast::line1d_adj<T>(y, L, W, H.j, ft, p->d_pos32, H.m, H.full_omega ? 1 : 0, st));
+    }
     if (run(2)) HIP_OK(wh2wav_fast::dwt1d<T>(W, x, S0, H.j0, H.j, ft, st));
     return WH2WAV_OK;
   }
@@ -614,7 +631,7 @@ int adjoint_impl(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t
   T* TMP = W + M * M;
   T* Z = TMP + M * M;
   if (use_fast(p)) {
-    if (run(0)) HIP_OK(wh2wav_fast::rowpass_adj<T>(y, Z, H.j, fast_tables_of<T>(p), fast_omega_of(p), st));
+    if (run(0)) HIP_OK(wh2wav_fast::rowpass_adj<T>(y, Z, H.j, fast_tables_of<T>(p), fast_omega_of(p), N, st));
     if (run(1)) HIP_OK(wh2wav_fast::colpass_adj<T>(Z, TMP, H.j, fast_tables_of<T>(p), st));
     if (run(2)) HIP_OK(wh2wav_fast::dwt2d<T>(TMP, x, W, Z, M, H.j0, H.j, fast_tables_of<T>(p), st));
     return WH2WAV_OK;
@@ -725,6 +742,9 @@ int wh2wav_plan(const wh2wav_desc* desc, wh2wav_plan_t* out) {
   if (use_fast1d(p)) {
     hipError_t e = H.dtype == WH2WAV_F64 ? wh2wav_fast::prepare_1d<double>(H.nu)
                                          : wh2wav_fast::prepare_1d<float>(H.nu);
+    if (e == hipSuccess && use_wave1d(p))
+      e = H.dtype == WH2WAV_F64 ? wh2wav_fast::prepare_lines<double>(H.j, H.nu)
+                                : wh2wav_fast::prepare_lines<float>(H.j, H.nu);
     if (e != hipSuccess) {
       delete p;
       return fail(WH2WAV_EHIP, std::string("kernel setup: ") + hipGetErrorString(e));

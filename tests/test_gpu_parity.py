@@ -43,6 +43,8 @@ CASES_1D = [
     (3, 3, 1, 3, None), (3, 6, 2, 3, 0.25),
     (4, 3, 2, 3, 0.6), (4, 10, 1, 3, None), (4, 8, 3, 3, 0.2),
     (6, 4, 1, 4, None), (8, 4, 2, 4, 0.5), (8, 7, 2, 4, None),
+    # lines of 128 .. 2048 values: one workgroup per transform (wave line kernels)
+    (3, 9, 2, 3, 0.3), (6, 10, 1, 4, 0.2), (8, 11, 1, 4, 0.15), (2, 11, 2, 2, None), (4, 9, 3, 3, 0.1),
 ]
 
 
