@@ -18,10 +18,13 @@ issue: their roofline is algorithmic flops (table-product FMAs and FWHT
 additions per output sample) against the FP32 FMA peak without packed
 instructions, with the HBM figures alongside.
 
-Two more legs are reported in the same JSON line (skip with --no-extras):
+More legs are reported in the same JSON line (skip with --no-extras):
 * "autograd": the 1024^2 db4 q=1 FP32 operator (25 % Omega) through the
   torch.autograd.Function (gradient of 0.5 ||P A x - y||^2 by backward), the
   plain pair on the same operator, and 200 FISTA iterations;
+* "round_robin": the default workload on four independent operators in turn
+  (about 600 MB live, beyond the 256 MB MALL), pairs/s and the row passes'
+  per-launch time and HBM rate;
 * "batched": 96 uneven instances (1D 2^12..2^16, 2D 128^2..512^2 and 1024^2,
   db2/db4/db8, q = 1, 2, 10-30 % Omega, FP32) as one graph launch per
   direction after the schedule autotuner, against per-instance plain calls.
@@ -220,6 +223,68 @@ def small_configs_leg(torch, steps):
     return out
 
 
+def round_robin_leg(torch, steps, name="2d_db8_j11_q2_12.5pct", copies=4):
+    """The roofline workload on `copies` independent operators (own plan, sample
+    list, workspace and vectors each: about 600 MB live at four copies, more
+    than the 256 MB MALL), one pair per step in turn, so that every pass
+    reads its inputs from HBM rather than the MALL.  Reports pairs/s and the
+    per-launch duration and HBM rate of the two row passes."""
+    from paper_2106_00554_amd import _abi
+    from paper_2106_00554_amd.operator import Wh2Wav
+    from tests import inputs
+
+    w = inputs.WORKLOADS[name]
+    X, omega = inputs.workload_inputs(name)
+    dt = torch.float32
+    ops, xs, ys, xas = [], [], [], []
+    for c in range(copies):
+        o = Wh2Wav(w["dim"], w["j"], w["q"], w["nu"], w["j0"], dt, omega)
+        ops.append(o)
+        xs.append(torch.tensor(X * (1.0 + 0.01 * c), dtype=dt, device=o.device))
+        ys.append(torch.empty(o.m, dtype=dt, device=o.device))
+        xas.append(torch.empty(o.x_shape, dtype=dt, device=o.device))
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    nf = _abi.wh2wav_stage_count(ops[0]._plan, 0)
+    na = _abi.wh2wav_stage_count(ops[0]._plan, 1)
+    fwd_row, adj_row = ("fwd", nf - 1), ("adj", 0)  # the row passes (gather / scatter)
+    keys = [("fwd", s) for s in range(nf)] + [("adj", s) for s in range(na)]
+
+    def run(c, key):
+        o, d = ops[c], key[0]
+        wsp = o.workspace.data_ptr()
+        if d == "fwd":
+            _abi.wh2wav_forward_stage(o._plan, key[1], xs[c].data_ptr(), ys[c].data_ptr(), wsp, sp)
+        else:
+            _abi.wh2wav_adjoint_stage(o._plan, key[1], ys[c].data_ptr(), xas[c].data_ptr(), wsp, sp)
+
+    for c in range(copies):
+        for key in keys:
+            run(c, key)
+    n = steps * copies
+    ev = {k: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+          for k in (fwd_row, adj_row)}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n):
+        c = i % copies
+        for key in keys:
+            if key in ev:
+                ev[key][i][0].record(stream)
+                run(c, key)
+                ev[key][i][1].record(stream)
+            else:
+                run(c, key)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    nbytes = stage_bytes(w, ops[0].m, 4)
+    out = {"workload": name, "copies": copies, "pairs_per_s": n / elapsed, "ms_per_pair": elapsed / n * 1e3}
+    for key, label in ((fwd_row, "k_rowpass_fwd"), (adj_row, "k_rowpass_adj")):
+        ms = sum(b.elapsed_time(e) for b, e in ev[key]) / n
+        out[label] = {"launch_ms": ms, "hbm_GBs": nbytes[key] / (ms * 1e-3) / 1e9}
+    return out
+
+
 def batched_leg(torch, steps):
     from paper_2106_00554_amd.operator import Wh2Wav, Wh2WavBatch
     from tests import inputs
@@ -267,7 +332,7 @@ def main():
     ap.add_argument("--dtype", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--only", choices=["batched", "autograd", "small"], default=None,
+    ap.add_argument("--only", choices=["batched", "autograd", "small", "round_robin"], default=None,
                     help="run one extra leg alone (for profiling) and print its JSON")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -284,7 +349,8 @@ def main():
     import torch
 
     if args.only:
-        leg = {"batched": batched_leg, "autograd": autograd_leg, "small": small_configs_leg}[args.only]
+        leg = {"batched": batched_leg, "autograd": autograd_leg, "small": small_configs_leg,
+               "round_robin": round_robin_leg}[args.only]
         print(json.dumps({args.only: leg(torch, max(3, args.steps // 5))}), flush=True)
         return
 
@@ -392,6 +458,7 @@ def main():
         out["autograd"] = autograd_leg(torch, max(5, args.steps // 2))
         out["batched"] = batched_leg(torch, max(3, args.steps // 5))
         out["small_configs"] = small_configs_leg(torch, args.steps)
+        out["round_robin"] = round_robin_leg(torch, max(3, args.steps // 5))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(name, X, omega, args.cpu_budget)
     print(json.dumps(out), flush=True)
