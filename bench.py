@@ -341,8 +341,9 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (the operator is measured on one MI355X); "
-              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        print("bench.py: the operator is measured on one MI355X only; "
+              f"--gpus {args.gpus} is not supported (see the sharding notes in the design document)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

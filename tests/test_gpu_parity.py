@@ -1,8 +1,7 @@
 """GPU parity: the HIP path through the C ABI against the CPU oracle.
 
-Bar: relative l2 error <= 1e-12 in FP64 and <= 1e-5 in FP32 (the tolerances
-of the specification this build targets); FP32 errors are also reported
-against the FP64 GPU result.  Sizes span several tiles and every boundary
+Bar: relative l2 error <= 1e-12 in FP64 and <= 1e-5 in FP32; FP32 errors
+are also reported against the FP64 GPU result.  Sizes span several tiles and every boundary
 regime: j = J0 (no interior functions), Haar, empty and ragged Omega rows.
 """
 import numpy as np
