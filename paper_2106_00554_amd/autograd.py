@@ -84,7 +84,8 @@ class Wh2WavLayer(torch.nn.Module):
 
 
 def soft_threshold(z, t):
-    return torch.sign(z) * torch.clamp(z.abs() - t, min=0.0)
+    """sign(z) max(|z| - t, 0) for t >= 0, one elementwise kernel."""
+    return torch.nn.functional.softshrink(z, t) if t > 0 else z.clone()
 
 
 def objective(op, x, y, lam):
@@ -110,9 +111,11 @@ def fista(op, y, lam, iters, x0=None, L=1.0, callback=None):
         loss = 0.5 * torch.dot(r, r)
         (grad,) = torch.autograd.grad(loss, z)
         with torch.no_grad():
-            x_new = soft_threshold(z - step * grad, step * lam)
+            x_new = soft_threshold(torch.add(z, grad, alpha=-step), step * lam)
             t_new = 0.5 * (1.0 + (1.0 + 4.0 * t * t) ** 0.5)
-            z = x_new + ((t - 1.0) / t_new) * (x_new - x)
+            # z = x_new + beta (x_new - x), beta = (t - 1) / t_new: lerp with
+            # weight 1 + beta >= 1 evaluates exactly this expression
+            z = torch.lerp(x, x_new, 1.0 + (t - 1.0) / t_new)
         x, t = x_new, t_new
         if callback is not None:
             callback(k, x)
