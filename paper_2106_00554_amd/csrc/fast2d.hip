@@ -110,13 +110,28 @@ __device__ __forceinline__ void line_forward(const T (&xi)[R], T (&v)[R], int s,
     for (int m = 0; m < NU; ++m) bv = fma(left ? eL[m] : eR[m], band[(p * NU + m) * Q + s], bv);
     bv = lane < 2 * B ? bv : T(0);
   }
+  if constexpr (R >= B) {
+    // the bands sit in lanes 0 and 63: masked adds, one instruction each
+    T bl[B], br[B];
 #pragma unroll
-  for (int e = 0; e < B; ++e) {
-    const T a = read_lane(bv, e), b = read_lane(bv, B + e);
-    constexpr int M = 64 * R;
-    const int pr = M - B + e;  // right band position
-    v[e % R] += lane == e / R ? a : T(0);
-    v[pr % R] += lane == pr / R ? b : T(0);
+    for (int e = 0; e < B; ++e) bl[e] = read_lane(bv, e), br[e] = read_lane(bv, B + e);
+    if (lane == 0) {
+#pragma unroll
+      for (int e = 0; e < B; ++e) v[e] += bl[e];
+    }
+    if (lane == 63) {
+#pragma unroll
+      for (int e = 0; e < B; ++e) v[R - B + e] += br[e];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < B; ++e) {
+      const T a = read_lane(bv, e), b = read_lane(bv, B + e);
+      constexpr int M = 64 * R;
+      const int pr = M - B + e;  // right band position
+      v[e % R] += lane == e / R ? a : T(0);
+      v[pr % R] += lane == pr / R ? b : T(0);
+    }
   }
   fwht_wave<T, R>(v, lane);
 }
