@@ -27,8 +27,9 @@ using namespace wave;
 // Halo: window w[0 .. R+2H) with w[H + r] = x[r]; the H values on each side
 // come from the neighbouring lanes (from several lanes when H > R), zero
 // beyond the ends of the line.  Position p of the line is register p % R of
-// lane p / R.
-template <typename T, int R, int H>
+// lane p / R.  ZERO = false: x is already zero at its first and last H
+// positions, which is what the lane exchange wraps around to beyond the ends.
+template <typename T, int R, int H, bool ZERO = true>
 __device__ __forceinline__ void make_window(const T (&x)[R], T (&w)[R + 2 * H], int lane) {
 #pragma unroll
   for (int r = 0; r < R; ++r) w[H + r] = x[r];
@@ -37,17 +38,19 @@ __device__ __forceinline__ void make_window(const T (&x)[R], T (&w)[R + 2 * H], 
     const int dl = 1 + e / R;  // lane distance of position lane R - 1 - e (left) / lane R + R + e (right)
     const T a = shfl_from(x[R - 1 - e % R], (lane - dl) & 63);
     const T b = shfl_from(x[e % R], (lane + dl) & 63);
-    w[H - 1 - e] = lane < dl ? T(0) : a;
-    w[H + R + e] = lane + dl > 63 ? T(0) : b;
+    w[H - 1 - e] = ZERO && lane < dl ? T(0) : a;
+    w[H + R + e] = ZERO && lane + dl > 63 ? T(0) : b;
   }
 }
 
-// v[r] = sum_l x[p - l] T_l  (p = lane R + r, l in [-nu+1, nu-1], tap[l + nu - 1] = T_l)
+// v[r] = sum_l x[p - l] T_l  (p = lane R + r, l in [-nu+1, nu-1], tap[l + nu - 1] = T_l).
+// x is zero at its first and last nu positions (the boundary coefficients
+// enter through the bands), so the halo needs no zeroing at the line ends.
 template <typename T, int R, int NU>
 __device__ __forceinline__ void table_product(const T (&x)[R], T (&v)[R], const T (&tap)[2 * NU - 1], int lane) {
   constexpr int H = NU - 1;
   T w[R + 2 * H];
-  make_window<T, R, H>(x, w, lane);
+  make_window<T, R, H, false>(x, w, lane);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     T acc = 0;
