@@ -66,7 +66,10 @@ __device__ __forceinline__ void table_product_t(const T (&x)[R], T (&acc)[R], co
                                                 int lane) {
   constexpr int H = NU - 1;
   T w[R + 2 * H];
-  make_window<T, R, H>(x, w, lane);
+  // no zeroing at the line ends: the outputs at the first and last nu
+  // positions, the only ones that read beyond the ends, are replaced by the
+  // boundary-column products (place_edges)
+  make_window<T, R, H, false>(x, w, lane);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     T a = acc[r];
