@@ -44,6 +44,7 @@ CASES_1D = [
     (6, 4, 1, 4, None), (8, 4, 2, 4, 0.5), (8, 7, 2, 4, None),
     # lines of 128 .. 2048 values: one workgroup per transform (wave line kernels)
     (3, 9, 2, 3, 0.3), (6, 10, 1, 4, 0.2), (8, 11, 1, 4, 0.15), (2, 11, 2, 2, None), (4, 9, 3, 3, 0.1),
+    (4, 8, 4, 3, 0.3),  # q = 4: sixteen phase waves per workgroup
 ]
 
 
@@ -253,6 +254,7 @@ CASES_2D_WAVE = [
     (2, 7, 1, 2, 0.3), (8, 7, 1, 4, None), (6, 7, 2, 4, 0.25), (4, 7, 3, 3, 0.3),
     (4, 7, 1, 7, 0.3),  # j0 = j: no wavelet level
     (3, 8, 1, 3, 0.2), (8, 8, 2, 4, 0.15), (6, 9, 1, 4, 0.2), (8, 9, 1, 4, None),
+    (3, 7, 4, 3, 0.2),  # q = 4: sixteen phase waves per row workgroup
 ]
 
 
