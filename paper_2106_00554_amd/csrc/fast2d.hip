@@ -13,9 +13,13 @@
 //   * sequency order and the odd-phase mirror are index maps
 //     (k = bitrev(gray(b)) xor (s & 1)), applied in the gather / scatter.
 // Row passes run one workgroup per row of the N x M intermediate, one wave
-// per phase s; column passes read or write the intermediate in 16-column
-// (8 for the adjoint) tiles through an LDS staging area so that every global
-// access is a contiguous segment.
+// per phase s (the 1D operator on lines of up to 2048 values is the same
+// kernel on its single row); the forward one gathers its samples from half a
+// line of LDS at a time.  Column passes read or write the intermediate in
+// 16-column (8 for the adjoint) tiles through an LDS staging area so that
+// every global access is a contiguous segment; the forward one runs two
+// phases per workgroup, the adjoint fetches the next phase's rows while the
+// current one computes.
 #include "fast2d.h"
 #include "wave_ops.h"
 
