@@ -176,7 +176,8 @@ __global__ void __launch_bounds__(256) k_analysis2d_tile(const T* __restrict__ i
 // then (S X) S^T); analysis filters along the array's rows index first.
 
 // Synthesis level k: X[r][c] = (r < half && c < half) ? ll[r][c] : det[r][c]
-// (ll and det share the row stride ld); out = S X S^T (trans: out^T).  Tile: TS x TS outputs, 256 threads, runs of P output pairs.
+// (ll and det share the row stride ld); out = S X S^T (trans: out^T).  Tile:
+// TS x TS outputs, 256 threads, runs of P output pairs.
 template <typename T, int NU, int TS, int P>
 __global__ void __launch_bounds__(256) k_synth2d_direct(const T* __restrict__ ll, const T* __restrict__ det,
                                                         int64_t ld, T* __restrict__ out, int64_t ld_out, int k,
@@ -196,9 +197,11 @@ __global__ void __launch_bounds__(256) k_synth2d_direct(const T* __restrict__ ll
   const int YW = W2 + 1;                      // odd: conflict-free in both directions
   T* Ys = reinterpret_cast<T*>(smem_raw);     // TS x YW: column-filtered rows r0 .. r0+TS-1
   const TileLds<T> tl = load_tables<T, NU>(t, tab_lds, hr, gr);
-  constexpr int RUNS = TS / (2 * P), LO = synth_lo<NU>();
+  // tiles whose rows reach a boundary read the boundary blocks from LDS
+  if (!(pair_is_interior<NU>(r0 >> 1, half) && pair_is_interior<NU>((r0 >> 1) + TS / 2 - 1, half))) __syncthreads();
+  constexpr int RUNS = TS / (2 * P), LO = synth_lo<NU>(), NT = 256;
   // pass 1, columns: item = (window column j, run u of P output row pairs)
-  for (int item = int(threadIdx.x); item < W2 * RUNS; item += 256) {
+  for (int item = int(threadIdx.x); item < W2 * RUNS; item += NT) {
     const int j = item % W2, u = item / W2;
     const int col = j < nc ? clo + j : half + clo + (j - nc);
     const T* ca = (col < half ? ll : det) + col;  // rows 0 .. half-1
@@ -209,9 +212,10 @@ __global__ void __launch_bounds__(256) k_synth2d_direct(const T* __restrict__ ll
       const int64_t off = int64_t(i0 + LO) * ld;
       synth_run<T, NU, P>(ca + off, cd + off, int(ld), hr, gr, e, o);
     } else {
-      // boundary blocks from global memory (the LDS copy is not yet visible)
       const int64_t off = int64_t(rlo) * ld;
-      synth_run_edge<T, NU, P>(ca + off, cd + off, int(ld), rlo, rhi, i0, half, hr, gr, t.synL, t.synR, e, o);
+      // FP64 keeps its registers: there the hoisted loads cost a wave per SIMD
+      synth_run_edge<T, NU, P, (P <= 2 && sizeof(T) == 4)>(ca + off, cd + off, int(ld), rlo, rhi, i0, half, hr, gr,
+                                                           tl.sLs, tl.sRs, e, o);
     }
     T* yc = Ys + 2 * u * P * YW + j;
 #pragma unroll
@@ -223,7 +227,7 @@ __global__ void __launch_bounds__(256) k_synth2d_direct(const T* __restrict__ ll
   // registers with lanes over r (consecutive addresses).  Otherwise, with
   // short runs, lanes run over u (each row segment written by consecutive
   // lanes); with long runs the tile is staged in LDS and written row by row.
-  static_assert(TS * RUNS <= 256, "one row item per thread");
+  static_assert(TS * RUNS <= NT, "one row item per thread");
   constexpr bool STAGE = P >= 4;
   const int item = int(threadIdx.x);
   const bool rfast = trans || STAGE;
@@ -265,7 +269,7 @@ __global__ void __launch_bounds__(256) k_synth2d_direct(const T* __restrict__ ll
   }
   __syncthreads();
   const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
-  for (int rr = wave; rr < TS; rr += 4)
+  for (int rr = wave; rr < TS; rr += NT / 64)
     for (int cc = lane; cc < TS; cc += 64) out[int64_t(r0 + rr) * ld_out + c0 + cc] = Os[rr * OW + cc];
 }
 
@@ -292,9 +296,11 @@ __global__ void __launch_bounds__(256) k_analysis2d_direct(const T* __restrict__
   const int YW = nq + 1;
   T* Ys = reinterpret_cast<T*>(smem_raw);  // 2TH x YW: a rows, then d rows
   const TileLds<T> tl = load_tables<T, NU>(t, tab_lds, hr, gr);
-  constexpr int RUNS = TH / P;
+  // tiles whose rows reach a boundary read the boundary blocks from LDS
+  if (!(A0 >= NU && A0 + TH - 1 < half - NU)) __syncthreads();
+  constexpr int RUNS = TH / P, NT = 256;
   // pass 1, along the row index of `in`: item = (window column jq, run u)
-  for (int item = int(threadIdx.x); item < nq * RUNS; item += 256) {
+  for (int item = int(threadIdx.x); item < nq * RUNS; item += NT) {
     const int jq = item % nq, u = item / nq;
     const T* cx = in + qlo + jq;
     const int m0 = A0 + u * P;
@@ -302,8 +308,8 @@ __global__ void __launch_bounds__(256) k_analysis2d_direct(const T* __restrict__
     if (m0 >= NU && m0 + P - 1 < half - NU)
       analysis_run<T, NU, P>(cx + int64_t(2 * m0 - NU + 1) * ld_in, int(ld_in), hr, gr, a, d);
     else
-      analysis_run_edge<T, NU, P>(cx + int64_t(plo) * ld_in, int(ld_in), plo, phi, m0, half, hr, gr, t.synL,
-                                  t.synR, a, d);
+      analysis_run_edge<T, NU, P>(cx + int64_t(plo) * ld_in, int(ld_in), plo, phi, m0, half, hr, gr, tl.sLs,
+                                  tl.sRs, a, d);
     T* yc = Ys + u * P * YW + jq;
 #pragma unroll
     for (int p = 0; p < P; ++p) yc[p * YW] = a[p], yc[(TH + p) * YW] = d[p];
@@ -314,7 +320,7 @@ __global__ void __launch_bounds__(256) k_analysis2d_direct(const T* __restrict__
   // or (g_c, g_r) (trans = 1).  Lanes run over rho: the transposed case is
   // written straight from registers (consecutive addresses); otherwise the
   // four TH x TH blocks are staged in LDS and written row by row.
-  static_assert(2 * TH * RUNS <= 256, "one row item per thread");
+  static_assert(2 * TH * RUNS <= NT, "one row item per thread");
   const int item = int(threadIdx.x);
   const int rho = item % (2 * TH), u = item / (2 * TH);
   const int m0 = B0 + u * P;
@@ -353,7 +359,7 @@ __global__ void __launch_bounds__(256) k_analysis2d_direct(const T* __restrict__
   }
   __syncthreads();
   const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
-  for (int rr = wave; rr < 2 * TH; rr += 4) {
+  for (int rr = wave; rr < 2 * TH; rr += NT / 64) {
     const int orow = rr < TH ? A0 + rr : half + A0 + (rr - TH);
     for (int oc = lane; oc < 2 * TH; oc += 64) {
       const int ocol = oc < TH ? B0 + oc : half + B0 + (oc - TH);

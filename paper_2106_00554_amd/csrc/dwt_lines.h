@@ -188,13 +188,28 @@ __device__ __forceinline__ void analysis_run(const T* __restrict__ px, int strid
 // for m in the window [wlo, whi], which holds every coefficient the run reads.
 // Interior taps see the boundary coefficients as zero; the boundary blocks
 // then add the contributions of the nu left and nu right boundary functions.
-template <typename T, int NU, int P>
+// HOIST issues the boundary coefficients' loads together with the window's
+// (clamped to the window, used only where the boundary blocks apply), so that
+// a run near both ends waits on memory once; worth its registers for short
+// runs read from global memory.
+template <typename T, int NU, int P, bool HOIST = false>
 __device__ __forceinline__ void synth_run_edge(const T* __restrict__ pa, const T* __restrict__ pd, int stride, int wlo,
                                                int whi, int i0, int half, const T (&hr)[2 * NU],
                                                const T (&gr)[2 * NU], const T* __restrict__ sL,
                                                const T* __restrict__ sR, T (&e)[P], T (&o)[P]) {
   constexpr int LO = synth_lo<NU>(), L = P + synth_hi<NU>() - LO, ROWS = 3 * NU - 1;
   const int size = 2 * half;
+  T hl[NU], hdl[NU], hq[NU], hdq[NU];
+  if constexpr (HOIST) {
+#pragma unroll
+    for (int cc = 0; cc < NU; ++cc) {
+      const int pl = cc, pr = half - 1 - cc;
+      const int ml = (pl < wlo ? wlo : (pl > whi ? whi : pl)) - wlo;
+      const int mr = (pr < wlo ? wlo : (pr > whi ? whi : pr)) - wlo;
+      hl[cc] = pa[ml * stride], hdl[cc] = pd[ml * stride];
+      hq[cc] = pa[mr * stride], hdq[cc] = pd[mr * stride];
+    }
+  }
   T a[L], d[L];
 #pragma unroll
   for (int u = 0; u < L; ++u) {
@@ -226,8 +241,13 @@ __device__ __forceinline__ void synth_run_edge(const T* __restrict__ pa, const T
     T bl[NU], bd[NU];
 #pragma unroll
     for (int cc = 0; cc < NU; ++cc) {
-      const int mc = (cc > whi ? whi : cc) - wlo;
-      const T va = pa[mc * stride], vd = pd[mc * stride];
+      T va, vd;
+      if constexpr (HOIST) {
+        va = hl[cc], vd = hdl[cc];
+      } else {
+        const int mc = (cc > whi ? whi : cc) - wlo;
+        va = pa[mc * stride], vd = pd[mc * stride];
+      }
       bl[cc] = cc < half ? va : T(0);
       bd[cc] = cc < half ? vd : T(0);
     }
@@ -254,8 +274,13 @@ __device__ __forceinline__ void synth_run_edge(const T* __restrict__ pa, const T
 #pragma unroll
     for (int cc = 0; cc < NU; ++cc) {
       const int pos = half - 1 - cc;
-      const int mc = (pos < wlo ? wlo : pos) - wlo;
-      const T va = pa[mc * stride], vd = pd[mc * stride];
+      T va, vd;
+      if constexpr (HOIST) {
+        va = hq[cc], vd = hdq[cc];
+      } else {
+        const int mc = (pos < wlo ? wlo : pos) - wlo;
+        va = pa[mc * stride], vd = pd[mc * stride];
+      }
       br[cc] = pos >= right_first ? va : T(0);
       bd[cc] = pos >= right_first ? vd : T(0);
     }
