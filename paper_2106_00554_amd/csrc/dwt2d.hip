@@ -595,17 +595,19 @@ constexpr int synth_tile(int size) {
   if (sizeof(T) == 4) return size >= 2048 ? 64 : size >= 256 ? 32 : 16;
   return size >= 256 ? 32 : 16;
 }
+// A tile is at least nu wide: the window ranges assume that the outputs
+// which read one end's boundary block lie in the tiles that reach that end.
 template <typename T>
-constexpr int analysis_tile(int half) {
-  if (sizeof(T) == 4) return half >= 1024 ? 32 : half >= 128 ? 16 : 8;
-  return half >= 128 ? 16 : 8;
+constexpr int analysis_tile(int half, int nu) {
+  const int th = sizeof(T) == 4 ? (half >= 1024 ? 32 : half >= 128 ? 16 : 8) : (half >= 128 ? 16 : 8);
+  return th < nu ? 16 : th;
 }
 
 template <typename T, int NU, int TS, int P>
 hipError_t launch_synth_direct(const T* ll, const T* det, T* dst, int64_t M, int k, int trans, const Tables<T>& t,
                                hipStream_t st) {
   const int half = 1 << k, size = 2 * half;
-  if (size % TS) return hipErrorInvalidValue;
+  if (size % TS || TS < NU) return hipErrorInvalidValue;
   const int nc = max_synth_window<NU>(half, TS);
   const size_t smem = size_t(TS) * (2 * nc + 1) * sizeof(T);
   const int ntile = size / TS;
@@ -618,7 +620,7 @@ template <typename T, int NU, int TH, int P>
 hipError_t launch_analysis_direct(const T* src, int trans, T* dst, T* x, int64_t M, int k, const Tables<T>& t,
                                   hipStream_t st) {
   const int half = 1 << k;
-  if (half % TH) return hipErrorInvalidValue;
+  if (half % TH || TH < NU) return hipErrorInvalidValue;
   const int nq = max_analysis_window<NU>(half, TH);
   const size_t smem = size_t(2 * TH) * (nq + 1) * sizeof(T);
   const int ntile = half / TH;
@@ -631,7 +633,7 @@ template <typename T, int NU, int TH, int P>
 hipError_t launch_analysis(const T* src, int trans, T* dst, T* x, int64_t M, int k, const Tables<T>& t,
                            hipStream_t st) {
   const int half = 1 << k;
-  if (half % TH) return hipErrorInvalidValue;
+  if (half % TH || TH < NU) return hipErrorInvalidValue;
   const int nr = max_analysis_window<NU>(half, TH);
   if (nr > analysis_window_max<NU, TH>()) return hipErrorInvalidValue;  // the kernel's load window
   const size_t smem = (size_t(nr) * (nr + 1) + size_t(nr) * (2 * TH + 1)) * sizeof(T);
@@ -700,7 +702,7 @@ hipError_t dwt2d_impl(const T* inT, T* x, T* s0, T* s1, int64_t M, int j0, int j
   for (int k = j - 1; k >= kc; --k) {
     // without a coarse stage the last tiled level writes LL_{j0} into x itself
     T* dst = (!coarse && k == kc) ? x : ((src == s0) ? s1 : s0);
-    const int th = analysis_tile<T>(1 << k);
+    const int th = analysis_tile<T>(1 << k, NU);
     if (th == 32)
       e = launch_analysis_direct<T, NU, 32, 8>(src, trans, dst, x, M, k, t, st);
     else if (th == 16)

@@ -45,6 +45,7 @@ CASES_1D = [
     # lines of 128 .. 2048 values: one workgroup per transform (wave line kernels)
     (3, 9, 2, 3, 0.3), (6, 10, 1, 4, 0.2), (8, 11, 1, 4, 0.15), (2, 11, 2, 2, None), (4, 9, 3, 3, 0.1),
     (4, 8, 4, 3, 0.3),  # q = 4: sixteen phase waves per workgroup
+    (10, 7, 1, 5, 0.4),  # the longest filters
 ]
 
 
@@ -71,6 +72,8 @@ CASES_2D = [
     (3, 3, 2, 3, 0.5), (4, 3, 1, 3, None), (4, 5, 1, 3, 0.25),
     (6, 5, 1, 4, 0.3), (8, 4, 2, 4, 0.2), (8, 6, 1, 4, 0.125),
     (2, 5, 1, 5, 0.3),  # no wavelet level (j0 = j) at M = 32
+    # nu > 8: analysis tiles on the small levels must be at least nu wide
+    (9, 7, 1, 5, 0.3), (10, 6, 1, 5, None),
 ]
 
 
