@@ -587,20 +587,32 @@ int max_analysis_window(int half, int th) {
   return w;
 }
 
-// Tile shapes per level: large tiles with long register runs where a level
-// has enough tiles to fill the chip, smaller ones (more workgroups) on
-// coarser levels.
+// Tile shape (outputs per side) and run length per level, from per-level
+// timings of every candidate: large tiles with long register runs where a
+// level has enough tiles to fill the chip; on the small, latency-bound levels
+// 16-point synthesis and 8-point analysis tiles, with single-output runs where
+// those are faster.  A tile is at least nu wide: the window ranges assume
+// that the outputs which read one end's boundary block lie in the tiles that
+// reach that end.
+struct TileShape {
+  int t, p;
+};
 template <typename T>
-constexpr int synth_tile(int size) {
-  if (sizeof(T) == 4) return size >= 2048 ? 64 : size >= 256 ? 32 : 16;
-  return size >= 256 ? 32 : 16;
+constexpr TileShape synth_shape(int size) {
+  if (sizeof(T) == 4 && size >= 2048) return {64, 8};
+  if (size >= (sizeof(T) == 4 ? 512 : 1024)) return {32, 2};
+  return {16, size == 32 ? 1 : 2};
 }
-// A tile is at least nu wide: the window ranges assume that the outputs
-// which read one end's boundary block lie in the tiles that reach that end.
 template <typename T>
-constexpr int analysis_tile(int half, int nu) {
-  const int th = sizeof(T) == 4 ? (half >= 1024 ? 32 : half >= 128 ? 16 : 8) : (half >= 128 ? 16 : 8);
-  return th < nu ? 16 : th;
+constexpr TileShape analysis_shape(int half, int nu) {
+  TileShape s{8, 1};
+  if (sizeof(T) == 4 && half >= 1024)
+    s = {32, 8};
+  else if (half >= 512)
+    s = {16, 2};
+  else if (sizeof(T) == 4 && half == 256)
+    s = {8, 2};
+  return s.t < nu ? TileShape{16, 2} : s;
 }
 
 template <typename T, int NU, int TS, int P>
@@ -676,11 +688,13 @@ hipError_t idwt2d_impl(const T* x, T* outT, T* s0, T* s1, int64_t M, int j0, int
   for (int k = kc; k < j; ++k) {
     const bool fin = k == j - 1;
     T* dst = fin ? outT : (ll == s0 ? s1 : s0);
-    const int ts = synth_tile<T>(2 << k);
-    if (ts == 64)
+    const TileShape sh = synth_shape<T>(2 << k);
+    if (sh.t == 64)
       e = launch_synth_direct<T, NU, 64, 8>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
-    else if (ts == 32)
+    else if (sh.t == 32)
       e = launch_synth_direct<T, NU, 32, 2>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
+    else if (sh.p == 1)
+      e = launch_synth_direct<T, NU, 16, 1>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
     else
       e = launch_synth_direct<T, NU, 16, 2>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
     if (e != hipSuccess) return e;
@@ -702,11 +716,13 @@ hipError_t dwt2d_impl(const T* inT, T* x, T* s0, T* s1, int64_t M, int j0, int j
   for (int k = j - 1; k >= kc; --k) {
     // without a coarse stage the last tiled level writes LL_{j0} into x itself
     T* dst = (!coarse && k == kc) ? x : ((src == s0) ? s1 : s0);
-    const int th = analysis_tile<T>(1 << k, NU);
-    if (th == 32)
+    const TileShape sh = analysis_shape<T>(1 << k, NU);
+    if (sh.t == 32)
       e = launch_analysis_direct<T, NU, 32, 8>(src, trans, dst, x, M, k, t, st);
-    else if (th == 16)
+    else if (sh.t == 16)
       e = launch_analysis<T, NU, 16, 2>(src, trans, dst, x, M, k, t, st);
+    else if (sh.p == 1)
+      e = launch_analysis<T, NU, 8, 1>(src, trans, dst, x, M, k, t, st);
     else
       e = launch_analysis<T, NU, 8, 2>(src, trans, dst, x, M, k, t, st);
     if (e != hipSuccess) return e;
@@ -728,8 +744,9 @@ hipError_t prepare_impl() {
   const void* kernels[] = {
       (const void*)k_synth2d_coarse<T, NU>,         (const void*)k_analysis2d_coarse<T, NU>,
       (const void*)k_analysis2d_tile<T, NU, 16, 2>, (const void*)k_analysis2d_tile<T, NU, 8, 2>,
-      (const void*)k_synth2d_direct<T, NU, 64, 8>,  (const void*)k_synth2d_direct<T, NU, 32, 2>,
-      (const void*)k_synth2d_direct<T, NU, 16, 2>,  (const void*)k_analysis2d_direct<T, NU, 32, 8>,
+      (const void*)k_analysis2d_tile<T, NU, 8, 1>,  (const void*)k_synth2d_direct<T, NU, 64, 8>,
+      (const void*)k_synth2d_direct<T, NU, 32, 2>,  (const void*)k_synth2d_direct<T, NU, 16, 2>,
+      (const void*)k_synth2d_direct<T, NU, 16, 1>,  (const void*)k_analysis2d_direct<T, NU, 32, 8>,
   };
   for (const void* f : kernels) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);

@@ -46,6 +46,7 @@ CASES_1D = [
     (3, 9, 2, 3, 0.3), (6, 10, 1, 4, 0.2), (8, 11, 1, 4, 0.15), (2, 11, 2, 2, None), (4, 9, 3, 3, 0.1),
     (4, 8, 4, 3, 0.3),  # q = 4: sixteen phase waves per workgroup
     (10, 7, 1, 5, 0.4),  # the longest filters
+    (5, 8, 1, 4, 0.3), (7, 9, 1, 4, None), (9, 6, 2, 5, 0.5),  # the remaining orders
 ]
 
 
@@ -74,6 +75,7 @@ CASES_2D = [
     (2, 5, 1, 5, 0.3),  # no wavelet level (j0 = j) at M = 32
     # nu > 8: analysis tiles on the small levels must be at least nu wide
     (9, 7, 1, 5, 0.3), (10, 6, 1, 5, None),
+    (5, 6, 1, 4, 0.3), (7, 6, 2, 4, None),  # the remaining orders
 ]
 
 
