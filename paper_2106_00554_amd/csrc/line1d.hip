@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(1024) k_synth1d_coarse(const T* __restrict__ x
   T* b = a + S;
   for (int i = tid; i < S; i += 1024) a[i] = x[i];
   __syncthreads();
-  constexpr int CP = 2, LO = synth_lo<NU>();
+  constexpr int CP = 1, LO = synth_lo<NU>();  // one pair per item: twice the items, half the chain
   for (int k = j0; k < kc; ++k) {
     const int half = 1 << k, runs = (half + CP - 1) / CP;
     for (int item = tid; item < runs; item += 1024) {
@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(1024) k_analysis1d_coarse(const T* __restrict_
   T* b = a + S;
   for (int i = tid; i < S; i += 1024) a[i] = in[i];
   __syncthreads();
-  constexpr int CP = 2;
+  constexpr int CP = 1;  // one output pair per item
   for (int k = kc - 1; k >= j0; --k) {
     const int half = 1 << k, size = 2 * half, runs = (half + CP - 1) / CP;
     for (int item = tid; item < runs; item += 1024) {
