@@ -43,7 +43,7 @@ def test_halfline_gram_against_quadrature(nu):
             assert abs(approx - float(G(k, kp))) < 2e-6
 
 
-@pytest.mark.parametrize("nu", [1, 2, 3, 4, 8])
+@pytest.mark.parametrize("nu", [1, 2, 3, 4, 8, 9, 10])
 def test_staggered_supports_and_signs(nu):
     from oracle import filters
     g = filters.wavelet(nu)
@@ -76,7 +76,8 @@ def test_interval_basis_orthonormal_by_quadrature(nu, j):
     assert np.abs(Gm - np.eye(Gm.shape[0])).max() < 5e-5
 
 
-@pytest.mark.parametrize("nu,j,q", [(1, 4, 1), (2, 4, 1), (2, 5, 2), (3, 4, 1), (4, 5, 1), (6, 5, 1), (8, 6, 1)])
+@pytest.mark.parametrize("nu,j,q", [(1, 4, 1), (2, 4, 1), (2, 5, 2), (3, 4, 1), (4, 5, 1), (6, 5, 1), (8, 6, 1),
+                                    (9, 6, 1), (10, 6, 1)])
 def test_polynomial_reproduction(nu, j, q):
     cfg = op.Config(nu, j, q)
     C = basis.multiscale(nu, j, cfg.j0, cfg.J).toarray()
@@ -93,7 +94,7 @@ def test_polynomial_reproduction(nu, j, q):
             assert res > 1e-12, (a, res)     # degree nu is not reproduced
 
 
-@pytest.mark.parametrize("nu,j", [(2, 4), (4, 5), (8, 6)])
+@pytest.mark.parametrize("nu,j", [(2, 4), (4, 5), (8, 6), (10, 6)])
 def test_wavelets_have_zero_mean(nu, j):
     cfg = op.Config(nu, j, 1)
     for k in range(cfg.j0, j):

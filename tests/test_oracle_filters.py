@@ -4,7 +4,7 @@ import pytest
 
 from oracle import filters
 
-NUS = [1, 2, 3, 4, 5, 6, 8]
+NUS = [1, 2, 3, 4, 5, 6, 7, 8, 9, 10]
 
 
 def test_db2_closed_form():
@@ -36,13 +36,14 @@ def test_vanishing_moments(nu):
     assert abs(np.sum(g * c ** nu)) > 1e-6
 
 
-@pytest.mark.parametrize("nu", [2, 3, 4, 6, 8])
+@pytest.mark.parametrize("nu", [2, 3, 4, 5, 6, 7, 8, 9, 10])
 def test_minimum_phase(nu):
     h = filters.daubechies(nu)
     # sum_k h_k z^(2nu-1-k) = (1 + z)^nu Q(z); the zeros of Q lie inside the unit circle
     binom = np.poly1d([1.0, 1.0]) ** nu
     quot, rem = np.polydiv(h, binom.coeffs)
-    assert np.abs(rem).max() < 1e-12
+    # the division's rounding grows with the degree
+    assert np.abs(rem).max() < (1e-12 if nu <= 8 else 1e-11)
     assert quot.size == nu
     assert (np.abs(np.roots(quot)) < 1).all()
 
