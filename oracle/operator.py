@@ -23,17 +23,24 @@ Parity status: pinned (Haar closed form, norm bound, polynomial
 reproduction, Fubini against the dense Kronecker matrix, Table 1 for DB2).
 """
 import numpy as np
+import scipy.sparse as sp
 
 from . import basis, walsh
 
 
 def walsh_rows(J, rows, C):
-    """Rows `rows` of H C (H = Walsh matrix of order 2^J), C sparse (2^J x K)."""
+    """Rows `rows` of H C (H = Walsh matrix of order 2^J), C sparse (2^J x K).
+
+    Each chunk of rows of H is generated once and multiplied with all K
+    columns; C is expanded to a dense array when it fits in 2 GiB, so that
+    the product is one BLAS matrix product per chunk.
+    """
     out = np.empty((len(rows), C.shape[1]))
+    dense = C.toarray() if C.shape[0] * C.shape[1] <= (1 << 28) else None
     step = 256
     for a in range(0, len(rows), step):
         Hr = walsh.walsh_matrix(J, rows=rows[a:a + step])
-        out[a:a + step] = (C.T @ Hr.T).T
+        out[a:a + step] = Hr @ dense if dense is not None else (C.T @ Hr.T).T
     return out
 
 
@@ -86,11 +93,19 @@ class Blocks2D:
         rows = np.arange(cfg.N) if rows is None else np.asarray(rows)
         self.rows = rows
         nu, J = cfg.nu, cfg.J
-        self.phi = {cfg.j0: walsh_rows(J, rows, basis.block(nu, cfg.j0, J, True))}
-        self.psi = {}
+        # every block is H C_block for the same Walsh rows: one product with
+        # the blocks' cell-integral matrices side by side
+        keys = [("phi", cfg.j0)]
         for k in range(cfg.j0, cfg.j):
-            self.phi.setdefault(k, walsh_rows(J, rows, basis.block(nu, k, J, True)))
-            self.psi[k] = walsh_rows(J, rows, basis.block(nu, k, J, False))
+            keys += [("phi", k)] if k != cfg.j0 else []
+            keys += [("psi", k)]
+        parts = [basis.block(nu, k, J, kind == "phi") for kind, k in keys]
+        allcols = walsh_rows(J, rows, sp.hstack(parts).tocsc())
+        self.phi, self.psi = {}, {}
+        c = 0
+        for (kind, k), part in zip(keys, parts):
+            (self.phi if kind == "phi" else self.psi)[k] = allcols[:, c:c + part.shape[1]]
+            c += part.shape[1]
 
     def bands(self):
         """Yield (row slice, col slice, first-dim block, second-dim block)."""

@@ -78,7 +78,7 @@ def test_boundary_bands_match_oracle(nu, j, q):
                     assert abs(table[p, m, s] - ref) < tol, (side, m, p, s, tol)
 
 
-@pytest.mark.parametrize("nu", [1, 2, 3, 4, 6])
+@pytest.mark.parametrize("nu", [1, 2, 3, 4, 6, 8])
 def test_synthesis_blocks_match_oracle(nu):
     """Boundary blocks of the one-level synthesis matrix V_k + W_k -> V_{k+1}.
 

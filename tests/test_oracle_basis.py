@@ -21,7 +21,7 @@ def _trap_gram(F, R):
     return F.T @ (F * w[:, None])
 
 
-@pytest.mark.parametrize("nu", [2, 3, 4])
+@pytest.mark.parametrize("nu", [2, 3, 4, 8])
 def test_halfline_gram_against_quadrature(nu):
     G = halfline.gram_left(nu)
     R = 13
@@ -74,6 +74,31 @@ def test_interval_basis_orthonormal_by_quadrature(nu, j):
     F = np.array(cols).T
     Gm = _trap_gram(F, R)
     assert np.abs(Gm - np.eye(Gm.shape[0])).max() < 5e-5
+
+
+def _interval_basis_points(nu, j, j0, R):
+    cols = [basis.scaling_function_points(nu, j0, m, R) for m in range(1 << j0)]
+    for k in range(j0, j):
+        cols += [basis.wavelet_points(nu, k, m, R) for m in range(1 << k)]
+    return np.array(cols).T
+
+
+@pytest.mark.parametrize("nu,j", [(6, 5), (8, 5)])
+def test_interval_basis_orthonormal_by_extrapolated_quadrature(nu, j):
+    """Orthonormality of the interval basis for the long filters (Sec. 3.2).
+
+    The boundary functions are nonzero with nonzero slope at the ends, so the
+    trapezoid error is c h^2 (it falls by 4 per halving, checked below); one
+    Richardson step (4 G_h/2 - G_h) / 3 removes that term.  Point values come
+    from the point-value cascade, not from the half-line Gram matrix.
+    """
+    j0 = int(np.ceil(np.log2(2 * nu)))
+    G12 = _trap_gram(_interval_basis_points(nu, j, j0, 12), 12)
+    G13 = _trap_gram(_interval_basis_points(nu, j, j0, 13), 13)
+    eye = np.eye(G12.shape[0])
+    e12, e13 = np.abs(G12 - eye).max(), np.abs(G13 - eye).max()
+    assert 3.5 < e12 / e13 < 4.5
+    assert np.abs((4 * G13 - G12) / 3 - eye).max() < 1e-6
 
 
 @pytest.mark.parametrize("nu,j,q", [(1, 4, 1), (2, 4, 1), (2, 5, 2), (3, 4, 1), (4, 5, 1), (6, 5, 1), (8, 6, 1),

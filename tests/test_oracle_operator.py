@@ -180,3 +180,35 @@ def test_sampled_1d_entries_equal_dense_products():
     np.testing.assert_allclose(op.forward_entries_1d(cfg, x, ns), (A @ x)[ns], rtol=0, atol=1e-13)
     cs = np.array([0, 3, 8, 9, 15, 16, 64, 100, 127])
     np.testing.assert_allclose(op.adjoint_entries_1d(cfg, yv, omega, cs), (A[omega].T @ yv)[cs], rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("nu,j,q", [(8, 6, 2), (4, 5, 1)])
+def test_sampled_2d_entries_equal_full_products(nu, j, q):
+    """The entry-by-entry 2D oracle equals the full separable products.
+
+    forward_entries_2d, walsh_column and adjoint_entries_2d are the oracle for
+    the full-size sampled checks; here they are compared with forward_2d_full,
+    adjoint_2d_full and the block columns at a size with boundary rows and
+    columns on both ends.
+    """
+    cfg = op.Config(nu, j, q)
+    N, M = cfg.N, cfg.M
+    blocks = op.Blocks2D(cfg)
+    X = inputs.coefficients_2d(j, cfg.j0, 91)
+    omega = inputs.multilevel_omega_2d(N, 0.3, 92, core=4)
+    yv = inputs.sample_vector(omega.size, 93)
+    alpha = op.forward_2d_full(blocks, X)
+    rng = np.random.default_rng(94)
+    n1 = np.concatenate([[0, 0, N - 1, N - 1, 1, N // 2], rng.integers(0, N, 40)])
+    n2 = np.concatenate([[0, N - 1, 0, N - 1, N - 2, 3], rng.integers(0, N, 40)])
+    np.testing.assert_allclose(op.forward_entries_2d(cfg, X, n1, n2), alpha[n1, n2], rtol=0, atol=1e-13)
+    # each column of a 1D block is walsh_column of that basis function
+    for kind, level, idx in [("phi", cfg.j0, 0), ("phi", cfg.j0, (1 << cfg.j0) - 1), ("phi", j - 1, nu + 1),
+                             ("psi", cfg.j0, 1), ("psi", j - 1, 0), ("psi", j - 1, (1 << (j - 1)) - 1)]:
+        ref = (blocks.phi if kind == "phi" else blocks.psi)[level][:, idx]
+        np.testing.assert_allclose(op.walsh_column(cfg, kind, level, idx), ref, rtol=0, atol=1e-14)
+    xa = op.adjoint_2d_full(blocks, yv, omega)
+    pos = [(0, 0), (0, M - 1), (M - 1, 0), (M - 1, M - 1), (1, 2), (M // 2 - 1, M // 2), (nu, M - nu - 1),
+           (3, 1), (M // 2 + 1, 5)]
+    got = op.adjoint_entries_2d(cfg, yv, omega, pos)
+    np.testing.assert_allclose(got, [xa[a, b] for a, b in pos], rtol=0, atol=1e-13)
