@@ -15,8 +15,16 @@ with HIP events; in the timed region two events per step bracket the
 dominant stage only, on the launch stream, which gives the per-launch
 duration used for the roofline.  The line kernels are bound by vector-ALU
 issue: their roofline is algorithmic flops (table-product FMAs and FWHT
-additions per output sample) against the FP32 FMA peak without packed
-instructions, with the HBM figures alongside.
+additions per output sample) against MI355X's published FP32 vector peak,
+with this build's issue ceiling (packed FP32 disabled: half that peak) and
+the HBM figures alongside.  "pair_hbm" is the whole pair's algorithmic HBM
+bytes (minimal-traffic count) over its time, against 8 TB/s.
+
+After the timed region the workload's forward of x and adjoint of a seeded
+sample vector are taken in FP32 and FP64; the "cpu_baseline" leg times the
+CPU oracle (one whole pair, all cores; a quarter of it on one thread) and
+"oracle_check" states every GPU result's relative l2 error against it, and
+FP32 against FP64 (also for the small configurations).
 
 More legs are reported in the same JSON line (skip with --no-extras):
 * "autograd": the 1024^2 db4 q=1 FP32 operator (25 % Omega) through the
@@ -40,9 +48,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP32 vector FMA peak without packed-FP32 instructions (the build disables
-# them): 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz.
-VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# MI355X's published FP32 vector peak (256 CUs x 4 SIMDs x 2.4 GHz, with
+# packed FP32 instructions): the roofline's peak.
+VALU_PEAK_TFLOPS = 157.3
+# The issue ceiling of this build: packed FP32 is disabled, so an FP32 FMA
+# retires 16 lanes x 2 flops per SIMD cycle, half the published figure.
+VALU_ISSUE_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
 def stage_bytes(w, m, elem):
@@ -67,6 +78,16 @@ def stage_flops(w):
     M, N = 1 << w["j"], 1 << (w["j"] + w["q"])
     per = 2 * (2 * w["nu"] - 1) + w["j"]
     return {("fwd", 1): M * N * per, ("fwd", 2): N * N * per, ("adj", 0): N * N * per, ("adj", 1): M * N * per}
+
+
+def pair_bytes(w, m, elem):
+    """Algorithmic HBM bytes of one forward + adjoint pair by the minimal-traffic
+    count: per direction x (s M^2), y (s m), Omega as a bitmask (N^2 / 8) and one
+    write plus one read of the M x N intermediate (2 s M N) in 2D."""
+    M, N = 1 << w["j"], 1 << (w["j"] + w["q"])
+    if w["dim"] == 1:
+        return 2 * ((M + m) * elem + (N + 7) // 8)
+    return 2 * ((M * M + m) * elem + N * N // 8 + 2 * M * N * elem)
 
 
 STAGE_NAMES = {("fwd", 0): "idwt", ("fwd", 1): "column_pass_fwd", ("fwd", 2): "row_pass_fwd_gather",
@@ -100,38 +121,108 @@ def traffic_for(kernel, workload):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(name, X, omega, budget_s):
-    """The oracle (plain sums, no fast transform) on a bounded sample of the workload."""
+def _rel(a, b):
     import numpy as np
+    a, b = np.asarray(a, dtype=np.float64).ravel(), np.asarray(b, dtype=np.float64).ravel()
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b)) / (nb if nb > 0 else 1.0)
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_oracle_leg(name, X, omega, yv, gpu, small):
+    """The CPU oracle on the host cores, and the GPU outputs checked against it.
+
+    The oracle is the separable dense tier: 1D Walsh-coefficient blocks of the
+    basis functions (the Walsh matrix times their cell integrals, no fast
+    transform), then alpha = sum over bands of A_a X_band A_b^T and the gather.
+    One-time construction (boundary functions, blocks) is timed apart.  All
+    cores: one whole forward of x and one whole adjoint of yv.  One thread: the
+    same pair restricted to a quarter of the Walsh rows n1, times 4.
+
+    gpu holds the GPU outputs of the benchmark workload: forward of x and adjoint
+    of yv, in FP32 and FP64.  small holds those of the small configurations.
+    """
+    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import halfline
     from oracle import operator as op
     from tests import inputs
 
     w = inputs.WORKLOADS[name]
     cfg = op.Config(w["nu"], w["j"], w["q"], w["j0"])
-    N, M = cfg.N, cfg.M
-    rng = np.random.default_rng(0)
-    yv = inputs.sample_vector(omega.size, 31)
-    op.forward_entries_2d(cfg, X, [0], [0])          # one-time boundary construction, untimed
-    nf = 64
-    pick = rng.choice(omega.size, nf, replace=False)
+    N = cfg.N
     t0 = time.perf_counter()
-    op.forward_entries_2d(cfg, X, omega[pick] // N, omega[pick] % N)
-    tf = (time.perf_counter() - t0) / nf
-    na = 2
-    pos = [(M - 1 - int(v), M // 2 + int(v)) for v in rng.integers(0, M // 4, na)]
+    halfline.edge_scaling(cfg.nu, "left"), halfline.edge_scaling(cfg.nu, "right")
+    halfline.edge_wavelets(cfg.nu, "left"), halfline.edge_wavelets(cfg.nu, "right")
+    t_edges = time.perf_counter() - t0
     t0 = time.perf_counter()
-    op.adjoint_entries_2d(cfg, yv, omega, pos)
-    ta = (time.perf_counter() - t0) / na
-    pair_s = omega.size * tf + M * M * ta
+    blocks = op.Blocks2D(cfg)
+    t_blocks = time.perf_counter() - t0
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    t0 = time.perf_counter()
+    y_ref = op.forward_2d_full(blocks, X, omega)
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    x_ref = op.adjoint_2d_full(blocks, yv, omega)
+    t_adj = time.perf_counter() - t0
+    rows = np.arange(N // 4)
+    Y = np.zeros(N * N)
+    Y[omega] = yv
+    Y_rows = Y.reshape(N, N)[rows].copy()
+    del Y
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        op.forward_2d_rows(blocks, X, rows)
+        op.adjoint_2d_rows(blocks, Y_rows, rows)
+        t_one = 4 * (time.perf_counter() - t0)
+    del blocks, Y_rows
+    check = {"workload": name,
+             "fwd_f32_vs_oracle": _rel(gpu["y32"], y_ref), "adj_f32_vs_oracle": _rel(gpu["x32"], x_ref),
+             "fwd_f64_vs_oracle": _rel(gpu["y64"], y_ref), "adj_f64_vs_oracle": _rel(gpu["x64"], x_ref),
+             "fwd_f32_vs_f64": _rel(gpu["y32"], gpu["y64"]), "adj_f32_vs_f64": _rel(gpu["x32"], gpu["x64"])}
+    small_check = {}
+    for key, rec in small.items():
+        sw = inputs.WORKLOADS[rec["workload"]]
+        scfg = op.Config(sw["nu"], sw["j"], sw["q"], sw["j0"])
+        if sw["dim"] == 1:
+            A = op.matrix_1d(scfg)
+            sy, sx = op.forward_1d(A, rec["x"], rec["omega"]), op.adjoint_1d(A, rec["yv"], rec["omega"])
+        else:
+            sb = op.Blocks2D(scfg)
+            sy, sx = op.forward_2d_full(sb, rec["x"], rec["omega"]), op.adjoint_2d_full(sb, rec["yv"], rec["omega"])
+        small_check[key] = {"fwd_vs_oracle": _rel(rec["y"], sy), "adj_vs_oracle": _rel(rec["xa"], sx)}
+    for base in {k.rsplit("_", 1)[0] for k in small}:
+        if f"{base}_f32" in small and f"{base}_f64" in small:
+            a, b = small[f"{base}_f32"], small[f"{base}_f64"]
+            small_check[f"{base}_f32"]["fwd_vs_f64"] = _rel(a["y"], b["y"])
+            small_check[f"{base}_f32"]["adj_vs_f64"] = _rel(a["xa"], b["xa"])
+    check["small_configs"] = small_check
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:
-        cores = os.cpu_count() or 1
-    return {"value": 1.0 / pair_s, "unit": "pairs/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{nf} forward outputs and {na} adjoint coefficients of the {name} workload, "
-                      f"timed one by one; a pair is projected as {omega.size} x and {M * M} x the "
-                      f"per-entry times ({tf * 1e3:.2f} ms, {ta:.2f} s)"}
+        host_cpus = len(os.sched_getaffinity(0))
+    except AttributeError:
+        host_cpus = os.cpu_count() or 1
+    baseline = {"value": 1.0 / (t_fwd + t_adj), "unit": "pairs/s", "cores": int(threads), "kind": "oracle",
+                "sample": f"one whole forward + adjoint pair of the {name} workload in the separable dense "
+                          f"oracle (FP64, BLAS on {threads} threads): forward {t_fwd:.2f} s, adjoint "
+                          f"{t_adj:.2f} s; one-time construction apart (boundary functions {t_edges:.1f} s, "
+                          f"Walsh-coefficient blocks {t_blocks:.1f} s)",
+                "value_1thread": 1.0 / t_one,
+                "sample_1thread": f"the same pair restricted to {rows.size} of the {N} Walsh rows n1, on 1 "
+                                  f"thread, times {N // rows.size}: {t_one:.1f} s per pair",
+                "host_cpus": host_cpus, "cpu_model": _cpu_model(),
+                "setup_s": {"boundary_functions": t_edges, "blocks": t_blocks}}
+    return baseline, check
 
 
 def timed(fn, steps, torch):
@@ -188,16 +279,18 @@ def autograd_leg(torch, steps):
             "fista_rel_error_vs_x_true": err}
 
 
-def small_configs_leg(torch, steps):
-    """The 1D db4 2^10 q=1 FP64 and 2D db4 512^2 q=1 (25 % Omega) workloads: us per pair and
-    effective GB/s (algorithmic bytes of a pair over its time; these working sets fit in the
-    last-level cache, so this is not an HBM figure)."""
+def small_configs_leg(torch, steps, outputs=None):
+    """The 1D db4 2^10 q=1 workload (FP64 and FP32) and the 2D db4 512^2 q=1 (25 % Omega)
+    workload (FP32 and FP64): us per pair and effective GB/s (algorithmic bytes of a pair
+    over its time; these working sets fit in the last-level cache, so this is not an HBM
+    figure).  If `outputs` is a dict, the forward of x and the adjoint of a seeded sample
+    vector are stored there per configuration, for the oracle check."""
     from paper_2106_00554_amd.operator import Wh2Wav
     from tests import inputs
 
     out = {}
-    for name, dtype in (("1d_db4_j10_q1", torch.float64), ("2d_db4_j9_q1_25pct", torch.float32),
-                        ("2d_db4_j9_q1_25pct", torch.float64)):
+    for name, dtype in (("1d_db4_j10_q1", torch.float64), ("1d_db4_j10_q1", torch.float32),
+                        ("2d_db4_j9_q1_25pct", torch.float32), ("2d_db4_j9_q1_25pct", torch.float64)):
         w = inputs.WORKLOADS[name]
         X, omega = inputs.workload_inputs(name)
         opr = Wh2Wav(w["dim"], w["j"], w["q"], w["nu"], w["j0"], dtype, omega)
@@ -218,8 +311,14 @@ def small_configs_leg(torch, steps):
             nbytes = 2 * (M + opr.m) * elem
         else:
             nbytes = 2 * (M * M + opr.m + 2 * M * N + 2 * M * M) * elem
-        out[f"{name}_{'f64' if elem == 8 else 'f32'}"] = {"us_per_pair": t * 1e6, "pairs_per_s": 1.0 / t,
-                                                            "effective_GBs": nbytes / t / 1e9}
+        key = f"{name}_{'f64' if elem == 8 else 'f32'}"
+        out[key] = {"us_per_pair": t * 1e6, "pairs_per_s": 1.0 / t, "effective_GBs": nbytes / t / 1e9}
+        if outputs is not None:
+            yv = inputs.sample_vector(opr.m, 41)
+            ya = opr.forward(x)
+            xb = opr.adjoint(torch.tensor(yv, dtype=dtype, device="cuda"))
+            outputs[key] = {"workload": name, "x": X, "omega": omega, "yv": yv,
+                            "y": ya.cpu().numpy(), "xa": xb.cpu().numpy()}
     return out
 
 
@@ -334,7 +433,6 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--only", choices=["batched", "autograd", "small", "round_robin"], default=None,
                     help="run one extra leg alone (for profiling) and print its JSON")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy MIB MiB device-to-device once before the run (a kernel of known traffic "
                          "for scaling hardware counters)")
@@ -434,14 +532,16 @@ def main():
         roofline = {"bound": "alu", "kernel": kernel, "achieved": tflops, "peak": VALU_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": tflops / VALU_PEAK_TFLOPS, "traffic": traffic,
                     "algorithmic_flops": flops, "launch_ms": dom_ms,
+                    "issue_peak": VALU_ISSUE_TFLOPS, "issue_frac": tflops / VALU_ISSUE_TFLOPS,
                     "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes": nbytes[dom]}}
     else:
         roofline = {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                     "algorithmic_bytes": nbytes[dom], "launch_ms": dom_ms}
+    pb = pair_bytes(w, opr.m, elem)
     out = {
-        "metric": "forward+adjoint matvec pairs/sec",
+        "metric": "forward+adjoint matvec pairs/sec and HBM GB/s (% peak), plain vs batched",
         "value": args.steps / elapsed,
         "unit": "pairs/s",
         "n_gpus": 1,
@@ -457,14 +557,31 @@ def main():
                    "N": 1 << (w["j"] + w["q"]), "q": w["q"], "omega_density": w["density"], "m": opr.m},
         "stages_ms_warmup": {STAGE_NAMES[k]: round(v, 4) for k, v in warm_stage.items()},
         "roofline": roofline,
+        "pair_hbm": {"algorithmic_bytes": pb, "achieved_GBs": pb / (elapsed / args.steps) / 1e9,
+                     "peak": HBM_PEAK_GBS, "frac": pb / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBS,
+                     "path_bytes": sum(nbytes.values()) if w["dim"] == 2 else None},
     }
+    # outputs for the oracle check (outside the timed region): forward of x
+    # and adjoint of a seeded sample vector, in this precision and the other
+    check = {}
+    small_out = {} if not args.no_cpu_baseline else None
+    if not args.no_cpu_baseline and w["dim"] == 2:
+        yv = inputs.sample_vector(opr.m, 31)
+        other = torch.float64 if dtype == torch.float32 else torch.float32
+        opr2 = Wh2Wav(w["dim"], w["j"], w["q"], w["nu"], w["j0"], other, omega)
+        for o, dt in ((opr, dtype), (opr2, other)):
+            tag = "32" if dt == torch.float32 else "64"
+            check["y" + tag] = o.forward(torch.tensor(X, dtype=dt, device=dev)).cpu().numpy()
+            check["x" + tag] = o.adjoint(torch.tensor(yv, dtype=dt, device=dev)).cpu().numpy()
+        del opr2
+        torch.cuda.empty_cache()
     if not args.no_extras:
         out["autograd"] = autograd_leg(torch, max(5, args.steps // 2))
         out["batched"] = batched_leg(torch, max(3, args.steps // 5))
-        out["small_configs"] = small_configs_leg(torch, args.steps)
+        out["small_configs"] = small_configs_leg(torch, args.steps, small_out)
         out["round_robin"] = round_robin_leg(torch, max(3, args.steps // 5))
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(name, X, omega, args.cpu_budget)
+    if check:
+        out["cpu_baseline"], out["oracle_check"] = cpu_oracle_leg(name, X, omega, yv, check, small_out or {})
     print(json.dumps(out), flush=True)
 
 

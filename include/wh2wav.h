@@ -40,9 +40,13 @@
  *   owned device pointers; x, y and ws must not overlap.  Calls are
  *   asynchronous on `stream` (a hipStream_t, or NULL for the null stream).
  *   Every function returns WH2WAV_OK (0) or a negative status; nothing
- *   throws across this interface.  Argument errors are detected on the host
- *   before any launch.  wh2wav_last_error() returns a thread-local message
- *   for the last failure on the calling thread.
+ *   throws across this interface (a failed host allocation inside a call
+ *   returns WH2WAV_ENOMEM, any other internal exception WH2WAV_EINTERNAL).
+ *   Argument errors are detected on the host before any launch.  A plan or
+ *   batch handle that was destroyed, or never returned by a plan call, is
+ *   refused with WH2WAV_EINVAL before it is dereferenced (destroying NULL is
+ *   a no-op).  wh2wav_last_error() returns a thread-local message for the
+ *   last failure on the calling thread.
  */
 #ifndef WH2WAV_H
 #define WH2WAV_H

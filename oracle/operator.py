@@ -152,6 +152,27 @@ def adjoint_2d_full(blocks, y, omega=None):
     return X
 
 
+def forward_2d_rows(blocks, X, rows):
+    """Rows n1 in `rows` of the full N x N alpha: sum over bands of A_a[rows] X_band A_b^T."""
+    rows = np.asarray(rows)
+    alpha = np.zeros((rows.size, blocks.cfg.N))
+    for rs, cs, Aa, Bb in blocks.bands():
+        alpha += Aa[rows] @ X[rs, cs] @ Bb.T
+    return alpha
+
+
+def adjoint_2d_rows(blocks, Y_rows, rows):
+    """x = A^T y for a sample array y that vanishes outside the rows n1 in `rows`;
+    Y_rows holds those rows (len(rows) x N).  Summed over disjoint row sets this
+    is adjoint_2d_full."""
+    rows = np.asarray(rows)
+    cfg = blocks.cfg
+    X = np.zeros((cfg.M, cfg.M))
+    for rs, cs, Aa, Bb in blocks.bands():
+        X[rs, cs] += Aa[rows].T @ Y_rows @ Bb
+    return X
+
+
 def quadtree_functions(cfg, c1, c2):
     """For quadtree position (c1, c2): ((kind1, level1, idx1), (kind2, level2, idx2))."""
     j0 = cfg.j0

@@ -2,6 +2,8 @@
 #pragma once
 
 #include <cstdint>
+#include <exception>
+#include <new>
 #include <string>
 
 #include "../../include/wh2wav.h"
@@ -10,6 +12,33 @@ namespace wh2wav {
 
 // Stores `msg` as the calling thread's last error and returns `code`.
 int set_error(int code, const std::string& msg);
+
+// The same, for use while handling an exception: never throws (on a failed
+// copy of the message the last error is left empty).
+int set_error_nothrow(int code, const char* msg) noexcept;
+
+// Runs the body of an extern "C" entry point so that no C++ exception crosses
+// the interface: std::bad_alloc becomes WH2WAV_ENOMEM, any other exception
+// WH2WAV_EINTERNAL, each with a message in wh2wav_last_error().
+template <typename F>
+int guarded(F&& body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return set_error_nothrow(WH2WAV_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return set_error_nothrow(WH2WAV_EINTERNAL, e.what());
+  } catch (...) {
+    return set_error_nothrow(WH2WAV_EINTERNAL, "unexpected internal error");
+  }
+}
+
+// Registry of live handles (plans and batches): calls with a handle that was
+// never returned by a plan call, or was already destroyed, fail with
+// WH2WAV_EINVAL instead of touching freed memory.
+void handle_add(const void* h);
+bool handle_remove(const void* h);
+bool handle_live(const void* h);
 
 struct PlanShape {
   int dim, j, q, nu, dtype;

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <memory>
 #include <new>
 #include <numeric>
 #include <string>
@@ -30,8 +31,21 @@ struct GraphEntry {
   int dir, branches, order;
   const void* ws;
   std::vector<const void*> in, out;
-  hipGraphExec_t exec;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;  // recorded after every launch of `exec`
 };
+
+// Waits for the last launch of a cached graph, then frees it: a graph may
+// still run on the caller's stream when it leaves the cache.
+void drop_graph(GraphEntry& g) {
+  if (g.done) {
+    (void)hipEventSynchronize(g.done);
+    (void)hipEventDestroy(g.done);
+  }
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  g.done = nullptr;
+  g.exec = nullptr;
+}
 
 }  // namespace
 
@@ -75,7 +89,7 @@ std::vector<int> schedule_order(const wh2wav_batch_s* b) {
 }
 
 void release_batch(wh2wav_batch_s* b) {
-  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+  for (auto& g : b->graphs) drop_graph(g);
   b->graphs.clear();
   for (auto* p : b->plans) wh2wav_destroy(p);
   b->plans.clear();
@@ -150,41 +164,50 @@ int run(wh2wav_batch_s* b, int dir, const void* const* in, void* const* out, voi
   }
   if (!hit) {
     if (b->graphs.size() >= kMaxGraphs) {
-      (void)hipGraphExecDestroy(b->graphs.front().exec);
+      drop_graph(b->graphs.front());
       b->graphs.erase(b->graphs.begin());
     }
     GraphEntry e;
     e.dir = dir, e.branches = b->branches, e.order = b->order, e.ws = ws;
     e.in.assign(in, in + n);
     e.out.assign(out, out + n);
+    HIP_B(hipEventCreateWithFlags(&e.done, hipEventDisableTiming));
     rc = capture(b, dir, in, out, ws, &e.exec);
-    if (rc) return rc;
+    if (rc) {
+      drop_graph(e);
+      return rc;
+    }
     b->graphs.push_back(std::move(e));
     hit = &b->graphs.back();
   }
   HIP_B(hipGraphLaunch(hit->exec, static_cast<hipStream_t>(stream)));
+  HIP_B(hipEventRecord(hit->done, static_cast<hipStream_t>(stream)));
   return WH2WAV_OK;
 }
 
-}  // namespace
+// A live batch handle (one returned by wh2wav_plan_batch and not destroyed).
+int check_batch(const wh2wav_batch_s* b) {
+  if (!b) return fail(WH2WAV_EINVAL, "batch is NULL");
+  if (!wh2wav::handle_live(b)) return fail(WH2WAV_EINVAL, "not a live batch (destroyed, or never created)");
+  return WH2WAV_OK;
+}
 
-extern "C" {
+void free_batch(wh2wav_batch_s* b) {
+  release_batch(b);
+  delete b;
+}
 
-int wh2wav_plan_batch(const wh2wav_desc* descs, int count, wh2wav_batch_t* out) {
+int plan_batch_body(const wh2wav_desc* descs, int count, wh2wav_batch_t* out) {
   if (!out) return fail(WH2WAV_EINVAL, "out is NULL");
   *out = nullptr;
   if (!descs || count <= 0) return fail(WH2WAV_EINVAL, "need at least one descriptor");
-  auto* b = new (std::nothrow) wh2wav_batch_s();
-  if (!b) return fail(WH2WAV_ENOMEM, "host allocation failed");
+  // owned by `hold` until it is handed out; free_batch releases every plan made so far
+  std::unique_ptr<wh2wav_batch_s, void (*)(wh2wav_batch_s*)> hold(new wh2wav_batch_s(), free_batch);
+  wh2wav_batch_s* b = hold.get();
   for (int i = 0; i < count; ++i) {
     wh2wav_plan_t p = nullptr;
     int rc = wh2wav_plan(&descs[i], &p);
-    if (rc != WH2WAV_OK) {
-      const std::string msg = "instance " + std::to_string(i) + ": " + wh2wav_last_error();
-      release_batch(b);
-      delete b;
-      return fail(rc, msg);
-    }
+    if (rc != WH2WAV_OK) return fail(rc, "instance " + std::to_string(i) + ": " + wh2wav_last_error());
     b->plans.push_back(p);
     b->shape.push_back(wh2wav::plan_shape(p));
     size_t bytes = 0;
@@ -198,40 +221,39 @@ int wh2wav_plan_batch(const wh2wav_desc* descs, int count, wh2wav_batch_t* out) 
     e = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming);
   }
-  if (e != hipSuccess) {
-    release_batch(b);
-    delete b;
-    return fail(WH2WAV_EHIP, std::string("batch streams: ") + hipGetErrorString(e));
-  }
-  *out = b;
+  if (e != hipSuccess) return fail(WH2WAV_EHIP, std::string("batch streams: ") + hipGetErrorString(e));
+  wh2wav::handle_add(b);
+  *out = hold.release();
   return WH2WAV_OK;
 }
 
-int wh2wav_batch_workspace_size(wh2wav_batch_t b, size_t* bytes) {
-  if (!b || !bytes) return fail(WH2WAV_EINVAL, "NULL argument");
+int batch_workspace_size_body(wh2wav_batch_t b, size_t* bytes) {
+  if (int rc = check_batch(b)) return rc;
+  if (!bytes) return fail(WH2WAV_EINVAL, "NULL argument");
   *bytes = b->ws_total;
   return WH2WAV_OK;
 }
 
-int wh2wav_forward_batch(wh2wav_batch_t b, const void* const* xs, void* const* ys, void* ws, void* stream) {
-  if (!b) return fail(WH2WAV_EINVAL, "batch is NULL");
+int forward_batch_body(wh2wav_batch_t b, const void* const* xs, void* const* ys, void* ws, void* stream) {
+  if (int rc = check_batch(b)) return rc;
   return run(b, 0, xs, ys, ws, stream);
 }
 
-int wh2wav_adjoint_batch(wh2wav_batch_t b, const void* const* ys, void* const* xs, void* ws, void* stream) {
-  if (!b) return fail(WH2WAV_EINVAL, "batch is NULL");
+int adjoint_batch_body(wh2wav_batch_t b, const void* const* ys, void* const* xs, void* ws, void* stream) {
+  if (int rc = check_batch(b)) return rc;
   return run(b, 1, ys, xs, ws, stream);
 }
 
-int wh2wav_batch_schedule(wh2wav_batch_t b, int* branches, int* order) {
-  if (!b || !branches || !order) return fail(WH2WAV_EINVAL, "NULL argument");
+int batch_schedule_body(wh2wav_batch_t b, int* branches, int* order) {
+  if (int rc = check_batch(b)) return rc;
+  if (!branches || !order) return fail(WH2WAV_EINVAL, "NULL argument");
   *branches = b->branches;
   *order = b->order;
   return WH2WAV_OK;
 }
 
-int wh2wav_batch_set_schedule(wh2wav_batch_t b, int branches, int order) {
-  if (!b) return fail(WH2WAV_EINVAL, "batch is NULL");
+int batch_set_schedule_body(wh2wav_batch_t b, int branches, int order) {
+  if (int rc = check_batch(b)) return rc;
   if (branches < 1 || branches > kMaxBranches || (order != 0 && order != 1))
     return fail(WH2WAV_EINVAL, "branches must be 1..8 and order 0 or 1");
   b->branches = branches;
@@ -239,9 +261,9 @@ int wh2wav_batch_set_schedule(wh2wav_batch_t b, int branches, int order) {
   return WH2WAV_OK;
 }
 
-int wh2wav_batch_tune(wh2wav_batch_t b, const void* const* xs, void* const* ys, void* const* xa, void* ws,
+int batch_tune_body(wh2wav_batch_t b, const void* const* xs, void* const* ys, void* const* xa, void* ws,
                       void* stream, int reps, float* best_ms) {
-  if (!b) return fail(WH2WAV_EINVAL, "batch is NULL");
+  if (int rc = check_batch(b)) return rc;
   if (reps < 1) return fail(WH2WAV_EINVAL, "reps must be >= 1");
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -285,11 +307,48 @@ int wh2wav_batch_tune(wh2wav_batch_t b, const void* const* xs, void* const* ys, 
   return rc;
 }
 
-int wh2wav_destroy_batch(wh2wav_batch_t b) {
+int destroy_batch_body(wh2wav_batch_t b) {
   if (!b) return WH2WAV_OK;
-  release_batch(b);
-  delete b;
+  if (!wh2wav::handle_remove(b)) return fail(WH2WAV_EINVAL, "not a live batch (destroyed twice, or never created)");
+  free_batch(b);
   return WH2WAV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wh2wav_plan_batch(const wh2wav_desc* descs, int count, wh2wav_batch_t* out) {
+  return wh2wav::guarded([&] { return plan_batch_body(descs, count, out); });
+}
+
+int wh2wav_batch_workspace_size(wh2wav_batch_t b, size_t* bytes) {
+  return wh2wav::guarded([&] { return batch_workspace_size_body(b, bytes); });
+}
+
+int wh2wav_forward_batch(wh2wav_batch_t b, const void* const* xs, void* const* ys, void* ws, void* stream) {
+  return wh2wav::guarded([&] { return forward_batch_body(b, xs, ys, ws, stream); });
+}
+
+int wh2wav_adjoint_batch(wh2wav_batch_t b, const void* const* ys, void* const* xs, void* ws, void* stream) {
+  return wh2wav::guarded([&] { return adjoint_batch_body(b, ys, xs, ws, stream); });
+}
+
+int wh2wav_batch_schedule(wh2wav_batch_t b, int* branches, int* order) {
+  return wh2wav::guarded([&] { return batch_schedule_body(b, branches, order); });
+}
+
+int wh2wav_batch_set_schedule(wh2wav_batch_t b, int branches, int order) {
+  return wh2wav::guarded([&] { return batch_set_schedule_body(b, branches, order); });
+}
+
+int wh2wav_batch_tune(wh2wav_batch_t b, const void* const* xs, void* const* ys, void* const* xa, void* ws,
+                      void* stream, int reps, float* best_ms) {
+  return wh2wav::guarded([&] { return batch_tune_body(b, xs, ys, xa, ws, stream, reps, best_ms); });
+}
+
+int wh2wav_destroy_batch(wh2wav_batch_t b) {
+  return wh2wav::guarded([&] { return destroy_batch_body(b); });
 }
 
 }  // extern "C"

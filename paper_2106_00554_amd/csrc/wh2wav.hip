@@ -29,8 +29,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <new>
 #include <string>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/wh2wav.h"
@@ -687,57 +690,67 @@ void release(wh2wav_plan_s* p) {
 
 }  // namespace
 
+namespace {
+std::mutex g_handles_mu;
+std::unordered_set<const void*>* g_handles = nullptr;  // never freed: outlives static destructors
+}  // namespace
+
 namespace wh2wav {
 int set_error(int code, const std::string& msg) { return fail(code, msg); }
+int set_error_nothrow(int code, const char* msg) noexcept {
+  try {
+    g_last_error = msg;
+  } catch (...) {
+    g_last_error.clear();
+  }
+  return code;
+}
+void handle_add(const void* h) {
+  std::lock_guard<std::mutex> lk(g_handles_mu);
+  if (!g_handles) g_handles = new std::unordered_set<const void*>();
+  g_handles->insert(h);
+}
+bool handle_remove(const void* h) {
+  std::lock_guard<std::mutex> lk(g_handles_mu);
+  return g_handles && g_handles->erase(h) == 1;
+}
+bool handle_live(const void* h) {
+  std::lock_guard<std::mutex> lk(g_handles_mu);
+  return g_handles && g_handles->count(h) == 1;
+}
 PlanShape plan_shape(wh2wav_plan_t p) {
   const auto& H = p->host;
   return PlanShape{H.dim, H.j, H.q, H.nu, H.dtype, H.M, H.N, H.m};
 }
 }  // namespace wh2wav
 
-extern "C" {
+namespace {
 
-const char* wh2wav_last_error(void) { return g_last_error.c_str(); }
-
-int wh2wav_plan(const wh2wav_desc* desc, wh2wav_plan_t* out) {
+int plan_body(const wh2wav_desc* desc, wh2wav_plan_t* out) {
   g_last_error.clear();
   if (!out) return fail(WH2WAV_EINVAL, "out is NULL");
   *out = nullptr;
-  auto* p = new (std::nothrow) wh2wav_plan_s();
-  if (!p) return fail(WH2WAV_ENOMEM, "host allocation failed");
+  // owned by `hold` until it is handed out; release() frees whatever was uploaded
+  std::unique_ptr<wh2wav_plan_s, void (*)(wh2wav_plan_s*)> hold(new wh2wav_plan_s(), release);
+  wh2wav_plan_s* p = hold.get();
   std::string err;
   int rc = wh2wav::build_host_plan(desc, &p->host, &err);
-  if (rc != WH2WAV_OK) {
-    delete p;
-    return fail(rc, err);
-  }
+  if (rc != WH2WAV_OK) return fail(rc, err);
   const auto& H = p->host;
-  if (H.j < 1) {
-    delete p;
-    return fail(WH2WAV_EUNSUPPORTED, "j must be >= 1");
-  }
+  if (H.j < 1) return fail(WH2WAV_EUNSUPPORTED, "j must be >= 1");
   const size_t elem = H.dtype == WH2WAV_F64 ? 8 : 4;
   if (!use_fast(p) && !use_fast1d(p) &&
-      2 * size_t(H.M) * elem + sizeof(int) * (size_t(H.words_per_row) + kThreads) > kMaxLds) {
-    delete p;
+      2 * size_t(H.M) * elem + sizeof(int) * (size_t(H.words_per_row) + kThreads) > kMaxLds)
     return fail(WH2WAV_EUNSUPPORTED, "M too large for the LDS line kernels");
-  }
   rc = H.dtype == WH2WAV_F64 ? prepare_line_kernels<double>() : prepare_line_kernels<float>();
-  if (rc != WH2WAV_OK) {
-    std::string m = g_last_error;
-    delete p;
-    return fail(rc, m);
-  }
+  if (rc != WH2WAV_OK) return rc;
   if (H.dim == 2) {
     hipError_t e = H.dtype == WH2WAV_F64 ? wh2wav_fast::prepare_dwt2d<double>(H.nu)
                                          : wh2wav_fast::prepare_dwt2d<float>(H.nu);
     if (e == hipSuccess && use_fast(p))
       e = H.dtype == WH2WAV_F64 ? wh2wav_fast::prepare_lines<double>(H.j, H.nu)
                                 : wh2wav_fast::prepare_lines<float>(H.j, H.nu);
-    if (e != hipSuccess) {
-      delete p;
-      return fail(WH2WAV_EHIP, std::string("kernel setup: ") + hipGetErrorString(e));
-    }
+    if (e != hipSuccess) return fail(WH2WAV_EHIP, std::string("kernel setup: ") + hipGetErrorString(e));
   }
   if (use_fast1d(p)) {
     hipError_t e = H.dtype == WH2WAV_F64 ? wh2wav_fast::prepare_1d<double>(H.nu)
@@ -745,17 +758,10 @@ int wh2wav_plan(const wh2wav_desc* desc, wh2wav_plan_t* out) {
     if (e == hipSuccess && use_wave1d(p))
       e = H.dtype == WH2WAV_F64 ? wh2wav_fast::prepare_lines<double>(H.j, H.nu)
                                 : wh2wav_fast::prepare_lines<float>(H.j, H.nu);
-    if (e != hipSuccess) {
-      delete p;
-      return fail(WH2WAV_EHIP, std::string("kernel setup: ") + hipGetErrorString(e));
-    }
+    if (e != hipSuccess) return fail(WH2WAV_EHIP, std::string("kernel setup: ") + hipGetErrorString(e));
   }
   rc = H.dtype == WH2WAV_F64 ? upload_tables<double>(p) : upload_tables<float>(p);
-  if (rc != WH2WAV_OK) {
-    std::string m = g_last_error;
-    release(p);
-    return fail(rc, m);
-  }
+  if (rc != WH2WAV_OK) return rc;
   auto upload = [&](void** dst, const void* src, size_t bytes) -> int {
     if (bytes == 0) return WH2WAV_OK;
     HIP_OK(hipMalloc(dst, bytes));
@@ -767,17 +773,25 @@ int wh2wav_plan(const wh2wav_desc* desc, wh2wav_plan_t* out) {
   if (rc == WH2WAV_OK) rc = upload((void**)&p->d_pos16, H.pos16.data(), sizeof(uint16_t) * H.pos16.size());
   if (rc == WH2WAV_OK) rc = upload((void**)&p->d_seg_ptr, H.seg_ptr.data(), sizeof(int64_t) * H.seg_ptr.size());
   if (rc == WH2WAV_OK) rc = upload((void**)&p->d_pos32, H.pos32.data(), sizeof(int32_t) * H.pos32.size());
-  if (rc != WH2WAV_OK) {
-    std::string m = g_last_error;
-    release(p);
-    return fail(rc, m);
-  }
-  *out = p;
+  if (rc != WH2WAV_OK) return rc;
+  wh2wav::handle_add(p);
+  *out = hold.release();
   return WH2WAV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wh2wav_last_error(void) { return g_last_error.c_str(); }
+
+int wh2wav_plan(const wh2wav_desc* desc, wh2wav_plan_t* out) {
+  return wh2wav::guarded([&] { return plan_body(desc, out); });
 }
 
 int wh2wav_workspace_size(wh2wav_plan_t p, size_t* bytes) {
   if (!p || !bytes) return fail(WH2WAV_EINVAL, "NULL argument");
+  if (!wh2wav::handle_live(p)) return fail(WH2WAV_EINVAL, "not a live plan (destroyed, or never created)");
   const auto& H = p->host;
   const size_t elem = H.dtype == WH2WAV_F64 ? 8 : 4;
   if (H.dim == 1)
@@ -789,6 +803,7 @@ int wh2wav_workspace_size(wh2wav_plan_t p, size_t* bytes) {
 
 static int check_call(wh2wav_plan_t p, const void* a, const void* b, void* ws) {
   if (!p) return fail(WH2WAV_EINVAL, "plan is NULL");
+  if (!wh2wav::handle_live(p)) return fail(WH2WAV_EINVAL, "not a live plan (destroyed, or never created)");
   const auto& H = p->host;
   const size_t elem = H.dtype == WH2WAV_F64 ? 8 : 4;
   const size_t in_out[2] = {size_t(H.dim == 1 ? H.M : H.M * H.M) * elem, size_t(H.m) * elem};
@@ -807,23 +822,27 @@ static int check_call(wh2wav_plan_t p, const void* a, const void* b, void* ws) {
 }
 
 static int forward_any(wh2wav_plan_t p, const void* x, void* y, void* ws, void* stream, int stage) {
-  g_last_error.clear();
-  int rc = check_call(p, x, y, ws);
-  if (rc) return rc;
-  auto st = static_cast<hipStream_t>(stream);
-  return p->host.dtype == WH2WAV_F64
-             ? forward_impl<double>(p, static_cast<const double*>(x), static_cast<double*>(y), ws, st, stage)
-             : forward_impl<float>(p, static_cast<const float*>(x), static_cast<float*>(y), ws, st, stage);
+  return wh2wav::guarded([&] {
+    g_last_error.clear();
+    int rc = check_call(p, x, y, ws);
+    if (rc) return rc;
+    auto st = static_cast<hipStream_t>(stream);
+    return p->host.dtype == WH2WAV_F64
+               ? forward_impl<double>(p, static_cast<const double*>(x), static_cast<double*>(y), ws, st, stage)
+               : forward_impl<float>(p, static_cast<const float*>(x), static_cast<float*>(y), ws, st, stage);
+  });
 }
 
 static int adjoint_any(wh2wav_plan_t p, const void* y, void* x, void* ws, void* stream, int stage) {
-  g_last_error.clear();
-  int rc = check_call(p, x, y, ws);
-  if (rc) return rc;
-  auto st = static_cast<hipStream_t>(stream);
-  return p->host.dtype == WH2WAV_F64
-             ? adjoint_impl<double>(p, static_cast<const double*>(y), static_cast<double*>(x), ws, st, stage)
-             : adjoint_impl<float>(p, static_cast<const float*>(y), static_cast<float*>(x), ws, st, stage);
+  return wh2wav::guarded([&] {
+    g_last_error.clear();
+    int rc = check_call(p, x, y, ws);
+    if (rc) return rc;
+    auto st = static_cast<hipStream_t>(stream);
+    return p->host.dtype == WH2WAV_F64
+               ? adjoint_impl<double>(p, static_cast<const double*>(y), static_cast<double*>(x), ws, st, stage)
+               : adjoint_impl<float>(p, static_cast<const float*>(y), static_cast<float*>(x), ws, st, stage);
+  });
 }
 
 int wh2wav_forward(wh2wav_plan_t p, const void* x, void* y, void* ws, void* stream) {
@@ -836,6 +855,7 @@ int wh2wav_adjoint(wh2wav_plan_t p, const void* y, void* x, void* ws, void* stre
 
 int wh2wav_stage_count(wh2wav_plan_t p, int direction, int* count) {
   if (!p || !count || (direction != 0 && direction != 1)) return fail(WH2WAV_EINVAL, "bad argument");
+  if (!wh2wav::handle_live(p)) return fail(WH2WAV_EINVAL, "not a live plan (destroyed, or never created)");
   *count = p->host.dim == 1 ? (direction == 0 ? 2 : 3) : 3;
   return WH2WAV_OK;
 }
@@ -858,11 +878,13 @@ int wh2wav_adjoint_stage(wh2wav_plan_t p, int stage, const void* y, void* x, voi
 }
 
 int wh2wav_destroy(wh2wav_plan_t p) {
+  if (!p) return WH2WAV_OK;
+  if (!wh2wav::handle_remove(p)) return fail(WH2WAV_EINVAL, "not a live plan (destroyed twice, or never created)");
   release(p);
   return WH2WAV_OK;
 }
 
-int wh2wav_host_table(const wh2wav_desc* desc, int which, double* out, size_t capacity, size_t* count) {
+static int host_table_body(const wh2wav_desc* desc, int which, double* out, size_t capacity, size_t* count) {
   g_last_error.clear();
   if (!count) return fail(WH2WAV_EINVAL, "count is NULL");
   wh2wav::HostPlan H;
@@ -888,6 +910,10 @@ int wh2wav_host_table(const wh2wav_desc* desc, int which, double* out, size_t ca
   *count = src->size();
   if (out) std::memcpy(out, src->data(), sizeof(double) * std::min(capacity, src->size()));
   return WH2WAV_OK;
+}
+
+int wh2wav_host_table(const wh2wav_desc* desc, int which, double* out, size_t capacity, size_t* count) {
+  return wh2wav::guarded([&] { return host_table_body(desc, which, out, capacity, count); });
 }
 
 }  // extern "C"

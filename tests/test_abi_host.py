@@ -135,3 +135,42 @@ def test_omega_validation(omega):
     with pytest.raises(abi.Wh2WavError) as e:
         abi.wh2wav_host_table(d, "row_ptr")
     assert e.value.code == abi.WH2WAV_EINVAL
+
+
+def test_handles_that_were_never_created_are_rejected():
+    """A pointer that no plan call returned is refused before it is dereferenced."""
+    bogus = ctypes.c_void_p(0x1000)
+    buf = ctypes.c_void_p(0x2000)
+    for call in (lambda: abi.wh2wav_forward(bogus, buf, ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), None),
+                 lambda: abi.wh2wav_adjoint(bogus, buf, ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), None),
+                 lambda: abi.wh2wav_workspace_size(bogus),
+                 lambda: abi.wh2wav_stage_count(bogus, 0),
+                 lambda: abi.wh2wav_destroy(bogus),
+                 lambda: abi.wh2wav_batch_workspace_size(bogus),
+                 lambda: abi.wh2wav_batch_schedule(bogus),
+                 lambda: abi.wh2wav_destroy_batch(bogus)):
+        with pytest.raises(abi.Wh2WavError) as e:
+            call()
+        assert e.value.code == abi.WH2WAV_EINVAL
+        assert "live" in abi.wh2wav_last_error()
+    # NULL handles are a no-op for the destroy calls
+    assert abi.LIB.wh2wav_destroy(None) == abi.WH2WAV_OK
+    assert abi.LIB.wh2wav_destroy_batch(None) == abi.WH2WAV_OK
+
+
+def test_sizes_beyond_the_supported_range_are_rejected():
+    for dim, j, q in ((2, 14, 2), (1, 26, 3)):
+        d, _ = desc(2, j, q, dim=dim)
+        with pytest.raises(abi.Wh2WavError) as e:
+            abi.wh2wav_host_table(d, "h")
+        assert e.value.code == abi.WH2WAV_EUNSUPPORTED
+
+
+def test_null_arguments_are_rejected():
+    assert abi.LIB.wh2wav_plan(None, None) == abi.WH2WAV_EINVAL
+    handle = ctypes.c_void_p()
+    assert abi.LIB.wh2wav_plan(None, ctypes.byref(handle)) == abi.WH2WAV_EINVAL
+    assert handle.value is None
+    d, _ = desc(2, 4, 1)
+    assert abi.LIB.wh2wav_host_table(ctypes.byref(d), 0, None, 0, None) == abi.WH2WAV_EINVAL
+    assert abi.LIB.wh2wav_plan_batch(None, 0, ctypes.byref(handle)) == abi.WH2WAV_EINVAL

@@ -292,3 +292,22 @@ def test_parity_2d_large_coarse_level(nu, j, q, j0, dtype):
     y, xa = gpu_pair(2, nu, j, q, j0, dtype, X, omega, yv)
     assert rel(y, op.forward_2d_full(blocks, X, omega)) < TOL[dtype]
     assert rel(xa, op.adjoint_2d_full(blocks, yv, omega)) < TOL[dtype]
+
+
+def test_destroyed_plans_are_rejected():
+    """Use after destroy and a second destroy fail with EINVAL instead of touching freed memory."""
+    from paper_2106_00554_amd import _abi
+    d = _abi.wh2wav_desc(dim=2, j=5, q=1, j0=3, nu=4, family=0, boundary=0, dtype=1, m=64 * 64, omega=None)
+    plan = _abi.wh2wav_plan(d)
+    nbytes = _abi.wh2wav_workspace_size(plan)
+    x = torch.randn(32 * 32, dtype=torch.float64, device="cuda")
+    y = torch.empty(64 * 64, dtype=torch.float64, device="cuda")
+    ws = torch.empty(nbytes // 8 + 1, dtype=torch.float64, device="cuda")
+    _abi.wh2wav_forward(plan, x.data_ptr(), y.data_ptr(), ws.data_ptr(), None)
+    torch.cuda.synchronize()
+    _abi.wh2wav_destroy(plan)
+    for call in (lambda: _abi.wh2wav_forward(plan, x.data_ptr(), y.data_ptr(), ws.data_ptr(), None),
+                 lambda: _abi.wh2wav_workspace_size(plan), lambda: _abi.wh2wav_destroy(plan)):
+        with pytest.raises(_abi.Wh2WavError) as e:
+            call()
+        assert e.value.code == _abi.WH2WAV_EINVAL

@@ -212,3 +212,16 @@ def test_sampled_2d_entries_equal_full_products(nu, j, q):
            (3, 1), (M // 2 + 1, 5)]
     got = op.adjoint_entries_2d(cfg, yv, omega, pos)
     np.testing.assert_allclose(got, [xa[a, b] for a, b in pos], rtol=0, atol=1e-13)
+
+
+def test_row_restricted_products_sum_to_full():
+    """forward_2d_rows / adjoint_2d_rows restrict the full products to row sets."""
+    cfg = op.Config(4, 5, 1)
+    blocks = op.Blocks2D(cfg)
+    X = inputs.coefficients_2d(5, cfg.j0, 81)
+    Y = inputs.sample_vector(cfg.N * cfg.N, 82).reshape(cfg.N, cfg.N)
+    alpha = op.forward_2d_full(blocks, X)
+    rows_a, rows_b = np.arange(0, 23), np.arange(23, cfg.N)
+    np.testing.assert_allclose(op.forward_2d_rows(blocks, X, rows_a), alpha[rows_a], rtol=0, atol=1e-14)
+    xa = op.adjoint_2d_rows(blocks, Y[rows_a], rows_a) + op.adjoint_2d_rows(blocks, Y[rows_b], rows_b)
+    np.testing.assert_allclose(xa, op.adjoint_2d_full(blocks, Y.ravel()), rtol=0, atol=1e-13)
