@@ -113,6 +113,20 @@ int wh2wav_stage_count(wh2wav_plan_t plan, int direction, int* count);
 int wh2wav_forward_stage(wh2wav_plan_t plan, int stage, const void* x, void* y, void* ws, void* stream);
 int wh2wav_adjoint_stage(wh2wav_plan_t plan, int stage, const void* y, void* x, void* ws, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): exactly
+ * wh2wav_forward, but the workspace is a fixed array of
+ * WH2WAV_NOALLOC_MAX_WORKSPACE bytes inside the library, one per GPU, held
+ * until the process ends; the call allocates nothing.  The caller still
+ * passes x and y (device pointers, as for wh2wav_forward).  The plan's device
+ * must be current.  Plans whose wh2wav_workspace_size exceeds the array are
+ * refused with WH2WAV_EUNSUPPORTED.  Every call on one GPU uses the same
+ * array, so calls that overlap in time on one GPU (on different streams or
+ * from different host threads) race: the caller must order them, for example
+ * on one stream. */
+#define WH2WAV_NOALLOC_MAX_WORKSPACE (32u << 20)
+int wh2wav_forward_noalloc(wh2wav_plan_t plan, const void* x, void* y, void* stream);
+
 /* Release the plan and its device memory.  NULL is accepted. */
 int wh2wav_destroy(wh2wav_plan_t plan);
 

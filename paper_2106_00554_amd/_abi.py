@@ -31,7 +31,10 @@ EXPORTS = ("wh2wav_plan", "wh2wav_workspace_size", "wh2wav_forward", "wh2wav_adj
            "wh2wav_destroy", "wh2wav_last_error", "wh2wav_host_table",
            "wh2wav_plan_batch", "wh2wav_batch_workspace_size", "wh2wav_forward_batch",
            "wh2wav_adjoint_batch", "wh2wav_batch_schedule", "wh2wav_batch_set_schedule",
-           "wh2wav_batch_tune", "wh2wav_destroy_batch")
+           "wh2wav_batch_tune", "wh2wav_destroy_batch", "wh2wav_forward_noalloc")
+
+# size of the library's fixed workspace array used by wh2wav_forward_noalloc
+WH2WAV_NOALLOC_MAX_WORKSPACE = 32 << 20
 
 
 class wh2wav_desc(ctypes.Structure):
@@ -91,6 +94,7 @@ def _load():
     lib.wh2wav_batch_set_schedule.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     lib.wh2wav_batch_tune.argtypes = [vp, pp, pp, pp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]
     lib.wh2wav_destroy_batch.argtypes = [vp]
+    lib.wh2wav_forward_noalloc.argtypes = [vp, vp, vp, vp]
     for name in EXPORTS:
         if name != "wh2wav_last_error":
             getattr(lib, name).restype = ctypes.c_int
@@ -120,6 +124,10 @@ def wh2wav_workspace_size(plan):
 
 def wh2wav_forward(plan, x_ptr, y_ptr, ws_ptr, stream_ptr):
     return _check(LIB.wh2wav_forward(plan, x_ptr, y_ptr, ws_ptr, stream_ptr))
+
+
+def wh2wav_forward_noalloc(plan, x_ptr, y_ptr, stream_ptr):
+    return _check(LIB.wh2wav_forward_noalloc(plan, x_ptr, y_ptr, stream_ptr))
 
 
 def wh2wav_adjoint(plan, y_ptr, x_ptr, ws_ptr, stream_ptr):

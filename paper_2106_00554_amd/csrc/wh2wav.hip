@@ -407,6 +407,7 @@ struct wh2wav_plan_s {
   int64_t* d_seg_ptr = nullptr;
   int32_t* d_pos32 = nullptr;
   size_t off_h = 0, off_g = 0, off_T = 0, off_BL = 0, off_BR = 0, off_SL = 0, off_SR = 0;
+  int device = 0;             // the device current when the plan was made
 };
 
 namespace {
@@ -736,6 +737,7 @@ int plan_body(const wh2wav_desc* desc, wh2wav_plan_t* out) {
   std::string err;
   int rc = wh2wav::build_host_plan(desc, &p->host, &err);
   if (rc != WH2WAV_OK) return fail(rc, err);
+  HIP_OK(hipGetDevice(&p->device));
   const auto& H = p->host;
   if (H.j < 1) return fail(WH2WAV_EUNSUPPORTED, "j must be >= 1");
   const size_t elem = H.dtype == WH2WAV_F64 ? 8 : 4;
@@ -882,6 +884,63 @@ int wh2wav_destroy(wh2wav_plan_t p) {
   if (!wh2wav::handle_remove(p)) return fail(WH2WAV_EINVAL, "not a live plan (destroyed twice, or never created)");
   release(p);
   return WH2WAV_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ entry point without allocation
+// The workspace of wh2wav_forward_noalloc: a fixed array in the library's
+// device code object, one copy per GPU (held until the process ends).  In host
+// code `scratch` names a host-side stand-in, never the device memory: kernels
+// get the address that hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = size_t(WH2WAV_NOALLOC_MAX_WORKSPACE);
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(WH2WAV_EUNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(WH2WAV_EHIP, "hipGetSymbolAddress returned NULL for the scratch array");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return WH2WAV_OK;
+}
+
+int forward_noalloc_body(wh2wav_plan_t p, const void* x, void* y, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(WH2WAV_EINVAL, "plan is NULL");
+  if (!wh2wav::handle_live(p)) return fail(WH2WAV_EINVAL, "not a live plan (destroyed, or never created)");
+  size_t need = 0;
+  int rc = wh2wav_workspace_size(p, &need);
+  if (rc) return rc;
+  if (need > kScratchBytes)
+    return fail(WH2WAV_EUNSUPPORTED, "workspace of " + std::to_string(need) + " bytes exceeds the " +
+                                         std::to_string(kScratchBytes) + "-byte array of the no-allocation call");
+  int dev = -1;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev != p->device) return fail(WH2WAV_EINVAL, "the plan's device must be current");
+  void* ws = nullptr;
+  rc = scratch_address(dev, &ws);
+  if (rc) return rc;
+  return forward_any(p, x, y, ws, stream, -1);
+}
+
+}  // namespace
+
+extern "C" {
+
+int wh2wav_forward_noalloc(wh2wav_plan_t p, const void* x, void* y, void* stream) {
+  return wh2wav::guarded([&] { return forward_noalloc_body(p, x, y, stream); });
 }
 
 static int host_table_body(const wh2wav_desc* desc, int which, double* out, size_t capacity, size_t* count) {
