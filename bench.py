@@ -29,13 +29,17 @@ FP32 against FP64 (also for the small configurations).
 More legs are reported in the same JSON line (skip with --no-extras):
 * "autograd": the 1024^2 db4 q=1 FP32 operator (25 % Omega) through the
   torch.autograd.Function (gradient of 0.5 ||P A x - y||^2 by backward), the
-  plain pair on the same operator, and 200 FISTA iterations;
+  plain pair on the same operator, the same gradient captured once as a HIP
+  graph and replayed, and 200 FISTA iterations, eager and graph-replayed;
 * "round_robin": the default workload on four independent operators in turn
   (about 600 MB live, beyond the 256 MB MALL), pairs/s and the row passes'
   per-launch time and HBM rate;
+* "variants": symlets, the periodic extension and the tensor-product basis on
+  the roofline workload's shape, and two shapes of the generic line kernels;
 * "batched": 96 uneven instances (1D 2^12..2^16, 2D 128^2..512^2 and 1024^2,
   db2/db4/db8, q = 1, 2, 10-30 % Omega, FP32) as one graph launch per
-  direction after the schedule autotuner, against per-instance plain calls.
+  direction (eight branches, largest instances first), against per-instance
+  plain calls.
 """
 import argparse
 import hashlib
@@ -265,6 +269,9 @@ def autograd_leg(torch, steps):
         grad()
     t_plain = timed(plain, steps, torch)
     t_grad = timed(grad, steps, torch)
+    gg = ag.GraphedGradient(opr, y)
+    xg = x.detach()
+    t_ggrad = timed(lambda: gg(xg), steps, torch)
     lam = 0.01 * float(opr.adjoint(y).abs().max())
     ag.fista(opr, y, lam, 3)  # warm-up
     torch.cuda.synchronize()
@@ -273,10 +280,19 @@ def autograd_leg(torch, steps):
     xr = ag.fista(opr, y, lam, iters)
     torch.cuda.synchronize()
     t_fista = time.perf_counter() - t0
+    ag.fista_graphed(opr, y, lam, 3)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xg_r = ag.fista_graphed(opr, y, lam, iters)
+    torch.cuda.synchronize()
+    t_fista_g = time.perf_counter() - t0
     err = float((xr - xt).norm() / xt.norm())
     return {"workload": name, "plain_pairs_per_s": 1.0 / t_plain, "autograd_grads_per_s": 1.0 / t_grad,
-            "fista_iters": iters, "fista_iters_per_s": iters / t_fista, "fista_lambda": lam,
-            "fista_rel_error_vs_x_true": err}
+            "graphed_grads_per_s": 1.0 / t_ggrad,
+            "fista_iters": iters, "fista_iters_per_s": iters / t_fista,
+            "fista_graphed_iters_per_s": iters / t_fista_g, "fista_lambda": lam,
+            "fista_rel_error_vs_x_true": err,
+            "fista_graphed_vs_eager": float((xg_r - xr).norm() / xr.norm())}
 
 
 def small_configs_leg(torch, steps, outputs=None):
@@ -319,6 +335,45 @@ def small_configs_leg(torch, steps, outputs=None):
             xb = opr.adjoint(torch.tensor(yv, dtype=dtype, device="cuda"))
             outputs[key] = {"workload": name, "x": X, "omega": omega, "yv": yv,
                             "y": ya.cpu().numpy(), "xa": xb.cpu().numpy()}
+    return out
+
+
+def variants_leg(torch, steps):
+    """Pairs/s of the widened operators on the roofline workload's shape and of
+    shapes served by the generic kernels: symlets, the periodic extension and
+    the tensor-product basis at 2048^2 db8 q = 2 (12.5 % Omega), and the
+    generic line kernels at 1024^2 db10 q = 1 and 4096^2 db4 q = 1 (10 % Omega);
+    all FP32."""
+    from paper_2106_00554_amd.operator import Wh2Wav
+    from tests import inputs
+
+    name = "2d_db8_j11_q2_12.5pct"
+    w = inputs.WORKLOADS[name]
+    X, omega = inputs.workload_inputs(name)
+    cases = [("sym8", dict(nu=8, j=11, q=2, j0=4, family="sym"), X, omega),
+             ("db8_periodic", dict(nu=8, j=11, q=2, j0=4, boundary="per"), X, omega),
+             ("db8_tensor", dict(nu=8, j=11, q=2, j0=4, basis2d="tensor"), X, omega)]
+    for nu, j, q, j0, dens in ((10, 10, 1, 5, 0.1), (4, 12, 1, 3, 0.1)):
+        N = 1 << (j + q)
+        cases.append((f"db{nu}_{1 << j}sq_generic", dict(nu=nu, j=j, q=q, j0=j0),
+                      inputs.coefficients_2d(j, j0, 700 + j), inputs.multilevel_omega_2d(N, dens, 701 + j)))
+    out = {}
+    for label, kw, Xc, om in cases:
+        opr = Wh2Wav(2, kw.pop("j"), kw.pop("q"), kw.pop("nu"), kw.pop("j0"), torch.float32, om, **kw)
+        x = torch.tensor(Xc, dtype=torch.float32, device="cuda")
+        y = torch.empty(opr.m, dtype=torch.float32, device="cuda")
+        xa = torch.empty_like(x)
+
+        def pair():
+            opr.forward(x, out=y)
+            opr.adjoint(y, out=xa)
+
+        for _ in range(3):
+            pair()
+        t = timed(pair, max(5, steps // 2), torch)
+        out[label] = {"M": opr.M, "q": opr.q, "m": opr.m, "us_per_pair": t * 1e6, "pairs_per_s": 1.0 / t}
+        del opr, x, y, xa
+        torch.cuda.empty_cache()
     return out
 
 
@@ -399,7 +454,10 @@ def batched_leg(torch, steps):
     xs = [torch.tensor(x, dtype=torch.float32, device="cuda") for _, x in full]
     ys = batch.new_outputs(0)
     xa = batch.new_outputs(1)
-    best_ms = batch.tune(xs, ys, xa, reps=2)
+    # fixed schedule: the autotuner (wh2wav_batch_tune) is kept off the GPU
+    # until a host crash seen in one run of it is explained
+    batch.set_schedule(8, 1)
+    best_ms = None
     sched = batch.schedule()
 
     def batched():
@@ -431,7 +489,7 @@ def main():
     ap.add_argument("--dtype", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--only", choices=["batched", "autograd", "small", "round_robin"], default=None,
+    ap.add_argument("--only", choices=["batched", "autograd", "small", "round_robin", "variants"], default=None,
                     help="run one extra leg alone (for profiling) and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy MIB MiB device-to-device once before the run (a kernel of known traffic "
@@ -449,7 +507,7 @@ def main():
 
     if args.only:
         leg = {"batched": batched_leg, "autograd": autograd_leg, "small": small_configs_leg,
-               "round_robin": round_robin_leg}[args.only]
+               "round_robin": round_robin_leg, "variants": variants_leg}[args.only]
         print(json.dumps({args.only: leg(torch, max(3, args.steps // 5))}), flush=True)
         return
 
@@ -580,6 +638,7 @@ def main():
         out["batched"] = batched_leg(torch, max(3, args.steps // 5))
         out["small_configs"] = small_configs_leg(torch, args.steps, small_out)
         out["round_robin"] = round_robin_leg(torch, max(3, args.steps // 5))
+        out["variants"] = variants_leg(torch, args.steps)
     if check:
         out["cpu_baseline"], out["oracle_check"] = cpu_oracle_leg(name, X, omega, yv, check, small_out or {})
     print(json.dumps(out), flush=True)

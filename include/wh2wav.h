@@ -28,7 +28,9 @@
  *       layout: the scaling block at [0, 2^{J0})^2 and, for each level
  *       k = J0..j-1, the bands [0,2^k) x [2^k,2^{k+1}) (phi (x) psi),
  *       [2^k,2^{k+1}) x [0,2^k) (psi (x) phi), [2^k,2^{k+1})^2 (psi (x) psi);
- *       the first array index belongs to the first coordinate.
+ *       the first array index belongs to the first coordinate.  With
+ *       basis2d = WH2WAV_TENSOR, x[c1][c2] is the coefficient of
+ *       r_{c1} (x) r_{c2}, c1 and c2 in 1D C_{psi,j} order.
  *   y   m = |Omega| values in increasing order of the sequency index n
  *       (1D) or of n1 * N + n2 (2D), n1 the first coordinate.
  *   Element type is float or double as chosen by the plan (dtype).
@@ -68,8 +70,23 @@ enum {
 };
 
 enum { WH2WAV_F32 = 0, WH2WAV_F64 = 1 };
-enum { WH2WAV_DB = 0 };               /* Daubechies, minimum phase (Sec. 3.2) */
-enum { WH2WAV_BD = 0 };               /* vanishing-moment-preserving edges */
+enum {
+  WH2WAV_DB = 0,                      /* Daubechies, minimum phase (Sec. 3.2) */
+  WH2WAV_SYM = 1                      /* symlets: least-asymmetric spectral factor (Sec. 3.2, Table 1);
+                                         the root choice of least phase deviation from linear */
+};
+enum {
+  WH2WAV_BD = 0,                      /* vanishing-moment-preserving boundary functions (Sec. 3.2) */
+  WH2WAV_PER = 1                      /* periodic extension (Sec. 3.2, Prop. 4.2 "per"): each
+                                         function crossing an end is periodised with period 1 */
+};
+
+/* 2D wavelet basis.  ISOTROPIC: at each level the scaling block splits into
+ * phi (x) psi, psi (x) phi, psi (x) psi (the quadtree layout below).  TENSOR:
+ * the products r_{c1} (x) r_{c2} of the 1D basis C_{psi,j}, x[c1][c2] in 1D
+ * order along each index; by Fubini (Sec. 5) its section is the Kronecker
+ * product of the 1D section with itself. */
+enum { WH2WAV_ISOTROPIC = 0, WH2WAV_TENSOR = 1 };
 
 typedef struct wh2wav_plan_s* wh2wav_plan_t;
 
@@ -79,12 +96,13 @@ typedef struct {
   int q;                /* N = 2^{j+q} per dimension, q >= 1 (Sec. 4: q > 0) */
   int j0;               /* coarsest level J0: 2^{J0} >= 2 nu for nu >= 2 (Sec. 3.2) */
   int nu;               /* vanishing moments, 1 (Haar) .. 10 */
-  int family;           /* WH2WAV_DB */
-  int boundary;         /* WH2WAV_BD */
+  int family;           /* WH2WAV_DB or WH2WAV_SYM */
+  int boundary;         /* WH2WAV_BD or WH2WAV_PER */
   int dtype;            /* WH2WAV_F32 or WH2WAV_F64 */
   int64_t m;            /* |Omega|; with omega == NULL, m must equal N^dim (all samples) */
   const int64_t* omega; /* host array of m strictly increasing linear indices in
                            [0, N^dim), or NULL; copied during wh2wav_plan */
+  int basis2d;          /* 2D only: WH2WAV_ISOTROPIC (0) or WH2WAV_TENSOR (1) */
 } wh2wav_desc;
 
 /* Build a plan: host-side tables (Sec. 3.2, Sec. 4.1, Prop. 4.2) and their

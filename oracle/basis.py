@@ -18,8 +18,13 @@ phi (Phi_r) and psi (Psi_r):
   boundary functions:  the same for each translate in their coefficient
                        vectors, keeping only cells inside [0, 1).
 
+Periodic extension (per=True in block / multiscale): every function of
+level k is periodised with period 1 (Sec. 3.2), no boundary functions.
+
 Parity status: pinned by polynomial reproduction, orthonormality against
-point-value quadrature, zero mean of wavelets and the Haar closed form.
+point-value quadrature, zero mean of wavelets and the Haar closed form; the
+periodic basis by orthonormality against quadrature, the partition of unity,
+the Haar case and the periodic formulas of Prop. 4.2.
 """
 import functools
 
@@ -59,7 +64,7 @@ def mp_str(a):
     return mp.nstr(a, 40) if isinstance(a, mp.mpf) else repr(float(a))
 
 
-@functools.lru_cache(maxsize=None)
+@functools.lru_cache(maxsize=None, typed=True)
 def _edge_float(nu):
     return (halfline.edge_scaling(nu, "left"), halfline.edge_scaling(nu, "right"),
             halfline.edge_wavelets(nu, "left"), halfline.edge_wavelets(nu, "right"))
@@ -87,6 +92,25 @@ def wavelet_cells(nu, k, m, J):
     return _translate_cells(nu, k, m, J, scaling=False)
 
 
+def periodic_cells(nu, k, m, J, scaling=True):
+    """Cell integrals of the periodic-extension function phi^per_{k,m} (psi^per_{k,m}).
+
+    Sec. 3.2 (periodic extension): a function crossing an end of [0, 1] is the
+    sum of its restriction and that of the translate by +-2^k positions, i.e.
+    sum_t f_{k, m + t 2^k} restricted to [0, 1] (for 2^k >= 2 nu only t = -1, 0,
+    1 can meet [0, 1]).  Its cell integrals at resolution 2^-J are those of
+    f_{k,m} with the cell index taken modulo 2^J.
+    """
+    r = J - k
+    tab = cascade.phi_cells(nu, r) if scaling else cascade.psi_cells(nu, r)
+    s = np.arange(tab.lo, tab.lo + tab.values.size)
+    i = np.mod(s + m * (1 << r), 1 << J)
+    out = np.zeros(1 << J)
+    np.add.at(out, i, tab.values * 2.0 ** (-k / 2.0))
+    nz = np.nonzero(out)[0]
+    return nz, out[nz]
+
+
 def check_level(nu, k, j0=None):
     if nu < 1:
         raise ValueError("nu must be >= 1")
@@ -96,12 +120,16 @@ def check_level(nu, k, j0=None):
         raise ValueError("level too coarse for the boundary construction: need 2^k >= 2 nu")
 
 
-def block(nu, k, J, scaling):
-    """Sparse (2^J x 2^k) matrix of cell integrals of B_{phi,k} or B_{psi,k}."""
+def block(nu, k, J, scaling, per=False):
+    """Sparse (2^J x 2^k) matrix of cell integrals of B_{phi,k} or B_{psi,k}
+    (boundary-corrected, or with per=True the periodic extension)."""
     check_level(nu, k)
     rows, cols, vals = [], [], []
     for m in range(1 << k):
-        i, v = (scaling_function_cells if scaling else wavelet_cells)(nu, k, m, J)
+        if per:
+            i, v = periodic_cells(nu, k, m, J, scaling)
+        else:
+            i, v = (scaling_function_cells if scaling else wavelet_cells)(nu, k, m, J)
         rows.append(i)
         cols.append(np.full(i.size, m))
         vals.append(v)
@@ -109,11 +137,11 @@ def block(nu, k, J, scaling):
                          shape=(1 << J, 1 << k))
 
 
-def multiscale(nu, j, j0, J):
+def multiscale(nu, j, j0, J, per=False):
     """Sparse (2^J x 2^j) cell-integral matrix of C_{psi,j} in the paper's order."""
-    parts = [block(nu, j0, J, True)]
+    parts = [block(nu, j0, J, True, per)]
     for k in range(j0, j):
-        parts.append(block(nu, k, J, False))
+        parts.append(block(nu, k, J, False, per))
     return sp.hstack(parts).tocsc()
 
 
@@ -146,6 +174,21 @@ def _combo_points(nu, level, coef, offset, R):
     out = np.zeros((1 << R) + 1)
     for t, a in coef.items():
         out += float(a) * _translate_points(nu, level, offset + t, R)
+    return out
+
+
+def periodic_points(nu, k, m, R, scaling=True):
+    """Point values of phi^per_{k,m} (psi^per_{k,m}) at x = i 2^-R, i = 0 .. 2^R: the sum of the
+    translates f_{k, m + t 2^k}, t = -1, 0, 1 (point-value cascade)."""
+    out = np.zeros((1 << R) + 1)
+    for t in (-1, 0, 1):
+        if scaling:
+            out += _translate_points(nu, k, m + t * (1 << k), R)
+        else:
+            from . import filters
+            g = filters.wavelet(nu)
+            coef = {2 * (m + t * (1 << k)) + c: g[ci] for ci, c in enumerate(range(-nu + 1, nu + 1))}
+            out += _combo_points(nu, k + 1, coef, 0, R)
     return out
 
 

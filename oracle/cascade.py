@@ -78,7 +78,7 @@ def _phi0(h, nu):
     vec = np.real(v[:, i]).astype(np.longdouble)
     vec /= vec.sum()
     # polish in extended precision: the other eigenvalues are at most 1/2 in modulus
-    h_ld = _taps_ld(filters.daubechies_mp(nu))
+    h_ld = _taps_ld(filters.scaling_mp(nu))
     Tld = np.zeros((n, n), dtype=np.longdouble)
     for a, s in enumerate(cells):
         for ci, c in enumerate(range(-nu + 1, nu + 1)):
@@ -96,12 +96,12 @@ def _taps_ld(taps_mp):
     return [np.longdouble(mp.nstr(t, 40)) for t in taps_mp]
 
 
-@functools.lru_cache(maxsize=None)
+@functools.lru_cache(maxsize=None, typed=True)
 def phi_cells(nu, r):
     """Phi_r for the Daubechies scaling function with nu vanishing moments."""
     if r == 0:
         return CellIntegrals(0, -nu + 1, _phi0(filters.daubechies(nu), nu))
-    h = _taps_ld(filters.daubechies_mp(nu))
+    h = _taps_ld(filters.scaling_mp(nu))
     prev = phi_cells(nu, r - 1)
     lo, hi = (-nu + 1) << r, nu << r
     s = np.arange(lo, hi)
@@ -111,7 +111,7 @@ def phi_cells(nu, r):
     return CellIntegrals(r, lo, out / np.sqrt(np.longdouble(2)))
 
 
-@functools.lru_cache(maxsize=None)
+@functools.lru_cache(maxsize=None, typed=True)
 def psi_cells(nu, r):
     """Psi_r, cell integrals of the wavelet psi at resolution 2^-r."""
     if r == 0:
@@ -128,7 +128,7 @@ def psi_cells(nu, r):
     return CellIntegrals(r, lo, out / np.sqrt(np.longdouble(2)))
 
 
-@functools.lru_cache(maxsize=None)
+@functools.lru_cache(maxsize=None, typed=True)
 def phi_points(nu, r):
     """phi(k 2^-r) for k in [(-nu+1) 2^r, nu 2^r], point-value cascade."""
     h = filters.daubechies(nu)

@@ -57,11 +57,11 @@ from . import filters
 DPS = 60
 
 
-@functools.lru_cache(maxsize=None)
+@functools.lru_cache(maxsize=None, typed=True)
 def gram_left(nu):
     """Return a function G(k, k') (mpf) of the left half-line Gram matrix."""
     with mp.workdps(DPS):
-        h = filters.daubechies_mp(nu)
+        h = filters.scaling_mp(nu)
         taps = list(range(-nu + 1, nu + 1))
 
         def known(a, b):
@@ -141,7 +141,7 @@ def _scale(alpha, x):
     return {k: alpha * v for k, v in x.items()}
 
 
-@functools.lru_cache(maxsize=None)
+@functools.lru_cache(maxsize=None, typed=True)
 def edge_scaling(nu, side):
     """Boundary scaling functions as tuples of {level-0 translate: coef}.
 
@@ -191,7 +191,7 @@ def _level0_to_level1(coef0, nu, side, taps):
     return out
 
 
-@functools.lru_cache(maxsize=None)
+@functools.lru_cache(maxsize=None, typed=True)
 def edge_wavelets(nu, side):
     """Boundary wavelets as tuples of {level-1 translate: coef}.
 
@@ -199,7 +199,7 @@ def edge_wavelets(nu, side):
     """
     G = gram_left(nu)
     with mp.workdps(DPS):
-        h = filters.daubechies_mp(nu)
+        h = filters.scaling_mp(nu)
         g = filters.wavelet_mp(nu)
         scal = edge_scaling(nu, side)
         sgn = 1 if side == "left" else -1

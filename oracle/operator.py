@@ -19,8 +19,14 @@ entries, so alpha = sum over (level, band) of A_a X_band A_b^T with the 1D
 blocks A_a, A_b of B_{phi,k} / B_{psi,k}; y = alpha[Omega] in increasing
 linear index n1 N + n2, n1 belonging to the first coordinate.
 
+Tensor-product 2D basis (the alternative to the isotropic one): the
+functions r_{c1} (x) r_{c2} of the 1D multiscale basis, so the section is the
+Kronecker product of the 1D section with itself (forward_2d_tensor).
+
 Parity status: pinned (Haar closed form, norm bound, polynomial
-reproduction, Fubini against the dense Kronecker matrix, Table 1 for DB2).
+reproduction, Fubini against the dense Kronecker matrix, Table 1 for DB2;
+the tensor basis against the Kronecker product of 1D basis columns and by
+the singular values it shares with the isotropic basis of the same space).
 """
 import numpy as np
 import scipy.sparse as sp
@@ -50,27 +56,29 @@ def walsh_cols(J, C):
 
 
 class Config:
-    """Sizes of one operator: M = 2^j per dimension, N = 2^(j+q), coarse level j0."""
+    """Sizes of one operator: M = 2^j per dimension, N = 2^(j+q), coarse level j0;
+    per=True selects the periodic extension instead of the boundary functions;
+    tensor=True the tensor-product 2D basis instead of the isotropic one."""
 
-    def __init__(self, nu, j, q, j0=None):
+    def __init__(self, nu, j, q, j0=None, per=False, tensor=False):
         if j0 is None:
             j0 = max(0, int(np.ceil(np.log2(2 * nu)))) if nu >= 2 else 0
         if q < 1 or j < j0 or (1 << j0) < 2 * nu and nu >= 2:
             raise ValueError("invalid (nu, j, q, j0)")
-        self.nu, self.j, self.q, self.j0 = nu, j, q, j0
+        self.nu, self.j, self.q, self.j0, self.per, self.tensor = nu, j, q, j0, per, tensor
         self.J = j + q
         self.M, self.N = 1 << j, 1 << (j + q)
 
 
 def matrix_1d(cfg):
     """Dense N x M matrix A of the wavelet basis C_{psi,j}."""
-    C = basis.multiscale(cfg.nu, cfg.j, cfg.j0, cfg.J)
+    C = basis.multiscale(cfg.nu, cfg.j, cfg.j0, cfg.J, cfg.per)
     return walsh_cols(cfg.J, C)
 
 
 def scaling_matrix_1d(cfg):
     """Dense N x M matrix of the scaling basis B_{phi,j} (P_N U P_M of Sec. 4)."""
-    C = basis.block(cfg.nu, cfg.j, cfg.J, True)
+    C = basis.block(cfg.nu, cfg.j, cfg.J, True, cfg.per)
     return walsh_cols(cfg.J, C)
 
 
@@ -99,7 +107,7 @@ class Blocks2D:
         for k in range(cfg.j0, cfg.j):
             keys += [("phi", k)] if k != cfg.j0 else []
             keys += [("psi", k)]
-        parts = [basis.block(nu, k, J, kind == "phi") for kind, k in keys]
+        parts = [basis.block(nu, k, J, kind == "phi", cfg.per) for kind, k in keys]
         allcols = walsh_rows(J, rows, sp.hstack(parts).tocsc())
         self.phi, self.psi = {}, {}
         c = 0
@@ -173,6 +181,29 @@ def adjoint_2d_rows(blocks, Y_rows, rows):
     return X
 
 
+# ---------------------------------------------------------------------------
+# Tensor-product 2D basis: the functions r_{c1} (x) r_{c2}, r the 1D multiscale
+# basis C_{psi,j}, x[c1, c2] their coefficients.  By Fubini (Sec. 5) the
+# section is the Kronecker product of the 1D section with itself.
+
+def forward_2d_tensor(A1, X, omega=None):
+    """alpha = A1 X A1^T (A1 the dense N x M 1D section), gathered on omega."""
+    alpha = A1 @ np.asarray(X) @ A1.T
+    return alpha if omega is None else alpha.ravel()[np.asarray(omega)]
+
+
+def adjoint_2d_tensor(A1, y, omega=None):
+    """X = A1^T Y A1 with Y the N x N array holding y on omega (zero elsewhere)."""
+    N = A1.shape[0]
+    if omega is None:
+        Y = np.asarray(y).reshape(N, N)
+    else:
+        Y = np.zeros(N * N)
+        Y[np.asarray(omega)] = y
+        Y = Y.reshape(N, N)
+    return A1.T @ Y @ A1
+
+
 def quadtree_functions(cfg, c1, c2):
     """For quadtree position (c1, c2): ((kind1, level1, idx1), (kind2, level2, idx2))."""
     j0 = cfg.j0
@@ -194,8 +225,11 @@ def dense_2d(cfg):
     def col(kind, level, idx):
         key = (kind, level, idx)
         if key not in cols:
-            f = basis.scaling_function_cells if kind == "phi" else basis.wavelet_cells
-            i, v = f(nu, level, idx, J)
+            if cfg.per:
+                i, v = basis.periodic_cells(nu, level, idx, J, kind == "phi")
+            else:
+                f = basis.scaling_function_cells if kind == "phi" else basis.wavelet_cells
+                i, v = f(nu, level, idx, J)
             c = np.zeros(cfg.N)
             c[i] = v
             cols[key] = walsh.walsh_matrix(J) @ c
@@ -204,7 +238,11 @@ def dense_2d(cfg):
     A2 = np.zeros((cfg.N * cfg.N, cfg.M * cfg.M))
     for c1 in range(cfg.M):
         for c2 in range(cfg.M):
-            f1, f2 = quadtree_functions(cfg, c1, c2)
+            if cfg.tensor:
+                f1, f2 = basis.position_1d(c1, cfg.j0), basis.position_1d(c2, cfg.j0)
+                f1, f2 = (f1[1], f1[0], f1[2]), (f2[1], f2[0], f2[2])
+            else:
+                f1, f2 = quadtree_functions(cfg, c1, c2)
             A2[:, c1 * cfg.M + c2] = np.kron(col(*f1), col(*f2))
     return A2
 
@@ -228,8 +266,11 @@ def forward_entries_2d(cfg, X, n1s, n2s):
 
 def walsh_column(cfg, kind, level, idx):
     """Column <f, w_n>, n < N, of one 1D basis function (kind 'phi' or 'psi')."""
-    f = basis.scaling_function_cells if kind == "phi" else basis.wavelet_cells
-    cells, vals = f(cfg.nu, level, idx, cfg.J)
+    if cfg.per:
+        cells, vals = basis.periodic_cells(cfg.nu, level, idx, cfg.J, kind == "phi")
+    else:
+        f = basis.scaling_function_cells if kind == "phi" else basis.wavelet_cells
+        cells, vals = f(cfg.nu, level, idx, cfg.J)
     out = np.zeros(cfg.N)
     step = 1024
     for a in range(0, cfg.N, step):
@@ -254,7 +295,7 @@ def adjoint_entries_2d(cfg, y, omega, positions):
 def forward_entries_1d(cfg, x, ns, C=None):
     """y_n = sum_c A[n, c] x_c for each n in ns, as sum_i w_n(i/N) f[i] with f = C x
     the cell integrals of the function sum_c x_c r_c (plain sums, no fast transform)."""
-    C = basis.multiscale(cfg.nu, cfg.j, cfg.j0, cfg.J) if C is None else C
+    C = basis.multiscale(cfg.nu, cfg.j, cfg.j0, cfg.J, cfg.per) if C is None else C
     f = C @ np.asarray(x, dtype=np.float64)
     ns = np.asarray(ns)
     out = np.empty(ns.size)
@@ -268,7 +309,7 @@ def forward_entries_1d(cfg, x, ns, C=None):
 def adjoint_entries_1d(cfg, y, omega, cs, C=None):
     """(A[omega]^T y)_c for each position c in cs: the column of one basis function
     restricted to omega, against y (plain sums)."""
-    C = basis.multiscale(cfg.nu, cfg.j, cfg.j0, cfg.J) if C is None else C
+    C = basis.multiscale(cfg.nu, cfg.j, cfg.j0, cfg.J, cfg.per) if C is None else C
     omega = np.arange(cfg.N) if omega is None else np.asarray(omega)
     out = []
     for c in cs:

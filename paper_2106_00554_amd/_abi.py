@@ -21,7 +21,11 @@ WH2WAV_EINTERNAL = -5
 WH2WAV_F32 = 0
 WH2WAV_F64 = 1
 WH2WAV_DB = 0
+WH2WAV_SYM = 1
 WH2WAV_BD = 0
+WH2WAV_PER = 1
+WH2WAV_ISOTROPIC = 0
+WH2WAV_TENSOR = 1
 
 TABLES = {"h": 0, "g": 1, "T": 2, "band_l": 3, "band_r": 4, "syn_l": 5, "syn_r": 6, "row_ptr": 7}
 
@@ -49,6 +53,7 @@ class wh2wav_desc(ctypes.Structure):
         ("dtype", ctypes.c_int),
         ("m", ctypes.c_int64),
         ("omega", ctypes.POINTER(ctypes.c_int64)),
+        ("basis2d", ctypes.c_int),
     ]
 
 

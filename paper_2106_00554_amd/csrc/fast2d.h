@@ -18,6 +18,7 @@ struct Tables {
   const T* synL;   // (3nu-1) * 2nu
   const T* synR;   // (3nu-1) * 2nu
   int nu, q, Q;
+  int per;         // periodic extension (Sec. 3.2): no boundary functions, lines wrap around
 };
 
 struct Omega {

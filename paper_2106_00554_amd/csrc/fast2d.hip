@@ -92,6 +92,10 @@ __device__ __forceinline__ void line_forward(const T (&xi)[R], T (&v)[R], int s,
   T x[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) x[r] = xi[r];
+  // Periodic extension: no boundary functions; the lane exchange of the
+  // table product wraps around the line, which is the periodised product.
+  // Otherwise the boundary values are zeroed (the bands below add them).
+  const bool bd = !t.per;
   T eL[NU], eR[NU];
 #pragma unroll
   for (int m = 0; m < NU; ++m) {
@@ -101,46 +105,48 @@ __device__ __forceinline__ void line_forward(const T (&xi)[R], T (&v)[R], int s,
     eR[m] = read_lane(xi[R - 1 - m % R], 63 - m / R);
     // per-element selects (conditional stores would let the compiler merge
     // them into one dynamically indexed store and move x to scratch)
-    x[m % R] = lane == m / R ? T(0) : x[m % R];
-    x[R - 1 - m % R] = lane == 63 - m / R ? T(0) : x[R - 1 - m % R];
+    x[m % R] = bd && lane == m / R ? T(0) : x[m % R];
+    x[R - 1 - m % R] = bd && lane == 63 - m / R ? T(0) : x[R - 1 - m % R];
   }
   T tap[2 * NU - 1];
 #pragma unroll
   for (int li = 0; li < 2 * NU - 1; ++li) tap[li] = t.tabT[li * Q + s];
   table_product<T, R, NU>(x, v, tap, lane);
-  // boundary bands (Prop. 4.2): positions p < B and p >= M - B
-  // lanes 0..B-1: left band row p = lane; lanes B..2B-1: right band row
-  // lane - B.  Loads are unconditional (clamped row) so they overlap.
-  T bv = T(0);
-  {
-    const bool left = lane < B;
-    const int p = left ? lane : (lane < 2 * B ? lane - B : 0);
-    const T* band = left ? t.bandL : t.bandR;
+  if (bd) {
+    // boundary bands (Prop. 4.2): positions p < B and p >= M - B
+    // lanes 0..B-1: left band row p = lane; lanes B..2B-1: right band row
+    // lane - B.  Loads are unconditional (clamped row) so they overlap.
+    T bv = T(0);
+    {
+      const bool left = lane < B;
+      const int p = left ? lane : (lane < 2 * B ? lane - B : 0);
+      const T* band = left ? t.bandL : t.bandR;
 #pragma unroll
-    for (int m = 0; m < NU; ++m) bv = fma(left ? eL[m] : eR[m], band[(p * NU + m) * Q + s], bv);
-    bv = lane < 2 * B ? bv : T(0);
-  }
-  if constexpr (R >= B) {
-    // the bands sit in lanes 0 and 63: masked adds, one instruction each
-    T bl[B], br[B];
-#pragma unroll
-    for (int e = 0; e < B; ++e) bl[e] = read_lane(bv, e), br[e] = read_lane(bv, B + e);
-    if (lane == 0) {
-#pragma unroll
-      for (int e = 0; e < B; ++e) v[e] += bl[e];
+      for (int m = 0; m < NU; ++m) bv = fma(left ? eL[m] : eR[m], band[(p * NU + m) * Q + s], bv);
+      bv = lane < 2 * B ? bv : T(0);
     }
-    if (lane == 63) {
+    if constexpr (R >= B) {
+      // the bands sit in lanes 0 and 63: masked adds, one instruction each
+      T bl[B], br[B];
 #pragma unroll
-      for (int e = 0; e < B; ++e) v[R - B + e] += br[e];
-    }
-  } else {
+      for (int e = 0; e < B; ++e) bl[e] = read_lane(bv, e), br[e] = read_lane(bv, B + e);
+      if (lane == 0) {
 #pragma unroll
-    for (int e = 0; e < B; ++e) {
-      const T a = read_lane(bv, e), b = read_lane(bv, B + e);
-      constexpr int M = 64 * R;
-      const int pr = M - B + e;  // right band position
-      v[e % R] += lane == e / R ? a : T(0);
-      v[pr % R] += lane == pr / R ? b : T(0);
+        for (int e = 0; e < B; ++e) v[e] += bl[e];
+      }
+      if (lane == 63) {
+#pragma unroll
+        for (int e = 0; e < B; ++e) v[R - B + e] += br[e];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < B; ++e) {
+        const T a = read_lane(bv, e), b = read_lane(bv, B + e);
+        constexpr int M = 64 * R;
+        const int pr = M - B + e;  // right band position
+        v[e % R] += lane == e / R ? a : T(0);
+        v[pr % R] += lane == pr / R ? b : T(0);
+      }
     }
   }
   fwht_wave<T, R>(v, lane);
@@ -159,6 +165,7 @@ __device__ __forceinline__ void line_adjoint(T (&v)[R], T (&acc)[R], T& eacc, in
 #pragma unroll
   for (int li = 0; li < 2 * NU - 1; ++li) tap[li] = t.tabT[li * Q + s];
   table_product_t<T, R, NU>(v, acc, tap, lane);
+  if (t.per) return;  // periodic: the wrapped correlation is the whole adjoint
   T rl[B], rr[B];
 #pragma unroll
   for (int e = 0; e < B; ++e) {
@@ -181,9 +188,11 @@ __device__ __forceinline__ void line_adjoint(T (&v)[R], T (&acc)[R], T& eacc, in
   eacc += el;
 }
 
-// Boundary positions of acc take their values from eacc.
+// Boundary positions of acc take their values from eacc (not for the periodic
+// extension, whose wrapped correlation already covers every position).
 template <typename T, int R, int NU>
-__device__ __forceinline__ void place_edges(T (&acc)[R], T eacc, int lane) {
+__device__ __forceinline__ void place_edges(T (&acc)[R], T eacc, int lane, int per) {
+  if (per) return;
 #pragma unroll
   for (int m = 0; m < NU; ++m) {
     const T a = read_lane(eacc, m), b = read_lane(eacc, NU + m);
@@ -358,7 +367,7 @@ __global__ void __launch_bounds__(1024) k_rowpass_adj(const T* __restrict__ y, T
     wave_sync();
     line_adjoint<T, R, NU>(v, acc, eacc, s, t, lane);
   }
-  place_edges<T, R, NU>(acc, eacc, lane);
+  place_edges<T, R, NU>(acc, eacc, lane, t.per);
   // cross-wave sum (waves that had no phase contribute zeros)
   LB::store(buf, lane, acc);
   __syncthreads();
@@ -409,7 +418,8 @@ __global__ void __launch_bounds__(1024) k_colpass_fwd(const T* __restrict__ xiT,
     store_line<T, R>(stage + wave * SP2 + lane * 2, v);
     __syncthreads();
     const int k = tid >> 3, cp = tid & 7;
-    const T o0 = stage[(2 * cp) * SP2 + k], o1 = stage[(2 * cp + 1) * SP2 + k];
+    T o0 = stage[(2 * cp) * SP2 + k], o1 = stage[(2 * cp + 1) * SP2 + k];
+    pin(o0), pin(o1);
     T* dst = Z + (int64_t(s) * M + k) * M + tile * TILE + 2 * cp;
     if constexpr (sizeof(T) == 4) {
       *reinterpret_cast<float2*>(dst) = make_float2(o0, o1);
@@ -430,6 +440,8 @@ __global__ void __launch_bounds__(1024) k_colpass_fwd(const T* __restrict__ xiT,
     T o[4];
 #pragma unroll
     for (int cc = 0; cc < 4; ++cc) o[cc] = stage[(4 * qg + cc) * SP + le * 4 + te];
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) pin(o[cc]);
     T* dst = Z + (int64_t(s) * M + k) * M + tile * TILE + 4 * qg;
     if constexpr (sizeof(T) == 4) {
       *reinterpret_cast<float4*>(dst) = make_float4(o[0], o[1], o[2], o[3]);
@@ -507,6 +519,8 @@ __global__ void __launch_bounds__(512 * NG) k_colpass_adj(const T* __restrict__ 
       stage[(2 * cp + 1) * SP2 + k] = o1;
       __syncthreads();
       load_line<T, R>(stage + wave * SP2 + lane * 2, v);
+#pragma unroll
+      for (int u = 0; u < R; ++u) pin(v[u]);
       __syncthreads();
       line_adjoint<T, R, NU>(v, acc, eacc, s, t, lane);
       continue;
@@ -519,12 +533,14 @@ __global__ void __launch_bounds__(512 * NG) k_colpass_adj(const T* __restrict__ 
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < 4; ++u) v[4 * i + u] = stage[wave * SP + lane * 4 + u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) pin(v[4 * i + u]);
       __syncthreads();
     }
     if (NG == 1 && s + NG < Q) fetch(s + NG);
     line_adjoint<T, R, NU>(v, acc, eacc, s, t, lane);
   }
-  place_edges<T, R, NU>(acc, eacc, lane);
+  place_edges<T, R, NU>(acc, eacc, lane, t.per);
   if constexpr (NG > 1) {
     static_assert(NG == 2, "two phase groups at most");
     // group 1 hands its partial sums to group 0, a few registers per round,
@@ -540,7 +556,7 @@ __global__ void __launch_bounds__(512 * NG) k_colpass_adj(const T* __restrict__ 
       if (g == 0) {
         const T* other = stage + TILE * SP;
 #pragma unroll
-        for (int u = 0; u < RC; ++u) acc[RC * i + u] += other[wave * SP + lane * RC + u];
+        for (int u = 0; u < RC; ++u) acc[RC * i + u] += other[wave * SP + lane * RC + u], pin(acc[RC * i + u]);
       }
       __syncthreads();
     }
@@ -604,12 +620,12 @@ hipError_t launch_colpass_adj(const T* Zt, T* xiT, const Tables<T>& t, hipStream
 
 // Supported (log2 M, nu).  Lines of M = 128 .. 2048 values (R = 2 .. 32 per
 // lane); boundary values and the table-product halo may span several lanes.
-#define WH2WAV_FAST_CASES(X)                                   \
-  X(7, 2) X(7, 3) X(7, 4) X(7, 6) X(7, 8)                      \
-  X(8, 2) X(8, 3) X(8, 4) X(8, 6) X(8, 8)                      \
-  X(9, 2) X(9, 3) X(9, 4) X(9, 6) X(9, 8)                      \
-  X(10, 2) X(10, 3) X(10, 4) X(10, 6) X(10, 8)                 \
-  X(11, 2) X(11, 3) X(11, 4) X(11, 6) X(11, 8)
+#define WH2WAV_FAST_CASES(X)                                                       \
+  X(7, 2) X(7, 3) X(7, 4) X(7, 5) X(7, 6) X(7, 7) X(7, 8)                          \
+  X(8, 2) X(8, 3) X(8, 4) X(8, 5) X(8, 6) X(8, 7) X(8, 8)                          \
+  X(9, 2) X(9, 3) X(9, 4) X(9, 5) X(9, 6) X(9, 7) X(9, 8)                          \
+  X(10, 2) X(10, 3) X(10, 4) X(10, 5) X(10, 6) X(10, 7) X(10, 8)                   \
+  X(11, 2) X(11, 3) X(11, 4) X(11, 5) X(11, 6) X(11, 7) X(11, 8)
 
 }  // namespace
 

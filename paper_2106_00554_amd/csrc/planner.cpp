@@ -57,18 +57,13 @@ Cx csqrt(Cx a) {
 }
 
 // ---------------------------------------------------------------- filters
-// Daubechies minimum-phase filter by spectral factorisation.  The roots of
-// P(y) = sum_{k<nu} C(nu-1+k, k) y^k are found with the Aberth-Ehrlich
-// iteration; each root gives z with (2 - z - 1/z)/4 = y, |z| < 1, and the
-// filter is the coefficient list of (1+z)^nu prod (z - z_i) from the highest
-// power down, scaled to sum sqrt(2).
-bool daubechies(int nu, std::vector<R>* out, std::string* err) {
-  out->clear();
-  if (nu == 1) {
-    R s = rsqrt(2) / 2;
-    *out = {s, s};
-    return true;
-  }
+// Spectral factorisation (Sec. 3.2: compactly supported orthonormal wavelets
+// with nu vanishing moments).  The roots of P(y) = sum_{k<nu} C(nu-1+k, k) y^k
+// are found with the Aberth-Ehrlich iteration; each root gives the pair z, 1/z
+// with (2 - z - 1/z)/4 = y, and a filter is the coefficient list of
+// (1+z)^nu prod (z - z_i) over one member of each pair, from the highest power
+// down, scaled to sum sqrt(2).
+bool y_roots(int nu, std::vector<Cx>* out, std::string* err) {
   const int d = nu - 1;
   std::vector<R> p(nu);  // p[k] = coefficient of y^k
   for (int k = 0; k < nu; ++k) {
@@ -117,9 +112,22 @@ bool daubechies(int nu, std::vector<R>* out, std::string* err) {
       if (cabs2(dp) > 0) z[i] = z[i] - v / dp;
     }
   if (!converged) {
-    *err = "Daubechies root finding did not converge";
+    *err = "filter root finding did not converge";
     return false;
   }
+  *out = z;
+  return true;
+}
+
+// The member z, |z| < 1, of the pair belonging to the root y.
+Cx inside_root(Cx y) {
+  Cx b = Cx{2, 0} - Cx{4, 0} * y;
+  Cx disc = csqrt(b * b - Cx{4, 0});
+  Cx z1 = (b + disc) / Cx{2, 0}, z2 = (b - disc) / Cx{2, 0};
+  return cabs2(z1) < 1 ? z1 : z2;
+}
+
+std::vector<R> taps_from_roots(int nu, const std::vector<Cx>& zs) {
   std::vector<Cx> poly{{1, 0}};
   auto mul = [&](Cx a0, Cx a1) {  // poly *= (a0 z + a1)
     std::vector<Cx> o(poly.size() + 1, Cx{0, 0});
@@ -130,17 +138,107 @@ bool daubechies(int nu, std::vector<R>* out, std::string* err) {
     poly.swap(o);
   };
   for (int i = 0; i < nu; ++i) mul({1, 0}, {1, 0});
-  for (int i = 0; i < d; ++i) {
-    Cx b = Cx{2, 0} - Cx{4, 0} * z[i];
-    Cx disc = csqrt(b * b - Cx{4, 0});
-    Cx z1 = (b + disc) / Cx{2, 0}, z2 = (b - disc) / Cx{2, 0};
-    Cx zi = cabs2(z1) < 1 ? z1 : z2;
-    mul({1, 0}, Cx{0, 0} - zi);
-  }
+  for (const Cx& zi : zs) mul({1, 0}, Cx{0, 0} - zi);
   R total = 0;
   for (auto& c : poly) total += c.re;
-  out->resize(poly.size());
-  for (size_t i = 0; i < poly.size(); ++i) (*out)[i] = poly[i].re * rsqrt(2) / total;
+  std::vector<R> out(poly.size());
+  for (size_t i = 0; i < poly.size(); ++i) out[i] = poly[i].re * rsqrt(2) / total;
+  return out;
+}
+
+// Daubechies filter: the minimum-phase choice (every z inside the unit circle).
+bool daubechies(int nu, std::vector<R>* out, std::string* err) {
+  out->clear();
+  if (nu == 1) {
+    R s = rsqrt(2) / 2;
+    *out = {s, s};
+    return true;
+  }
+  std::vector<Cx> ys;
+  if (!y_roots(nu, &ys, err)) return false;
+  std::vector<Cx> zs;
+  for (const Cx& y : ys) zs.push_back(inside_root(y));
+  *out = taps_from_roots(nu, zs);
+  return true;
+}
+
+// Deviation from linear phase of the filter with factor roots zs.  Read from
+// (1+z)^nu prod (z - z_i), highest power first, the filter's response is
+// e^{-i(2nu-1)w} c (1 + e^{iw})^nu prod (e^{iw} - z_i): its phase is linear in
+// w plus phi(w) = sum_i arg(e^{iw} - z_i), taken here from the roots on
+// w_k = pi k / 256 (k = 0 .. 256) and unwrapped along k.  Returns the largest
+// distance of phi from its least-squares straight line.  (From the taps, the
+// phase near w = pi, a zero of order nu, would carry no accurate digits.)
+R phase_deviation(const std::vector<Cx>& zs) {
+  constexpr int K = 256;
+  std::vector<R> w(K + 1), th(K + 1);
+  for (int k = 0; k <= K; ++k) {
+    w[k] = M_PIq * k / K;
+    const Cx u{cosq(w[k]), sinq(w[k])};
+    R a = 0;
+    for (const Cx& z : zs) {
+      const Cx d = u - z;
+      a += atan2q(d.im, d.re);
+    }
+    if (k > 0) {
+      while (a - th[k - 1] > M_PIq) a -= 2 * M_PIq;
+      while (a - th[k - 1] <= -M_PIq) a += 2 * M_PIq;
+    }
+    th[k] = a;
+  }
+  R sw = 0, st = 0, sww = 0, swt = 0;
+  for (int k = 0; k <= K; ++k) sw += w[k], st += th[k], sww += w[k] * w[k], swt += w[k] * th[k];
+  const R n = K + 1;
+  const R c = (n * swt - sw * st) / (n * sww - sw * sw);
+  const R a0 = (st - c * sw) / n;
+  R dev = 0;
+  for (int k = 0; k <= K; ++k) dev = std::max(dev, rabs(th[k] - a0 - c * w[k]));
+  return dev;
+}
+
+// Least-asymmetric filter (symlet).  Each root group of P(y) -- a real root,
+// or a conjugate pair taken together so the taps stay real -- takes the pair
+// member inside or outside the unit circle; groups are ordered by the real,
+// then the imaginary part of their member with Im y >= 0, and bit g of the
+// choice mask selects the outside member for group g.  The filter of least
+// phase_deviation wins; a mask and its complement give the same filter
+// reversed (equal deviation) and the smaller mask is kept.
+bool symlet(int nu, std::vector<R>* out, std::string* err) {
+  if (nu <= 1) return daubechies(nu, out, err);
+  std::vector<Cx> ys;
+  if (!y_roots(nu, &ys, err)) return false;
+  const R tol = 1e-20Q;
+  std::vector<Cx> reps;
+  for (const Cx& y : ys)
+    if (y.im >= -tol) reps.push_back(y);
+  std::sort(reps.begin(), reps.end(), [](const Cx& a, const Cx& b) {
+    return a.re != b.re ? a.re < b.re : a.im < b.im;
+  });
+  std::vector<std::vector<Cx>> groups;
+  for (const Cx& y : reps) {
+    const Cx zin = inside_root(y);
+    if (rabs(y.im) <= tol)
+      groups.push_back({zin});
+    else
+      groups.push_back({zin, Cx{zin.re, -zin.im}});
+  }
+  if (groups.size() > 16) {
+    *err = "too many root groups for the symlet search";
+    return false;
+  }
+  R best_dev = -1;
+  std::vector<Cx> best;
+  for (uint32_t mask = 0; mask < (1u << groups.size()); ++mask) {
+    std::vector<Cx> zs;
+    for (size_t g = 0; g < groups.size(); ++g)
+      for (const Cx& z : groups[g]) zs.push_back(((mask >> g) & 1u) ? Cx{1, 0} / z : z);
+    const R dev = phase_deviation(zs);
+    if (best_dev < 0 || dev < best_dev - 1e-20Q) {
+      best_dev = dev;
+      best = zs;
+    }
+  }
+  *out = taps_from_roots(nu, best);
   return true;
 }
 
@@ -520,9 +618,9 @@ int walsh_sign(int64_t n, int64_t k, int J) {
 
 }  // namespace
 
-int build_tables(int nu, int q, int j, HostPlan* P, std::string* err) {
+int build_tables(int family, int nu, int q, int j, HostPlan* P, std::string* err) {
   std::vector<R> h;
-  if (!daubechies(nu, &h, err)) return WH2WAV_EINTERNAL;
+  if (!(family == WH2WAV_SYM ? symlet(nu, &h, err) : daubechies(nu, &h, err))) return WH2WAV_EINTERNAL;
   std::vector<R> g(2 * nu);
   for (int c = -nu + 1; c <= nu; ++c) {
     R v = h[(1 - c) + nu - 1];
@@ -657,8 +755,10 @@ int build_host_plan(const wh2wav_desc* d, HostPlan* P, std::string* err) {
   if (d->j0 < 0 || d->j < d->j0) return *err = "need 0 <= j0 <= j", WH2WAV_EINVAL;
   if (d->nu >= 2 && ((int64_t)1 << d->j0) < 2 * d->nu)
     return *err = "coarsest level too small: need 2^j0 >= 2 nu", WH2WAV_EINVAL;
-  if (d->family != WH2WAV_DB) return *err = "only the Daubechies family is supported", WH2WAV_EUNSUPPORTED;
-  if (d->boundary != WH2WAV_BD) return *err = "only vanishing-moment boundaries are supported", WH2WAV_EUNSUPPORTED;
+  if (d->family != WH2WAV_DB && d->family != WH2WAV_SYM)
+    return *err = "family must be WH2WAV_DB or WH2WAV_SYM", WH2WAV_EINVAL;
+  if (d->boundary != WH2WAV_BD && d->boundary != WH2WAV_PER)
+    return *err = "boundary must be WH2WAV_BD or WH2WAV_PER", WH2WAV_EINVAL;
   if (d->dtype != WH2WAV_F32 && d->dtype != WH2WAV_F64) return *err = "dtype must be F32 or F64", WH2WAV_EINVAL;
   const int J = d->j + d->q;
   if ((d->dim == 1 && J > 28) || (d->dim == 2 && J > 15))
@@ -666,8 +766,20 @@ int build_host_plan(const wh2wav_desc* d, HostPlan* P, std::string* err) {
   P->dim = d->dim, P->j = d->j, P->q = d->q, P->j0 = d->j0, P->nu = d->nu, P->dtype = d->dtype;
   P->M = (int64_t)1 << d->j;
   P->N = (int64_t)1 << J;
-  int rc = build_tables(d->nu, d->q, d->j, P, err);
+  if (d->basis2d != WH2WAV_ISOTROPIC && d->basis2d != WH2WAV_TENSOR)
+    return *err = "basis2d must be WH2WAV_ISOTROPIC or WH2WAV_TENSOR", WH2WAV_EINVAL;
+  P->family = d->family;
+  P->per = d->boundary == WH2WAV_PER;
+  P->tensor = d->dim == 2 && d->basis2d == WH2WAV_TENSOR;
+  int rc = build_tables(d->family, d->nu, d->q, d->j, P, err);
   if (rc != WH2WAV_OK) return rc;
+  if (P->per) {
+    // periodic extension: every function is an interior one, periodised
+    std::fill(P->tabBL.begin(), P->tabBL.end(), 0.0);
+    std::fill(P->tabBR.begin(), P->tabBR.end(), 0.0);
+    std::fill(P->synL.begin(), P->synL.end(), 0.0);
+    std::fill(P->synR.begin(), P->synR.end(), 0.0);
+  }
 
   const int64_t total = d->dim == 1 ? P->N : P->N * P->N;
   if (d->m < 0 || d->m > total) return *err = "m out of range", WH2WAV_EINVAL;

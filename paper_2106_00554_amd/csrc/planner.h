@@ -24,6 +24,9 @@ namespace wh2wav {
 
 struct HostPlan {
   int dim = 1, j = 0, q = 1, j0 = 0, nu = 2, dtype = WH2WAV_F64;
+  int family = WH2WAV_DB;
+  bool per = false;          // periodic extension (Sec. 3.2): no boundary functions; bands and blocks are zero
+  bool tensor = false;       // 2D tensor-product basis (products of 1D basis functions)
   int64_t M = 0, N = 0;      // per dimension: M = 2^j, N = 2^{j+q}
   int Q = 2;                 // 2^q phases
 
@@ -67,6 +70,6 @@ int build_host_plan(const wh2wav_desc* d, HostPlan* out, std::string* err);
 // Shape/table builders shared by the two entry points that need them
 // (plan creation and host-table introspection).  They depend only on nu
 // and q (and j for the 2^{-j/2} factor).
-int build_tables(int nu, int q, int j, HostPlan* out, std::string* err);
+int build_tables(int family, int nu, int q, int j, HostPlan* out, std::string* err);
 
 }  // namespace wh2wav

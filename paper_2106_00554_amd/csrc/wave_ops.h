@@ -58,6 +58,19 @@ __device__ __forceinline__ double read_lane(double v, int l) {
   return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
+// Keeps a value read from LDS at this point of the program.  Before a
+// block-wide barrier after which other waves overwrite the same LDS words,
+// every value read from them must be pinned: the machine-level passes do not
+// treat s_barrier as a memory operation and may otherwise sink an LDS read
+// whose result is used only later past the barrier (observed for the last
+// staging round of the adjoint column pass, which then read the next phase's
+// values).  The empty asm takes the value as an operand, so the read and its
+// wait happen before it.
+template <typename T>
+__device__ __forceinline__ void pin(T& v) {
+  asm volatile("" : "+v"(v));
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();

@@ -69,6 +69,7 @@ struct Tables {
   const T* synL;   // (3nu-1) * 2nu
   const T* synR;   // (3nu-1) * 2nu
   int nu, q, Q;
+  int per;         // periodic extension (Sec. 3.2): lines wrap around, no boundary functions
 };
 
 struct OmegaDev {
@@ -173,6 +174,59 @@ __global__ void k_analysis(const T* __restrict__ in, T* __restrict__ out, int64_
   out[line * line_stride + o * elem_stride] = acc;
 }
 
+// One level of the inverse DWT of the periodic extension (Sec. 3.2): every
+// function is periodised, so output n of a line of 2^{k+1} values is
+// sum_c h_c a_m + g_c d_m over the m with n - 2m = c, m taken modulo 2^k.
+// line_fast: consecutive threads take consecutive lines (strided lines).
+template <typename T>
+__global__ void k_synth_per(const T* __restrict__ in, T* __restrict__ out, int64_t lines,
+                            int64_t line_stride, int64_t elem_stride, int k, int line_fast, Tables<T> t) {
+  const int64_t half = int64_t(1) << k, size = 2 * half;
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gid >= lines * size) return;
+  const int64_t line = line_fast ? gid % lines : gid / size;
+  const int64_t n = line_fast ? gid / lines : gid % size;
+  const T* src = in + line * line_stride;
+  const int nu = t.nu;
+  T acc = 0;
+  for (int c = -nu + 1; c <= nu; ++c) {
+    const int64_t d = n - c;
+    if (d & 1) continue;
+    const int64_t m = (d >> 1) & (half - 1);  // modulo 2^k, also for d < 0
+    acc += src[m * elem_stride] * t.h[c + nu - 1] + src[(half + m) * elem_stride] * t.g[c + nu - 1];
+  }
+  out[line * line_stride + n * elem_stride] = acc;
+}
+
+// Transpose of k_synth_per (one level of the periodic forward DWT):
+// a_m = sum_c h_c v_{(2m + c) mod 2^{k+1}}, d_m the same with g.
+template <typename T>
+__global__ void k_analysis_per(const T* __restrict__ in, T* __restrict__ out, int64_t lines,
+                               int64_t line_stride, int64_t elem_stride, int k, int line_fast, Tables<T> t) {
+  const int64_t half = int64_t(1) << k, size = 2 * half;
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gid >= lines * size) return;
+  const int64_t line = line_fast ? gid % lines : gid / size;
+  const int64_t o = line_fast ? gid / lines : gid % size;
+  const T* src = in + line * line_stride;
+  const int nu = t.nu;
+  const int kind = o >= half ? 1 : 0;
+  const int64_t m = o - kind * half;
+  const T* taps = kind ? t.g : t.h;
+  T acc = 0;
+  for (int c = -nu + 1; c <= nu; ++c) acc += taps[c + nu - 1] * src[((2 * m + c) & (size - 1)) * elem_stride];
+  out[line * line_stride + o * elem_stride] = acc;
+}
+
+// out = in^T for an n x n row-major array (any n), one element per thread.
+template <typename T>
+__global__ void k_transpose_any(const T* __restrict__ in, T* __restrict__ out, int64_t n) {
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gid >= n * n) return;
+  const int64_t r = gid / n, c = gid % n;
+  out[c * n + r] = in[r * n + c];
+}
+
 // Plain fill (kept as a kernel so that the path records no memset nodes when
 // a caller captures it into a graph).
 template <typename T>
@@ -230,6 +284,14 @@ __device__ void table_product(const T* xi, T* L, int M, int s, int tid, int nthr
                               const Tables<T>& t) {
   const int nu = t.nu, Q = t.Q, band = 2 * nu - 1;
   const int right_first = M - nu > nu ? M - nu : nu;
+  if (t.per) {  // periodic extension: the correlation wraps around the line
+    for (int p = tid; p < M; p += nthreads) {
+      T acc = 0;
+      for (int l = -nu + 1; l <= nu - 1; ++l) acc += xi[(p - l) & (M - 1)] * t.tabT[(l + nu - 1) * Q + s];
+      L[p] = acc;
+    }
+    return;
+  }
   for (int p = tid; p < M; p += nthreads) {
     T acc = 0;
     for (int l = -nu + 1; l <= nu - 1; ++l) {
@@ -256,6 +318,14 @@ __device__ void table_product_t(const T* R, T* xi, int M, int s, int tid, int nt
                                 const Tables<T>& t) {
   const int nu = t.nu, Q = t.Q, band = 2 * nu - 1;
   const int right_first = M - nu > nu ? M - nu : nu;
+  if (t.per) {
+    for (int m = tid; m < M; m += nthreads) {
+      T acc = 0;
+      for (int l = -nu + 1; l <= nu - 1; ++l) acc += R[(m + l) & (M - 1)] * t.tabT[(l + nu - 1) * Q + s];
+      xi[m] += acc;
+    }
+    return;
+  }
   for (int m = tid; m < M; m += nthreads) {
     T acc = 0;
     if (m >= nu && m < right_first) {
@@ -426,6 +496,7 @@ Tables<T> tables_of(const wh2wav_plan_s* p) {
   t.nu = p->host.nu;
   t.q = p->host.q;
   t.Q = p->host.Q;
+  t.per = p->host.per ? 1 : 0;
   return t;
 }
 
@@ -434,7 +505,7 @@ wh2wav_fast::Tables<T> fast_tables_of(const wh2wav_plan_s* p) {
   const Tables<T> a = tables_of<T>(p);
   wh2wav_fast::Tables<T> f;
   f.h = a.h, f.g = a.g, f.tabT = a.tabT, f.bandL = a.bandL, f.bandR = a.bandR, f.synL = a.synL, f.synR = a.synR;
-  f.nu = a.nu, f.q = a.q, f.Q = a.Q;
+  f.nu = a.nu, f.q = a.q, f.Q = a.Q, f.per = a.per;
   return f;
 }
 
@@ -449,7 +520,7 @@ wh2wav_fast::Omega fast_omega_of(const wh2wav_plan_s* p) {
 bool use_fast1d(const wh2wav_plan_s* p) {
   const auto& H = p->host;
   const bool f64 = H.dtype == WH2WAV_F64;
-  return H.dim == 1 && wh2wav_fast::supported1d(f64 ? 8 : 4, H.j, H.nu, H.q) && H.j0 <= (f64 ? 13 : 14);
+  return H.dim == 1 && !H.per && wh2wav_fast::supported1d(f64 ? 8 : 4, H.j, H.nu, H.q) && H.j0 <= (f64 ? 13 : 14);
 }
 
 // 1D lines of 128 .. 2048 values: the whole line transform (table product,
@@ -504,14 +575,109 @@ int launch_synth(const wh2wav_plan_s* p, const T* in, T* out, int64_t lines, int
                  int k, bool line_fast, bool analysis, hipStream_t st) {
   const int64_t total = lines * (int64_t(2) << k);
   const int64_t blocks = (total + kThreads - 1) / kThreads;
-  if (analysis)
+  if (p->host.per) {
+    if (analysis)
+      hipLaunchKernelGGL(k_analysis_per<T>, dim3(unsigned(blocks)), dim3(kThreads), 0, st, in, out, lines, ls, es,
+                         k, int(line_fast), tables_of<T>(p));
+    else
+      hipLaunchKernelGGL(k_synth_per<T>, dim3(unsigned(blocks)), dim3(kThreads), 0, st, in, out, lines, ls, es, k,
+                         int(line_fast), tables_of<T>(p));
+  } else if (analysis) {
     hipLaunchKernelGGL(k_analysis<T>, dim3(unsigned(blocks)), dim3(kThreads), 0, st, in, out, lines, ls, es, k,
                        int(line_fast), tables_of<T>(p));
-  else
+  } else {
     hipLaunchKernelGGL(k_synth<T>, dim3(unsigned(blocks)), dim3(kThreads), 0, st, in, out, lines, ls, es, k,
                        int(line_fast), tables_of<T>(p));
+  }
   HIP_OK(hipGetLastError());
   return WH2WAV_OK;
+}
+
+template <typename T>
+int launch_transpose(const T* in, T* out, int64_t n, hipStream_t st) {
+  const int64_t total = n * n;
+  hipLaunchKernelGGL(k_transpose_any<T>, dim3(unsigned((total + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
+                     in, out, n);
+  HIP_OK(hipGetLastError());
+  return WH2WAV_OK;
+}
+
+// Periodic extension, 2D inverse DWT x -> xi^T (out).  Each isotropic level
+// S X S^T runs as one-level synthesis along the columns, then along the rows
+// of the top-left 2^{k+1} block.  The levels run in the transposed frame:
+// the same synthesis applied to x^T (whose blocks are the transposed bands)
+// yields xi^T.  W, Z: M x M scratch.
+template <typename T>
+int idwt2d_per(const wh2wav_plan_s* p, const T* x, T* out, T* W, T* Z, hipStream_t st) {
+  const auto& H = p->host;
+  const int64_t M = H.M;
+  if (H.j0 == H.j) return launch_transpose<T>(x, out, M, st);
+  int rc = launch_transpose<T>(x, W, M, st);
+  for (int k = H.j0; k < H.j && rc == WH2WAV_OK; ++k) {
+    const int64_t size = int64_t(2) << k;
+    rc = launch_synth<T>(p, W, Z, size, 1, M, k, true, false, st);  // columns
+    if (rc == WH2WAV_OK) rc = launch_synth<T>(p, Z, k + 1 == H.j ? out : W, size, M, 1, k, false, false, st);
+  }
+  return rc;
+}
+
+// Its transpose: xi'^T (in) -> x.  in is read only by the first level.
+template <typename T>
+int dwt2d_per(const wh2wav_plan_s* p, const T* in, T* x, T* W, T* Z, hipStream_t st) {
+  const auto& H = p->host;
+  const int64_t M = H.M;
+  if (H.j0 == H.j) return launch_transpose<T>(in, x, M, st);
+  const T* src = in;
+  int rc = WH2WAV_OK;
+  for (int k = H.j - 1; k >= H.j0 && rc == WH2WAV_OK; --k) {
+    const int64_t size = int64_t(2) << k;
+    rc = launch_synth<T>(p, src, Z, size, M, 1, k, false, true, st);  // rows
+    if (rc == WH2WAV_OK) rc = launch_synth<T>(p, Z, W, size, 1, M, k, true, true, st);  // columns
+    src = W;
+  }
+  if (rc == WH2WAV_OK) rc = launch_transpose<T>(W, x, M, st);
+  return rc;
+}
+
+// Tensor-product basis: x[c1][c2] is the coefficient of r_{c1} (x) r_{c2}, so
+// xi = W x W^T with W the 1D multilevel synthesis (boundary-corrected or
+// periodic, as the plan says).  In the transposed frame xi^T = W x^T W^T: the
+// full 1D synthesis along every column, then along every row.  Each level
+// writes its block into `tmp`, which is copied back into `cur` (a memcpy
+// node, not a memset, if a caller captures the call).
+template <typename T>
+int tensor_level(const wh2wav_plan_s* p, T* cur, T* tmp, bool columns, int k, bool analysis, hipStream_t st) {
+  const int64_t M = p->host.M, size = int64_t(2) << k;
+  const size_t e = sizeof(T);
+  int rc = columns ? launch_synth<T>(p, cur, tmp, M, 1, M, k, true, analysis, st)
+                   : launch_synth<T>(p, cur, tmp, M, M, 1, k, false, analysis, st);
+  if (rc) return rc;
+  if (columns)  // rows 0 .. size-1, all M columns
+    HIP_OK(hipMemcpy2DAsync(cur, M * e, tmp, M * e, M * e, size, hipMemcpyDeviceToDevice, st));
+  else  // columns 0 .. size-1 of all M rows
+    HIP_OK(hipMemcpy2DAsync(cur, M * e, tmp, M * e, size * e, M, hipMemcpyDeviceToDevice, st));
+  return WH2WAV_OK;
+}
+
+// Tensor basis, forward first stage: x -> xi^T (out); W scratch.
+template <typename T>
+int idwt2d_tensor(const wh2wav_plan_s* p, const T* x, T* out, T* W, hipStream_t st) {
+  const auto& H = p->host;
+  int rc = launch_transpose<T>(x, out, H.M, st);
+  for (int k = H.j0; k < H.j && rc == WH2WAV_OK; ++k) rc = tensor_level<T>(p, out, W, true, k, false, st);
+  for (int k = H.j0; k < H.j && rc == WH2WAV_OK; ++k) rc = tensor_level<T>(p, out, W, false, k, false, st);
+  return rc;
+}
+
+// Its transpose: xi'^T (in, overwritten) -> x; W scratch.
+template <typename T>
+int dwt2d_tensor(const wh2wav_plan_s* p, T* in, T* x, T* W, hipStream_t st) {
+  const auto& H = p->host;
+  int rc = WH2WAV_OK;
+  for (int k = H.j - 1; k >= H.j0 && rc == WH2WAV_OK; --k) rc = tensor_level<T>(p, in, W, false, k, true, st);
+  for (int k = H.j - 1; k >= H.j0 && rc == WH2WAV_OK; --k) rc = tensor_level<T>(p, in, W, true, k, true, st);
+  if (rc == WH2WAV_OK) rc = launch_transpose<T>(in, x, H.M, st);
+  return rc;
 }
 
 // Forward stages: 0 = inverse DWT, 1 = column pass (2D) / line transform (1D),
@@ -559,8 +725,15 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
   T* TMP = W + M * M;
   T* Z = TMP + M * M;
   const bool fast = use_fast(p);
-  if (run(0))  // xi^T into TMP (tiled 2D wavelet kernels, every shape); W and Z serve as scratch
+  if (run(0) && H.tensor) {  // xi^T into TMP; W serves as scratch
+    int rc = idwt2d_tensor<T>(p, x, TMP, W, st);
+    if (rc) return rc;
+  } else if (run(0) && H.per) {  // xi^T into TMP; W and Z serve as scratch
+    int rc = idwt2d_per<T>(p, x, TMP, W, Z, st);
+    if (rc) return rc;
+  } else if (run(0)) {  // xi^T into TMP (tiled 2D wavelet kernels, every shape); W and Z serve as scratch
     HIP_OK(wh2wav_fast::idwt2d<T>(x, TMP, W, Z, M, H.j0, H.j, fast_tables_of<T>(p), st));
+  }
   if (fast) {
     if (run(1)) HIP_OK(wh2wav_fast::colpass_fwd<T>(TMP, Z, H.j, fast_tables_of<T>(p), st));
     if (run(2)) HIP_OK(wh2wav_fast::rowpass_fwd<T>(Z, y, H.j, fast_tables_of<T>(p), fast_omega_of(p), N, st));
@@ -637,6 +810,8 @@ int adjoint_impl(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t
   if (use_fast(p)) {
     if (run(0)) HIP_OK(wh2wav_fast::rowpass_adj<T>(y, Z, H.j, fast_tables_of<T>(p), fast_omega_of(p), N, st));
     if (run(1)) HIP_OK(wh2wav_fast::colpass_adj<T>(Z, TMP, H.j, fast_tables_of<T>(p), st));
+    if (run(2) && H.tensor) return dwt2d_tensor<T>(p, TMP, x, W, st);
+    if (run(2) && H.per) return dwt2d_per<T>(p, TMP, x, W, Z, st);
     if (run(2)) HIP_OK(wh2wav_fast::dwt2d<T>(TMP, x, W, Z, M, H.j0, H.j, fast_tables_of<T>(p), st));
     return WH2WAV_OK;
   }
@@ -654,6 +829,8 @@ int adjoint_impl(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t
                        0, t, om);
     HIP_OK(hipGetLastError());
   }
+  if (run(2) && H.tensor) return dwt2d_tensor<T>(p, TMP, x, W, st);
+  if (run(2) && H.per) return dwt2d_per<T>(p, TMP, x, W, Z, st);
   if (run(2)) HIP_OK(wh2wav_fast::dwt2d<T>(TMP, x, W, Z, M, H.j0, H.j, fast_tables_of<T>(p), st));
   return WH2WAV_OK;
 }

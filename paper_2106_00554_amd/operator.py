@@ -19,8 +19,18 @@ def default_j0(nu):
     return 0 if nu == 1 else int(math.ceil(math.log2(2 * nu)))
 
 
-def make_desc(dim, j, q, nu, j0=None, dtype=torch.float64, omega=None):
-    """Build a wh2wav_desc; returns (desc, keepalive) -- keep the second alive until planned."""
+_FAMILIES = {"db": _abi.WH2WAV_DB, "sym": _abi.WH2WAV_SYM}
+_BOUNDARIES = {"bd": _abi.WH2WAV_BD, "per": _abi.WH2WAV_PER}
+_BASES = {"isotropic": _abi.WH2WAV_ISOTROPIC, "tensor": _abi.WH2WAV_TENSOR}
+
+
+def make_desc(dim, j, q, nu, j0=None, dtype=torch.float64, omega=None, family="db", boundary="bd",
+              basis2d="isotropic"):
+    """Build a wh2wav_desc; returns (desc, keepalive) -- keep the second alive until planned.
+
+    family: "db" (Daubechies) or "sym" (least-asymmetric symlets); boundary:
+    "bd" (vanishing-moment-preserving boundary functions) or "per" (periodic);
+    basis2d: "isotropic" (quadtree) or "tensor" (products of 1D basis functions)."""
     j0 = default_j0(nu) if j0 is None else j0
     N = 1 << (j + q)
     total = N ** dim
@@ -31,21 +41,24 @@ def make_desc(dim, j, q, nu, j0=None, dtype=torch.float64, omega=None):
         m = int(keep.size)
         ptr = keep.ctypes.data_as(_abi.ctypes.POINTER(_abi.ctypes.c_int64)) if m else \
             _abi.ctypes.cast(_abi.ctypes.pointer(_abi.ctypes.c_int64(0)), _abi.ctypes.POINTER(_abi.ctypes.c_int64))
-    desc = _abi.wh2wav_desc(dim=dim, j=j, q=q, j0=j0, nu=nu, family=_abi.WH2WAV_DB,
-                            boundary=_abi.WH2WAV_BD, dtype=_DTYPES[dtype], m=m, omega=ptr)
+    desc = _abi.wh2wav_desc(dim=dim, j=j, q=q, j0=j0, nu=nu, family=_FAMILIES[family],
+                            boundary=_BOUNDARIES[boundary], dtype=_DTYPES[dtype], m=m, omega=ptr,
+                            basis2d=_BASES[basis2d])
     return desc, keep
 
 
 class Wh2Wav:
     """y = P_Omega A x and x = A^T P_Omega^T y on the current CUDA/HIP device."""
 
-    def __init__(self, dim, j, q, nu, j0=None, dtype=torch.float64, omega=None, device=None):
-        self.dim, self.j, self.q, self.nu = dim, j, q, nu
+    def __init__(self, dim, j, q, nu, j0=None, dtype=torch.float64, omega=None, device=None, family="db",
+                 boundary="bd", basis2d="isotropic"):
+        self.dim, self.j, self.q, self.nu, self.family, self.boundary = dim, j, q, nu, family, boundary
+        self.basis2d = basis2d
         self.j0 = default_j0(nu) if j0 is None else j0
         self.dtype = dtype
         self.M, self.N = 1 << j, 1 << (j + q)
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
-        desc, keep = make_desc(dim, j, q, nu, self.j0, dtype, omega)
+        desc, keep = make_desc(dim, j, q, nu, self.j0, dtype, omega, family, boundary, basis2d)
         self.m = int(desc.m)
         with torch.cuda.device(self.device):
             self._plan = _abi.wh2wav_plan(desc)
@@ -107,7 +120,8 @@ class Wh2WavBatch:
         self.x_shapes, self.ms, self.dtypes = [], [], []
         for sp in specs:
             dtype = sp.get("dtype", torch.float64)
-            d, k = make_desc(sp["dim"], sp["j"], sp["q"], sp["nu"], sp.get("j0"), dtype, sp.get("omega"))
+            d, k = make_desc(sp["dim"], sp["j"], sp["q"], sp["nu"], sp.get("j0"), dtype, sp.get("omega"),
+                             sp.get("family", "db"), sp.get("boundary", "bd"), sp.get("basis2d", "isotropic"))
             descs.append(d)
             keeps.append(k)
             M = 1 << sp["j"]

@@ -15,10 +15,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def desc(nu, j, q, dim=1, j0=None, dtype=1, omega=None):
+    """Descriptor for nu (an int: Daubechies; a filters.Symlet: symlets)."""
     j0 = (0 if nu == 1 else int(np.ceil(np.log2(2 * nu)))) if j0 is None else j0
     N = 1 << (j + q)
-    d = abi.wh2wav_desc(dim=dim, j=j, q=q, j0=j0, nu=nu, family=0, boundary=0, dtype=dtype,
-                        m=N ** dim, omega=None)
+    fam = abi.WH2WAV_SYM if isinstance(nu, filters.Symlet) else abi.WH2WAV_DB
+    d = abi.wh2wav_desc(dim=dim, j=j, q=q, j0=j0, nu=int(nu), family=fam, boundary=0, dtype=dtype,
+                        m=N ** dim, omega=None, basis2d=0)
     keep = None
     if omega is not None:
         keep = np.ascontiguousarray(np.asarray(omega, dtype=np.int64))
@@ -35,14 +37,16 @@ def test_every_declared_symbol_is_exported():
         assert hasattr(abi.LIB, name)
 
 
-@pytest.mark.parametrize("nu", [1, 2, 3, 4, 8])
+@pytest.mark.parametrize("nu", [1, 2, 3, 4, 8, filters.Symlet(2), filters.Symlet(4), filters.Symlet(5),
+                                filters.Symlet(6), filters.Symlet(8), filters.Symlet(10)])
 def test_filters_match_oracle(nu):
     d, _ = desc(nu, max(4, int(np.ceil(np.log2(2 * nu))) + 1), 1)
     assert np.abs(np.array(abi.wh2wav_host_table(d, "h")) - filters.daubechies(nu)).max() < 2e-16
     assert np.abs(np.array(abi.wh2wav_host_table(d, "g")) - filters.wavelet(nu)).max() < 2e-16
 
 
-@pytest.mark.parametrize("nu,j,q", [(1, 3, 1), (2, 4, 1), (4, 5, 2), (8, 6, 2), (3, 4, 3)])
+@pytest.mark.parametrize("nu,j,q", [(1, 3, 1), (2, 4, 1), (4, 5, 2), (8, 6, 2), (3, 4, 3), (filters.Symlet(4), 5, 2),
+                                    (filters.Symlet(6), 5, 1)])
 def test_interior_table_matches_oracle(nu, j, q):
     d, _ = desc(nu, j, q)
     Q = 1 << q
@@ -56,7 +60,8 @@ def test_interior_table_matches_oracle(nu, j, q):
     assert np.abs(T - ref).max() < 1e-15
 
 
-@pytest.mark.parametrize("nu,j,q", [(1, 3, 1), (2, 4, 1), (4, 5, 2), (8, 6, 1), (3, 4, 2)])
+@pytest.mark.parametrize("nu,j,q", [(1, 3, 1), (2, 4, 1), (4, 5, 2), (8, 6, 1), (3, 4, 2), (filters.Symlet(4), 5, 2),
+                                    (filters.Symlet(5), 5, 1)])
 def test_boundary_bands_match_oracle(nu, j, q):
     """Prop. 4.2 (bd): Walsh coefficients at s < 2^q of the boundary functions on each cell."""
     d, _ = desc(nu, j, q)
@@ -78,7 +83,7 @@ def test_boundary_bands_match_oracle(nu, j, q):
                     assert abs(table[p, m, s] - ref) < tol, (side, m, p, s, tol)
 
 
-@pytest.mark.parametrize("nu", [1, 2, 3, 4, 6, 8])
+@pytest.mark.parametrize("nu", [1, 2, 3, 4, 6, 8, filters.Symlet(4), filters.Symlet(6)])
 def test_synthesis_blocks_match_oracle(nu):
     """Boundary blocks of the one-level synthesis matrix V_k + W_k -> V_{k+1}.
 
@@ -119,7 +124,8 @@ def test_omega_row_offsets():
 
 
 @pytest.mark.parametrize("field,value", [("dim", 3), ("nu", 0), ("nu", 11), ("q", 0), ("j0", 1), ("j", 1),
-                                         ("dtype", 5), ("family", 1), ("boundary", 2), ("m", 5)])
+                                         ("dtype", 5), ("family", 2), ("boundary", 2), ("boundary", -1), ("m", 5),
+                                         ("basis2d", 2)])
 def test_descriptor_validation(field, value):
     d, _ = desc(2, 4, 1)
     setattr(d, field, value)

@@ -53,9 +53,17 @@ def test_autograd_gradient_equals_oracle_adjoint(dtype, tol):
     assert abs(loss.item() - 0.5 * r @ r) <= tol * 0.5 * (r @ r)
 
 
-@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 2e-3)])
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 1e-3)])
 def test_finite_differences_1024(dtype, tol):
-    """cfg of the reconstruction example: db4, M = 1024^2, q = 1, 25 % multilevel Omega."""
+    """cfg of the reconstruction example: db4, M = 1024^2, q = 1, 25 % multilevel Omega.
+
+    f(x) = 0.5 ||P A x - y||^2 is quadratic, so the central difference
+    [f(x + e v) - f(x - e v)] / 2e equals <grad f, v> up to rounding for any e.
+    Each direction is a Gaussian w plus (||w|| / ||grad||) grad, so <grad, v> is
+    about ||w|| ||grad|| and a gradient of the wrong sign or size fails by far;
+    the loss is summed in FP64.  The mismatch is measured against |<grad, v>|:
+    the FP32 bound follows from the FP32 forward error (about 4e-7 relative),
+    which the difference quotient magnifies by about ||x|| / ||grad||."""
     from paper_2106_00554_amd import autograd as ag
     name = "2d_db4_j10_q1_25pct"
     w = inputs.WORKLOADS[name]
@@ -69,7 +77,7 @@ def test_finite_differences_1024(dtype, tol):
                      requires_grad=True)
 
     def f(z):
-        r = ag.forward(opr, z) - y
+        r = (ag.forward(opr, z) - y).double()
         return 0.5 * torch.dot(r, r)
 
     loss = f(x)
@@ -77,15 +85,16 @@ def test_finite_differences_1024(dtype, tol):
     rng = inputs.rng_for(4003)
     worst = 0.0
     with torch.no_grad():
+        gn = grad.double().norm()
         for _ in range(32):
-            v = torch.tensor(rng.standard_normal(opr.x_shape), dtype=dtype, device="cuda")
+            wv = torch.tensor(rng.standard_normal(opr.x_shape), dtype=torch.float64, device="cuda")
+            v = (wv + (wv.norm() / gn) * grad.double()).to(dtype)
             eps = (x.norm() / v.norm()).item()
             fp, fm = f(x + eps * v).item(), f(x - eps * v).item()
             fd = (fp - fm) / (2 * eps)
-            exact = torch.sum(grad * v).item()
-            scale = (abs(fp) + abs(fm)) / (2 * eps) + grad.norm().item() * v.norm().item()
-            worst = max(worst, abs(fd - exact) / scale)
-    print(f"worst scaled FD mismatch {worst:.3e}")
+            exact = torch.sum(grad.double() * v.double()).item()
+            worst = max(worst, abs(fd - exact) / abs(exact))
+    print(f"worst FD mismatch relative to <grad, v>: {worst:.3e}")
     assert worst < tol
 
 
@@ -152,3 +161,31 @@ def test_batched_leading_dimension():
     xb = ag.adjoint(opr, yb)
     for b in range(3):
         assert torch.equal(xb[b], opr.adjoint(yb[b].contiguous()))
+
+
+def test_graphed_gradient_and_fista_match_eager():
+    """The HIP-graph forms replayed several times, with eager work in between, equal the eager forms."""
+    from paper_2106_00554_amd import autograd as ag
+    name = "2d_db4_j10_q1_25pct"
+    w = inputs.WORKLOADS[name]
+    Xtrue, omega = inputs.workload_inputs(name)
+    for dtype in (torch.float64, torch.float32):
+        opr = make_op(w["nu"], w["j"], w["q"], w["j0"], dtype, omega)
+        y = ag.forward(opr, torch.tensor(Xtrue, dtype=dtype, device="cuda")).detach()
+        gg = ag.GraphedGradient(opr, y)
+        for seed in (501, 502, 503):
+            xv = torch.tensor(inputs.coefficients_2d(w["j"], w["j0"], seed), dtype=dtype, device="cuda")
+            got = gg(xv).clone()
+            z = xv.clone().requires_grad_(True)
+            r = ag.forward(opr, z) - y
+            (ref,) = torch.autograd.grad(0.5 * torch.dot(r, r), z)
+            torch.cuda.synchronize()
+            assert rel(got.cpu().numpy(), ref.cpu().numpy()) < (1e-12 if dtype == torch.float64 else 1e-5)
+        lam = 0.01 * float(opr.adjoint(y).abs().max())
+        x_eager = ag.fista(opr, y, lam, 12)
+        x_graph = ag.fista_graphed(opr, y, lam, 12)
+        x_graph2 = ag.fista_graphed(opr, y, lam, 12)
+        torch.cuda.synchronize()
+        tol = 1e-12 if dtype == torch.float64 else 1e-5
+        assert rel(x_graph.cpu().numpy(), x_eager.cpu().numpy()) < tol
+        assert torch.equal(x_graph, x_graph2)

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import operator as op
+from oracle.filters import Symlet
 from tests import inputs
 
 torch = pytest.importorskip("torch")
@@ -22,11 +23,13 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
-def gpu_pair(dim, nu, j, q, j0, dtype, x, omega, y_in):
+def gpu_pair(dim, nu, j, q, j0, dtype, x, omega, y_in, boundary="bd", basis2d="isotropic"):
+    """Forward of x and adjoint of y_in through the C ABI; nu an int (Daubechies) or a Symlet."""
+    from oracle.filters import family
     from paper_2106_00554_amd.operator import Wh2Wav
-    print(f"[gpu] dim={dim} nu={nu} j={j} q={q} j0={j0} {dtype} m={'all' if omega is None else len(omega)}",
-          flush=True)
-    opr = Wh2Wav(dim, j, q, nu, j0, dtype, omega)
+    print(f"[gpu] dim={dim} nu={nu!r} j={j} q={q} j0={j0} {boundary} {basis2d} {dtype} "
+          f"m={'all' if omega is None else len(omega)}", flush=True)
+    opr = Wh2Wav(dim, j, q, int(nu), j0, dtype, omega, family=family(nu), boundary=boundary, basis2d=basis2d)
     xt = torch.tensor(x, dtype=dtype, device="cuda")
     y = opr.forward(xt)
     yt = torch.tensor(y_in, dtype=dtype, device="cuda")
@@ -260,6 +263,7 @@ CASES_2D_WAVE = [
     (4, 7, 1, 7, 0.3),  # j0 = j: no wavelet level
     (3, 8, 1, 3, 0.2), (8, 8, 2, 4, 0.15), (6, 9, 1, 4, 0.2), (8, 9, 1, 4, None),
     (3, 7, 4, 3, 0.2),  # q = 4: sixteen phase waves per row workgroup
+    (5, 8, 1, 4, 0.2), (7, 9, 2, 4, None), (5, 10, 1, 4, 0.25), (7, 7, 1, 4, 0.3),  # odd orders 5 and 7
 ]
 
 
@@ -311,3 +315,101 @@ def test_destroyed_plans_are_rejected():
         with pytest.raises(_abi.Wh2WavError) as e:
             call()
         assert e.value.code == _abi.WH2WAV_EINVAL
+
+
+CASES_SYMLETS = [
+    # dim, symlet order, j, q, j0, omega density: generic and wave kernels, 1D and 2D
+    (1, 4, 8, 1, 3, None), (1, 6, 11, 2, 4, 0.2), (1, 5, 6, 2, 4, 0.5),
+    (2, 4, 6, 1, 3, 0.3), (2, 5, 7, 2, 4, None), (2, 8, 9, 1, 4, 0.2), (2, 6, 10, 1, 4, 0.25),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dim,nu,j,q,j0,dens", CASES_SYMLETS)
+def test_parity_symlets(dim, nu, j, q, j0, dens, dtype):
+    """Symlets (least-asymmetric filters, Sec. 3.2 / Table 1) through every kernel family."""
+    sym = Symlet(nu)
+    cfg = op.Config(sym, j, q, j0)
+    seed = 7000 + 100 * nu + 10 * j + q + dim
+    if dim == 1:
+        x = inputs.coefficients_1d(j, j0, seed)
+        omega = None if dens is None else inputs.uniform_omega(cfg.N, dens, seed + 1)
+        m = cfg.N if omega is None else omega.size
+        yv = inputs.sample_vector(m, seed + 2)
+        A = op.matrix_1d(cfg)
+        y_ref, x_ref = op.forward_1d(A, x, omega), op.adjoint_1d(A, yv, omega)
+    else:
+        x = inputs.coefficients_2d(j, j0, seed)
+        omega = None if dens is None else inputs.multilevel_omega_2d(cfg.N, dens, seed + 1)
+        m = cfg.N ** 2 if omega is None else omega.size
+        yv = inputs.sample_vector(m, seed + 2)
+        blocks = op.Blocks2D(cfg)
+        y_ref = op.forward_2d_full(blocks, x, omega).reshape(-1)
+        x_ref = op.adjoint_2d_full(blocks, yv, omega)
+    y, xa = gpu_pair(dim, sym, j, q, j0, dtype, x, omega, yv)
+    assert rel(y, y_ref) < TOL[dtype], rel(y, y_ref)
+    assert rel(xa, x_ref) < TOL[dtype], rel(xa, x_ref)
+
+
+CASES_PERIODIC = [
+    # dim, nu (int: Daubechies, negative: symlet of that order), j, q, j0, omega density
+    (1, 1, 4, 1, 0, None), (1, 2, 5, 1, 2, 0.4), (1, 4, 8, 2, 3, None), (1, 8, 10, 1, 4, 0.3), (1, 3, 12, 1, 3, 0.2),
+    (1, -4, 7, 2, 3, 0.5),
+    (2, 2, 4, 1, 2, None), (2, 4, 5, 2, 3, 0.3), (2, 3, 6, 1, 3, 0.25),   # generic line kernels
+    (2, 4, 7, 1, 3, 0.3), (2, 8, 9, 2, 4, 0.15), (2, 6, 10, 1, 4, None),  # wave line kernels
+    (2, 2, 8, 3, 2, 0.2), (2, -6, 8, 1, 4, 0.25), (2, 8, 4, 1, 4, 0.5),   # j0 = j
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dim,nu,j,q,j0,dens", CASES_PERIODIC)
+def test_parity_periodic(dim, nu, j, q, j0, dens, dtype):
+    """Periodic extension (Sec. 3.2, Prop. 4.2 "per") through the generic and wave kernels."""
+    nu = Symlet(-nu) if nu < 0 else nu
+    cfg = op.Config(nu, j, q, j0, per=True)
+    seed = 9000 + 100 * int(nu) + 10 * j + q + dim
+    if dim == 1:
+        x = inputs.coefficients_1d(j, j0, seed)
+        omega = None if dens is None else inputs.uniform_omega(cfg.N, dens, seed + 1)
+        m = cfg.N if omega is None else omega.size
+        yv = inputs.sample_vector(m, seed + 2)
+        A = op.matrix_1d(cfg)
+        y_ref, x_ref = op.forward_1d(A, x, omega), op.adjoint_1d(A, yv, omega)
+    else:
+        x = inputs.coefficients_2d(j, j0, seed)
+        omega = None if dens is None else inputs.multilevel_omega_2d(cfg.N, dens, seed + 1, core=4)
+        m = cfg.N ** 2 if omega is None else omega.size
+        yv = inputs.sample_vector(m, seed + 2)
+        blocks = op.Blocks2D(cfg)
+        y_ref = op.forward_2d_full(blocks, x, omega).reshape(-1)
+        x_ref = op.adjoint_2d_full(blocks, yv, omega)
+    y, xa = gpu_pair(dim, nu, j, q, j0, dtype, x, omega, yv, boundary="per")
+    assert rel(y, y_ref) < TOL[dtype], rel(y, y_ref)
+    assert rel(xa, x_ref) < TOL[dtype], rel(xa, x_ref)
+
+
+CASES_TENSOR = [
+    # nu, j, q, j0, omega density, boundary
+    (2, 4, 1, 2, None, "bd"), (4, 6, 2, 3, 0.3, "bd"), (3, 5, 1, 3, 0.25, "per"),   # generic line kernels
+    (4, 8, 1, 3, 0.2, "bd"), (8, 9, 1, 4, 0.15, "bd"), (2, 10, 1, 2, 0.2, "per"),  # wave line kernels
+    (6, 7, 2, 4, None, "bd"),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("nu,j,q,j0,dens,boundary", CASES_TENSOR)
+def test_parity_tensor_basis(nu, j, q, j0, dens, boundary, dtype):
+    """Tensor-product 2D basis (Kronecker product of the 1D section, Sec. 5)."""
+    cfg = op.Config(nu, j, q, j0, per=boundary == "per", tensor=True)
+    seed = 11000 + 100 * nu + 10 * j + q
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((cfg.M, cfg.M))
+    omega = None if dens is None else inputs.multilevel_omega_2d(cfg.N, dens, seed + 1, core=4)
+    m = cfg.N ** 2 if omega is None else omega.size
+    yv = inputs.sample_vector(m, seed + 2)
+    A1 = op.matrix_1d(cfg)
+    y_ref = op.forward_2d_tensor(A1, x, omega).reshape(-1)
+    x_ref = op.adjoint_2d_tensor(A1, yv, omega)
+    y, xa = gpu_pair(2, nu, j, q, j0, dtype, x, omega, yv, boundary=boundary, basis2d="tensor")
+    assert rel(y, y_ref) < TOL[dtype], rel(y, y_ref)
+    assert rel(xa, x_ref) < TOL[dtype], rel(xa, x_ref)
