@@ -264,6 +264,7 @@ CASES_2D_WAVE = [
     (3, 8, 1, 3, 0.2), (8, 8, 2, 4, 0.15), (6, 9, 1, 4, 0.2), (8, 9, 1, 4, None),
     (3, 7, 4, 3, 0.2),  # q = 4: sixteen phase waves per row workgroup
     (5, 8, 1, 4, 0.2), (7, 9, 2, 4, None), (5, 10, 1, 4, 0.25), (7, 7, 1, 4, 0.3),  # odd orders 5 and 7
+    (4, 11, 1, 3, 0.1), (2, 11, 1, 2, None),  # 2048-value lines: two phase groups in the adjoint column pass (FP32)
 ]
 
 
