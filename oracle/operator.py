@@ -23,10 +23,17 @@ Tensor-product 2D basis (the alternative to the isotropic one): the
 functions r_{c1} (x) r_{c2} of the 1D multiscale basis, so the section is the
 Kronecker product of the 1D section with itself (forward_2d_tensor).
 
+d dimensions and unequal sides (forward_nd_* / adjoint_nd_*): the same
+splitting with one 1D section per axis (mode products), in the tensor basis
+(any sides) or the isotropic one (equal sides, octant layout).
+
 Parity status: pinned (Haar closed form, norm bound, polynomial
 reproduction, Fubini against the dense Kronecker matrix, Table 1 for DB2;
 the tensor basis against the Kronecker product of 1D basis columns and by
-the singular values it shares with the isotropic basis of the same space).
+the singular values it shares with the isotropic basis of the same space;
+the d-dimensional functions against the 2D ones at d = 2, against columns
+built one by one from 1D basis functions at d = 3 and for unequal sides,
+separable inputs, and shared singular values).
 """
 import numpy as np
 import scipy.sparse as sp
@@ -319,3 +326,125 @@ def adjoint_entries_1d(cfg, y, omega, cs, C=None):
         out.append(np.dot(H @ col.data, y))
     return np.array(out)
 
+
+
+# ---------------------------------------------------------------------------
+# d dimensions and unequal sides.  Sec. 5 splits the 2D inner products into
+# 1D ones (Fubini); the same splitting holds for any d-fold tensor product.
+# Sampling functions w_{n_0} (x) ... (x) w_{n_{d-1}}; y lists alpha in
+# increasing linear index over the row-major N_0 x ... x N_{d-1} array.
+# Two reconstruction bases:
+# * tensor: the products r_{c_0} (x) ... (x) r_{c_{d-1}} of the 1D multiscale
+#   bases of the axes, whose sizes may differ (M_a = 2^{j_a}, N_a = 2^{j_a+q}).
+#   The section is the Kronecker product of the 1D sections, applied here one
+#   axis at a time (mode products);
+# * isotropic (equal sides): the d-dimensional analogue of the quadtree
+#   layout.  The coarse cube [0, 2^{j0})^d holds phi_{j0} (x) ... (x) phi_{j0};
+#   at each level k the cube [0, 2^{k+1})^d holds 2^d - 1 detail blocks, one
+#   per nonzero beta in {0, 1}^d, at offset 2^k along the axes with
+#   beta_a = 1, holding psi_k along those axes and phi_k along the others.
+
+def mode_apply(mats, X):
+    """Y = X x_0 mats[0] x_1 mats[1] ... : matrix mats[a] acts on axis a of X."""
+    Y = np.asarray(X, dtype=np.float64)
+    for a, A in enumerate(mats):
+        Y = np.moveaxis(np.tensordot(A, Y, axes=([1], [a])), 0, a)
+    return Y
+
+
+def _scatter_samples(shape, y, omega):
+    """The array of the given shape holding y at the linear indices omega (zero elsewhere)."""
+    size = int(np.prod(shape))
+    if omega is None:
+        return np.asarray(y, dtype=np.float64).reshape(shape)
+    Y = np.zeros(size)
+    Y[np.asarray(omega)] = y
+    return Y.reshape(shape)
+
+
+def forward_nd_tensor(mats, X, omega=None):
+    """alpha = X with the 1D section mats[a] (N_a x M_a) applied along each axis a."""
+    alpha = mode_apply(mats, X)
+    return alpha if omega is None else alpha.ravel()[np.asarray(omega)]
+
+
+def adjoint_nd_tensor(mats, y, omega=None):
+    """X = Y with mats[a]^T applied along each axis, Y holding y on omega."""
+    Y = _scatter_samples(tuple(A.shape[0] for A in mats), y, omega)
+    return mode_apply([A.T for A in mats], Y)
+
+
+def octant_bands(cfg, d):
+    """Yield (slices, kinds, level) of the isotropic d-dimensional basis."""
+    import itertools
+    s0 = slice(0, 1 << cfg.j0)
+    yield (s0,) * d, ("phi",) * d, cfg.j0
+    for k in range(cfg.j0, cfg.j):
+        lo, hi = slice(0, 1 << k), slice(1 << k, 1 << (k + 1))
+        for beta in itertools.product((0, 1), repeat=d):
+            if any(beta):
+                yield tuple(hi if b else lo for b in beta), tuple("psi" if b else "phi" for b in beta), k
+
+
+def forward_nd_iso(blocks, X, omega=None):
+    """Isotropic basis: alpha = sum over blocks of X_block with the 1D blocks
+    A_phi[k] / A_psi[k] (Blocks2D, all N rows) applied along each axis."""
+    X = np.asarray(X, dtype=np.float64)
+    d, N = X.ndim, blocks.cfg.N
+    alpha = np.zeros((N,) * d)
+    for sl, kinds, k in octant_bands(blocks.cfg, d):
+        alpha += mode_apply([blocks.phi[k] if kd == "phi" else blocks.psi[k] for kd in kinds], X[sl])
+    return alpha if omega is None else alpha.ravel()[np.asarray(omega)]
+
+
+def adjoint_nd_iso(blocks, y, d, omega=None):
+    """Its transpose: the M^d array of coefficients from y on omega."""
+    cfg = blocks.cfg
+    Y = _scatter_samples((cfg.N,) * d, y, omega)
+    X = np.zeros((cfg.M,) * d)
+    for sl, kinds, k in octant_bands(cfg, d):
+        X[sl] += mode_apply([(blocks.phi[k] if kd == "phi" else blocks.psi[k]).T for kd in kinds], Y)
+    return X
+
+
+def octree_functions(cfg, cs):
+    """For isotropic position cs = (c_0, ..., c_{d-1}): the 1D function (kind, level, idx) per axis."""
+    j0 = cfg.j0
+    if all(c < (1 << j0) for c in cs):
+        return [("phi", j0, int(c)) for c in cs]
+    k = max(int(c).bit_length() for c in cs) - 1
+    return [("phi", k, int(c)) if c < (1 << k) else ("psi", k, int(c) - (1 << k)) for c in cs]
+
+
+def dense_nd(cfgs, tensor, columns=None):
+    """Dense (prod N_a) x (prod M_a) matrix, column by column as Kronecker products
+    of the 1D Walsh columns of the basis functions (tiny sizes only).  cfgs: one
+    Config per axis (equal ones for the isotropic basis); columns: the linear
+    coefficient indices to build (all by default), in that order."""
+    cols = {}
+
+    def col(a, kind, level, idx):
+        key = (a, kind, level, idx)
+        if key not in cols:
+            cols[key] = walsh_column(cfgs[a], kind, level, idx)
+        return cols[key]
+
+    shape_m = [c.M for c in cfgs]
+    if columns is None:
+        columns = range(int(np.prod(shape_m)))
+    columns = list(columns)
+    A = np.zeros((int(np.prod([c.N for c in cfgs])), len(columns)))
+    for ci, flat in enumerate(columns):
+        cs = np.unravel_index(int(flat), shape_m)
+        if tensor:
+            fs = []
+            for a, c in enumerate(cs):
+                level, kind, idx = basis.position_1d(c, cfgs[a].j0)
+                fs.append((kind, level, idx))
+        else:
+            fs = octree_functions(cfgs[0], cs)
+        v = np.ones(1)
+        for a, f in enumerate(fs):
+            v = np.kron(v, col(a, *f))
+        A[:, ci] = v
+    return A
