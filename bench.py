@@ -341,9 +341,10 @@ def small_configs_leg(torch, steps, outputs=None):
 def variants_leg(torch, steps):
     """Pairs/s of the widened operators on the roofline workload's shape and of
     shapes served by the generic kernels: symlets, the periodic extension and
-    the tensor-product basis at 2048^2 db8 q = 2 (12.5 % Omega), and the
-    generic line kernels at 1024^2 db10 q = 1 and 4096^2 db4 q = 1 (10 % Omega);
-    all FP32."""
+    the tensor-product basis at 2048^2 db8 q = 2 (12.5 % Omega), the generic
+    line kernels at 1024^2 db10 q = 1 and 4096^2 db4 q = 1 (10 % Omega), and
+    the per-axis path: 64^3 db4 q = 1 (isotropic, 12.5 % Omega) and unequal
+    sides 2048 x 256 db4 q = 1 (tensor basis, 12.5 % Omega); all FP32."""
     from paper_2106_00554_amd.operator import Wh2Wav
     from tests import inputs
 
@@ -357,9 +358,14 @@ def variants_leg(torch, steps):
         N = 1 << (j + q)
         cases.append((f"db{nu}_{1 << j}sq_generic", dict(nu=nu, j=j, q=q, j0=j0),
                       inputs.coefficients_2d(j, j0, 700 + j), inputs.multilevel_omega_2d(N, dens, 701 + j)))
+    cases.append(("db4_64cube_3d", dict(dim=3, nu=4, j=6, q=1, j0=3), inputs.coefficients_nd((64, 64, 64), 760),
+                  inputs.uniform_omega(128 ** 3, 0.125, 761)))
+    cases.append(("db4_2048x256_tensor", dict(nu=4, j=11, q=1, j0=3, basis2d="tensor", j_axes=(11, 8)),
+                  inputs.coefficients_nd((2048, 256), 770), inputs.uniform_omega(4096 * 512, 0.125, 771)))
     out = {}
     for label, kw, Xc, om in cases:
-        opr = Wh2Wav(2, kw.pop("j"), kw.pop("q"), kw.pop("nu"), kw.pop("j0"), torch.float32, om, **kw)
+        dim = kw.pop("dim", 2)
+        opr = Wh2Wav(dim, kw.pop("j"), kw.pop("q"), kw.pop("nu"), kw.pop("j0"), torch.float32, om, **kw)
         x = torch.tensor(Xc, dtype=torch.float32, device="cuda")
         y = torch.empty(opr.m, dtype=torch.float32, device="cuda")
         xa = torch.empty_like(x)
@@ -371,7 +377,8 @@ def variants_leg(torch, steps):
         for _ in range(3):
             pair()
         t = timed(pair, max(5, steps // 2), torch)
-        out[label] = {"M": opr.M, "q": opr.q, "m": opr.m, "us_per_pair": t * 1e6, "pairs_per_s": 1.0 / t}
+        out[label] = {"x_shape": list(opr.x_shape), "q": opr.q, "m": opr.m, "us_per_pair": t * 1e6,
+                      "pairs_per_s": 1.0 / t}
         del opr, x, y, xa
         torch.cuda.empty_cache()
     return out

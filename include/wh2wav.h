@@ -13,7 +13,11 @@
  * Daubechies basis C_{psi,j} on [0,1] with vanishing-moment-preserving
  * boundary functions (Sec. 3.2).  In one dimension M = 2^j and N = 2^{j+q};
  * in two dimensions A acts on M x M coefficient arrays and produces N x N
- * Walsh samples (Sec. 5, Algorithm 2), so the section is N^2 x M^2.  The
+ * Walsh samples (Sec. 5, Algorithm 2), so the section is N^2 x M^2.  Sec. 5
+ * notes that the splitting holds for any d-fold tensor product: in three
+ * dimensions A maps M^3 coefficients to N^3 samples.  With the tensor basis
+ * the axes may have their own sizes M_a = 2^{j_a}, N_a = 2^{j_a + q} (the
+ * 1D section of each axis; Sec. 4 reaches other sizes by padding).  The
  * product is computed in O(N log N) (Algorithm 1 and Lemma 3.3) without
  * forming A: inverse DWT C_{psi,j} -> B_{phi,j} (Remark on compressive
  * sensing), a product with O(2^q) tables of Walsh coefficients of the
@@ -30,9 +34,15 @@
  *       [2^k,2^{k+1}) x [0,2^k) (psi (x) phi), [2^k,2^{k+1})^2 (psi (x) psi);
  *       the first array index belongs to the first coordinate.  With
  *       basis2d = WH2WAV_TENSOR, x[c1][c2] is the coefficient of
- *       r_{c1} (x) r_{c2}, c1 and c2 in 1D C_{psi,j} order.
+ *       r_{c1} (x) r_{c2}, c1 and c2 in 1D C_{psi,j} order (M_1 x M_2).
+ *       3D: M_1 x M_2 x M_3 row-major.  Isotropic (equal sides): the scaling
+ *       block [0, 2^{J0})^3 and, per level k, the 7 blocks at offset 2^k
+ *       along the axes a with beta_a = 1 (beta in {0,1}^3, not all zero),
+ *       holding psi along those axes and phi along the others.  Tensor:
+ *       x[c1][c2][c3] is the coefficient of r_{c1} (x) r_{c2} (x) r_{c3}.
  *   y   m = |Omega| values in increasing order of the sequency index n
- *       (1D) or of n1 * N + n2 (2D), n1 the first coordinate.
+ *       (1D) or of the row-major linear index of (n1, ..., n_d) over the
+ *       N_1 x ... x N_d array (2D, 3D), n1 the first coordinate.
  *   Element type is float or double as chosen by the plan (dtype).
  *
  * Ownership and errors
@@ -81,17 +91,18 @@ enum {
                                          function crossing an end is periodised with period 1 */
 };
 
-/* 2D wavelet basis.  ISOTROPIC: at each level the scaling block splits into
- * phi (x) psi, psi (x) phi, psi (x) psi (the quadtree layout below).  TENSOR:
- * the products r_{c1} (x) r_{c2} of the 1D basis C_{psi,j}, x[c1][c2] in 1D
+/* Wavelet basis in 2D and 3D.  ISOTROPIC: at each level the scaling block
+ * splits into phi (x) psi, psi (x) phi, psi (x) psi (the quadtree layout
+ * below; in 3D the 7 products with at least one psi).  TENSOR: the products
+ * r_{c1} (x) r_{c2} (x) ... of the 1D bases C_{psi,j_a} of the axes, x in 1D
  * order along each index; by Fubini (Sec. 5) its section is the Kronecker
- * product of the 1D section with itself. */
+ * product of the 1D sections of the axes. */
 enum { WH2WAV_ISOTROPIC = 0, WH2WAV_TENSOR = 1 };
 
 typedef struct wh2wav_plan_s* wh2wav_plan_t;
 
 typedef struct {
-  int dim;              /* 1 or 2 */
+  int dim;              /* 1, 2 or 3 */
   int j;                /* M = 2^j per dimension, j0 <= j */
   int q;                /* N = 2^{j+q} per dimension, q >= 1 (Sec. 4: q > 0) */
   int j0;               /* coarsest level J0: 2^{J0} >= 2 nu for nu >= 2 (Sec. 3.2) */
@@ -99,10 +110,12 @@ typedef struct {
   int family;           /* WH2WAV_DB or WH2WAV_SYM */
   int boundary;         /* WH2WAV_BD or WH2WAV_PER */
   int dtype;            /* WH2WAV_F32 or WH2WAV_F64 */
-  int64_t m;            /* |Omega|; with omega == NULL, m must equal N^dim (all samples) */
+  int64_t m;            /* |Omega|; with omega == NULL, m must equal N_1 ... N_dim (all samples) */
   const int64_t* omega; /* host array of m strictly increasing linear indices in
-                           [0, N^dim), or NULL; copied during wh2wav_plan */
-  int basis2d;          /* 2D only: WH2WAV_ISOTROPIC (0) or WH2WAV_TENSOR (1) */
+                           [0, N_1 ... N_dim), or NULL; copied during wh2wav_plan */
+  int basis2d;          /* dim 2 and 3: WH2WAV_ISOTROPIC (0) or WH2WAV_TENSOR (1) */
+  int j_axes[3];        /* dim 2 and 3: j_a of axis a (M_a = 2^{j_a}, N_a = 2^{j_a + q}); 0 takes j;
+                           entries at a >= dim must be 0; unequal sides need WH2WAV_TENSOR */
 } wh2wav_desc;
 
 /* Build a plan: host-side tables (Sec. 3.2, Sec. 4.1, Prop. 4.2) and their
@@ -112,10 +125,10 @@ int wh2wav_plan(const wh2wav_desc* desc, wh2wav_plan_t* out);
 /* Bytes of device workspace a forward or adjoint call needs (may be 0). */
 int wh2wav_workspace_size(wh2wav_plan_t plan, size_t* bytes);
 
-/* y = P_Omega A x.  x: M^dim elements, y: m elements (device pointers). */
+/* y = P_Omega A x.  x: M_1 ... M_dim elements, y: m elements (device pointers). */
 int wh2wav_forward(wh2wav_plan_t plan, const void* x, void* y, void* ws, void* stream);
 
-/* x = A^T P_Omega^T y.  y: m elements, x: M^dim elements (device pointers). */
+/* x = A^T P_Omega^T y.  y: m elements, x: M_1 ... M_dim elements (device pointers). */
 int wh2wav_adjoint(wh2wav_plan_t plan, const void* y, void* x, void* ws, void* stream);
 
 /* Staged execution, for callers that time or interleave the stages (for

@@ -54,6 +54,7 @@ class wh2wav_desc(ctypes.Structure):
         ("m", ctypes.c_int64),
         ("omega", ctypes.POINTER(ctypes.c_int64)),
         ("basis2d", ctypes.c_int),
+        ("j_axes", ctypes.c_int * 3),
     ]
 
 

@@ -43,6 +43,7 @@ bool handle_live(const void* h);
 struct PlanShape {
   int dim, j, q, nu, dtype;
   int64_t M, N, m;
+  int64_t xlen, ntot;  // coefficients (M_1 ... M_dim) and Walsh samples (N_1 ... N_dim)
 };
 PlanShape plan_shape(wh2wav_plan_t p);
 

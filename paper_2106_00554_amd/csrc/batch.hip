@@ -74,7 +74,7 @@ int fail(int code, const std::string& msg) { return wh2wav::set_error(code, msg)
   } while (0)
 
 double cost_of(const wh2wav::PlanShape& s) {
-  const double n = s.dim == 1 ? double(s.N) : double(s.N) * double(s.N);
+  const double n = double(s.ntot);
   const double e = s.dtype == WH2WAV_F64 ? 2.0 : 1.0;
   return n * e;
 }
@@ -142,7 +142,7 @@ int check_ptrs(const wh2wav_batch_s* b, int dir, const void* const* in, void* co
   if (!ws && b->ws_total) return fail(WH2WAV_EINVAL, "workspace is NULL");
   for (size_t i = 0; i < b->plans.size(); ++i) {
     const auto& s = b->shape[i];
-    const int64_t xlen = s.dim == 1 ? s.M : s.M * s.M;
+    const int64_t xlen = s.xlen;
     const int64_t inlen = dir == 0 ? xlen : s.m, outlen = dir == 0 ? s.m : xlen;
     if ((inlen && !in[i]) || (outlen && !out[i]))
       return fail(WH2WAV_EINVAL, "instance " + std::to_string(i) + ": NULL input or output");

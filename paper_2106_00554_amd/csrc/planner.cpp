@@ -749,7 +749,7 @@ int build_host_plan(const wh2wav_desc* d, HostPlan* P, std::string* err) {
     *err = "descriptor is NULL";
     return WH2WAV_EINVAL;
   }
-  if (d->dim != 1 && d->dim != 2) return *err = "dim must be 1 or 2", WH2WAV_EINVAL;
+  if (d->dim < 1 || d->dim > 3) return *err = "dim must be 1, 2 or 3", WH2WAV_EINVAL;
   if (d->nu < 1 || d->nu > 10) return *err = "nu must be in [1, 10]", WH2WAV_EINVAL;
   if (d->q < 1) return *err = "q must be >= 1", WH2WAV_EINVAL;
   if (d->j0 < 0 || d->j < d->j0) return *err = "need 0 <= j0 <= j", WH2WAV_EINVAL;
@@ -760,19 +760,66 @@ int build_host_plan(const wh2wav_desc* d, HostPlan* P, std::string* err) {
   if (d->boundary != WH2WAV_BD && d->boundary != WH2WAV_PER)
     return *err = "boundary must be WH2WAV_BD or WH2WAV_PER", WH2WAV_EINVAL;
   if (d->dtype != WH2WAV_F32 && d->dtype != WH2WAV_F64) return *err = "dtype must be F32 or F64", WH2WAV_EINVAL;
+  if (d->basis2d != WH2WAV_ISOTROPIC && d->basis2d != WH2WAV_TENSOR)
+    return *err = "basis2d must be WH2WAV_ISOTROPIC or WH2WAV_TENSOR", WH2WAV_EINVAL;
+  // per-axis sizes: j_axes[a] for a < dim (0 takes j), zero beyond dim
+  bool unequal = false;
+  for (int a = 0; a < 3; ++a) {
+    const int v = d->j_axes[a];
+    if (a >= d->dim || d->dim == 1) {
+      if (v != 0 && !(d->dim == 1 && a == 0 && v == d->j))
+        return *err = "j_axes entries beyond dim (and all of them in 1D) must be 0", WH2WAV_EINVAL;
+      continue;
+    }
+    if (v < 0) return *err = "j_axes entries must be >= 0", WH2WAV_EINVAL;
+    const int ja = v ? v : d->j;
+    if (ja < d->j0) return *err = "need j0 <= j_axes[a] on every axis", WH2WAV_EINVAL;
+    P->ja[a] = ja;
+    unequal = unequal || ja != d->j;
+  }
+  if (unequal && d->basis2d != WH2WAV_TENSOR)
+    return *err = "unequal sides need the tensor basis (WH2WAV_TENSOR)", WH2WAV_EINVAL;
   const int J = d->j + d->q;
   if ((d->dim == 1 && J > 28) || (d->dim == 2 && J > 15))
     return *err = "size exceeds the supported range", WH2WAV_EUNSUPPORTED;
+  int64_t total = 1;
+  if (d->dim >= 2) {
+    int jsum = 0;
+    for (int a = 0; a < d->dim; ++a) {
+      if (P->ja[a] + d->q > 15) return *err = "size exceeds the supported range", WH2WAV_EUNSUPPORTED;
+      jsum += P->ja[a] + d->q;
+    }
+    if (jsum > 32) return *err = "size exceeds the supported range (N_1 ... N_dim > 2^32)", WH2WAV_EUNSUPPORTED;
+  }
   P->dim = d->dim, P->j = d->j, P->q = d->q, P->j0 = d->j0, P->nu = d->nu, P->dtype = d->dtype;
   P->M = (int64_t)1 << d->j;
   P->N = (int64_t)1 << J;
-  if (d->basis2d != WH2WAV_ISOTROPIC && d->basis2d != WH2WAV_TENSOR)
-    return *err = "basis2d must be WH2WAV_ISOTROPIC or WH2WAV_TENSOR", WH2WAV_EINVAL;
   P->family = d->family;
   P->per = d->boundary == WH2WAV_PER;
-  P->tensor = d->dim == 2 && d->basis2d == WH2WAV_TENSOR;
+  P->tensor = d->dim >= 2 && d->basis2d == WH2WAV_TENSOR;
+  P->nd = d->dim == 3 || unequal;
   int rc = build_tables(d->family, d->nu, d->q, d->j, P, err);
   if (rc != WH2WAV_OK) return rc;
+  if (P->nd) {
+    for (int a = 0; a < d->dim; ++a) {
+      P->Ma[a] = (int64_t)1 << P->ja[a];
+      P->Na[a] = (int64_t)1 << (P->ja[a] + d->q);
+      if (P->ja[a] == d->j) {
+        P->tabT_ax[a] = P->tabT, P->tabBL_ax[a] = P->tabBL, P->tabBR_ax[a] = P->tabBR;
+      } else {
+        HostPlan axis;
+        rc = build_tables(d->family, d->nu, d->q, P->ja[a], &axis, err);
+        if (rc != WH2WAV_OK) return rc;
+        P->tabT_ax[a] = std::move(axis.tabT);
+        P->tabBL_ax[a] = std::move(axis.tabBL);
+        P->tabBR_ax[a] = std::move(axis.tabBR);
+      }
+      if (P->per) {
+        std::fill(P->tabBL_ax[a].begin(), P->tabBL_ax[a].end(), 0.0);
+        std::fill(P->tabBR_ax[a].begin(), P->tabBR_ax[a].end(), 0.0);
+      }
+    }
+  }
   if (P->per) {
     // periodic extension: every function is an interior one, periodised
     std::fill(P->tabBL.begin(), P->tabBL.end(), 0.0);
@@ -781,13 +828,19 @@ int build_host_plan(const wh2wav_desc* d, HostPlan* P, std::string* err) {
     std::fill(P->synR.begin(), P->synR.end(), 0.0);
   }
 
-  const int64_t total = d->dim == 1 ? P->N : P->N * P->N;
+  if (P->nd) {
+    for (int a = 0; a < d->dim; ++a) total *= P->Na[a];
+    P->row_len = P->Na[d->dim - 1];
+  } else {
+    total = d->dim == 1 ? P->N : P->N * P->N;
+    P->row_len = P->N;
+  }
   if (d->m < 0 || d->m > total) return *err = "m out of range", WH2WAV_EINVAL;
   P->m = d->m;
-  P->rows = d->dim == 1 ? 1 : P->N;
-  P->words_per_row = (P->N + 31) / 32;
+  P->rows = d->dim == 1 ? 1 : total / P->row_len;
+  P->words_per_row = (P->row_len + 31) / 32;
   if (!d->omega) {
-    if (d->m != total) return *err = "omega is NULL but m != N^dim", WH2WAV_EINVAL;
+    if (d->m != total) return *err = "omega is NULL but m != N_1 ... N_dim", WH2WAV_EINVAL;
     P->full_omega = true;
   } else {
     bool full = d->m == total;
@@ -805,19 +858,19 @@ int build_host_plan(const wh2wav_desc* d, HostPlan* P, std::string* err) {
     P->mask.assign((size_t)(P->rows * P->words_per_row), 0u);
     for (int64_t i = 0; i < d->m; ++i) {
       int64_t v = d->omega[i];
-      int64_t r = d->dim == 1 ? 0 : v / P->N, c = d->dim == 1 ? v : v % P->N;
+      int64_t r = d->dim == 1 ? 0 : v / P->row_len, c = d->dim == 1 ? v : v % P->row_len;
       P->mask[(size_t)(r * P->words_per_row + c / 32)] |= 1u << (c % 32);
       P->row_ptr[r + 1]++;
     }
   } else {
-    for (int64_t r = 0; r < P->rows; ++r) P->row_ptr[r + 1] = P->N;
+    for (int64_t r = 0; r < P->rows; ++r) P->row_ptr[r + 1] = P->row_len;
   }
   for (int64_t r = 0; r < P->rows; ++r) P->row_ptr[r + 1] += P->row_ptr[r];
   P->pos16.clear();
   P->seg_ptr.clear();
   // 2D, and 1D lines of at most 2048 values (one wave per phase line): the
   // sample list per (row, phase); 1D has the single row n1 = 0
-  if ((d->dim == 2 || d->j <= 11) && !P->full_omega && P->M <= 65536) {
+  if (!P->nd && (d->dim == 2 || d->j <= 11) && !P->full_omega && P->M <= 65536) {
     const int64_t Q = P->Q, M = P->M, nrows = d->dim == 2 ? P->N : 1;
     P->seg_ptr.assign((size_t)(nrows * Q + 1), 0);
     P->pos16.resize((size_t)d->m);

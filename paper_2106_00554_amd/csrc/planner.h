@@ -26,9 +26,16 @@ struct HostPlan {
   int dim = 1, j = 0, q = 1, j0 = 0, nu = 2, dtype = WH2WAV_F64;
   int family = WH2WAV_DB;
   bool per = false;          // periodic extension (Sec. 3.2): no boundary functions; bands and blocks are zero
-  bool tensor = false;       // 2D tensor-product basis (products of 1D basis functions)
+  bool tensor = false;       // tensor-product basis (products of 1D basis functions), 2D and 3D
   int64_t M = 0, N = 0;      // per dimension: M = 2^j, N = 2^{j+q}
   int Q = 2;                 // 2^q phases
+  // Three dimensions or unequal sides: the per-axis path.  Axis a has
+  // M_a = 2^{ja[a]}, N_a = 2^{ja[a] + q} (entries at a >= dim are 1), and its
+  // own interior and band tables (the 2^{-j_a/2} factor differs per axis).
+  bool nd = false;
+  int ja[3] = {0, 0, 0};
+  int64_t Ma[3] = {1, 1, 1}, Na[3] = {1, 1, 1};
+  std::vector<double> tabT_ax[3], tabBL_ax[3], tabBR_ax[3];
 
   std::vector<double> h, g;  // 2 nu taps each, index c + nu - 1 for c in [-nu+1, nu]
   // T[(l + nu - 1) * Q + s], l in [-nu+1, nu-1]
@@ -47,8 +54,9 @@ struct HostPlan {
 
   bool full_omega = true;
   int64_t m = 0;
-  int64_t rows = 1;          // 1 (1D) or N (2D)
-  int64_t words_per_row = 0; // ceil(N / 32)
+  int64_t rows = 1;          // 1 (1D), N (2D) or N_1 ... N_{dim-1}: all but the last axis
+  int64_t row_len = 0;       // samples per row: N (1D, 2D) or N_dim
+  int64_t words_per_row = 0; // ceil(row_len / 32)
   std::vector<uint32_t> mask;        // rows * words_per_row
   std::vector<int64_t> row_ptr;      // rows + 1
   // 2D sample list for the line kernels (only when Omega is not full).  A

@@ -28,6 +28,7 @@
 // last in the adjoint.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -100,23 +101,17 @@ __device__ __forceinline__ uint32_t sequency_of(uint32_t k, uint32_t s, int j) {
 }
 
 // ------------------------------------------------------------------ IDWT
-// One level of the inverse DWT along lines: [a_k | d_k] (2^k + 2^k values)
-// -> scaling coefficients at level k+1 (2^{k+1} values).  Interior columns
-// use the filters (phi_{k,m} = sum_c h_c phi_{k+1,2m+c}); boundary columns
-// use the synthesis bands.  One thread per output value.
+// One level of the inverse DWT along a line: [a_k | d_k] (2^k + 2^k values,
+// element stride es from src) -> output n of the scaling coefficients at
+// level k+1 (2^{k+1} values).  Interior columns use the filters
+// (phi_{k,m} = sum_c h_c phi_{k+1,2m+c}); boundary columns use the synthesis
+// bands.
 template <typename T>
-__global__ void k_synth(const T* __restrict__ in, T* __restrict__ out, int64_t lines,
-                        int64_t line_stride, int64_t elem_stride, int k, int line_fast,
-                        Tables<T> t) {
+__device__ T synth_value(const T* __restrict__ src, int64_t es, int64_t n, int k, const Tables<T>& t) {
   const int64_t half = int64_t(1) << k, size = 2 * half;
-  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (gid >= lines * size) return;
-  const int64_t line = line_fast ? gid % lines : gid / size;
-  const int64_t n = line_fast ? gid / lines : gid % size;
-  const T* src = in + line * line_stride;
   const int nu = t.nu;
-  auto A = [&](int64_t m) { return src[m * elem_stride]; };
-  auto D = [&](int64_t m) { return src[(half + m) * elem_stride]; };
+  auto A = [&](int64_t m) { return src[m * es]; };
+  auto D = [&](int64_t m) { return src[(half + m) * es]; };
   T acc = 0;
   const int64_t right_first = half - nu > nu ? half - nu : nu;  // first right-boundary position
   int64_t mlo = (n - nu + 1) / 2;  // ceil((n - nu) / 2) for n - nu >= -1
@@ -141,20 +136,14 @@ __global__ void k_synth(const T* __restrict__ in, T* __restrict__ out, int64_t l
       acc += t.synR[i * 2 * nu + cc] * A(pos) + t.synR[i * 2 * nu + nu + cc] * D(pos);
     }
   }
-  out[line * line_stride + n * elem_stride] = acc;
+  return acc;
 }
 
-// Transpose of k_synth (one level of the forward DWT).
+// Transpose of synth_value (one level of the forward DWT): output o of
+// [a_k | d_k] from the 2^{k+1} values of the line.
 template <typename T>
-__global__ void k_analysis(const T* __restrict__ in, T* __restrict__ out, int64_t lines,
-                           int64_t line_stride, int64_t elem_stride, int k, int line_fast,
-                           Tables<T> t) {
+__device__ T analysis_value(const T* __restrict__ src, int64_t es, int64_t o, int k, const Tables<T>& t) {
   const int64_t half = int64_t(1) << k, size = 2 * half;
-  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (gid >= lines * size) return;
-  const int64_t line = line_fast ? gid % lines : gid / size;
-  const int64_t o = line_fast ? gid / lines : gid % size;
-  const T* src = in + line * line_stride;
   const int nu = t.nu;
   const int kind = o >= half ? 1 : 0;
   const int64_t m = o - kind * half;
@@ -163,59 +152,92 @@ __global__ void k_analysis(const T* __restrict__ in, T* __restrict__ out, int64_
   T acc = 0;
   if (m >= nu && m < right_first) {
     const T* taps = kind ? t.g : t.h;
-    for (int c = -nu + 1; c <= nu; ++c) acc += taps[c + nu - 1] * src[(2 * m + c) * elem_stride];
+    for (int c = -nu + 1; c <= nu; ++c) acc += taps[c + nu - 1] * src[(2 * m + c) * es];
   } else if (m < nu) {
-    for (int r = 0; r < rows && r < size; ++r) acc += t.synL[r * 2 * nu + kind * nu + m] * src[r * elem_stride];
+    for (int r = 0; r < rows && r < size; ++r) acc += t.synL[r * 2 * nu + kind * nu + m] * src[r * es];
   } else {
     const int64_t cc = half - 1 - m;
-    for (int r = 0; r < rows; ++r)
-      acc += t.synR[r * 2 * nu + kind * nu + cc] * src[(size - rows + r) * elem_stride];
+    for (int r = 0; r < rows; ++r) acc += t.synR[r * 2 * nu + kind * nu + cc] * src[(size - rows + r) * es];
   }
-  out[line * line_stride + o * elem_stride] = acc;
+  return acc;
 }
 
 // One level of the inverse DWT of the periodic extension (Sec. 3.2): every
 // function is periodised, so output n of a line of 2^{k+1} values is
 // sum_c h_c a_m + g_c d_m over the m with n - 2m = c, m taken modulo 2^k.
-// line_fast: consecutive threads take consecutive lines (strided lines).
 template <typename T>
-__global__ void k_synth_per(const T* __restrict__ in, T* __restrict__ out, int64_t lines,
-                            int64_t line_stride, int64_t elem_stride, int k, int line_fast, Tables<T> t) {
-  const int64_t half = int64_t(1) << k, size = 2 * half;
-  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (gid >= lines * size) return;
-  const int64_t line = line_fast ? gid % lines : gid / size;
-  const int64_t n = line_fast ? gid / lines : gid % size;
-  const T* src = in + line * line_stride;
+__device__ T synth_value_per(const T* __restrict__ src, int64_t es, int64_t n, int k, const Tables<T>& t) {
+  const int64_t half = int64_t(1) << k;
   const int nu = t.nu;
   T acc = 0;
   for (int c = -nu + 1; c <= nu; ++c) {
     const int64_t d = n - c;
     if (d & 1) continue;
     const int64_t m = (d >> 1) & (half - 1);  // modulo 2^k, also for d < 0
-    acc += src[m * elem_stride] * t.h[c + nu - 1] + src[(half + m) * elem_stride] * t.g[c + nu - 1];
+    acc += src[m * es] * t.h[c + nu - 1] + src[(half + m) * es] * t.g[c + nu - 1];
   }
-  out[line * line_stride + n * elem_stride] = acc;
+  return acc;
 }
 
-// Transpose of k_synth_per (one level of the periodic forward DWT):
-// a_m = sum_c h_c v_{(2m + c) mod 2^{k+1}}, d_m the same with g.
+// Its transpose: a_m = sum_c h_c v_{(2m + c) mod 2^{k+1}}, d_m the same with g.
 template <typename T>
-__global__ void k_analysis_per(const T* __restrict__ in, T* __restrict__ out, int64_t lines,
-                               int64_t line_stride, int64_t elem_stride, int k, int line_fast, Tables<T> t) {
+__device__ T analysis_value_per(const T* __restrict__ src, int64_t es, int64_t o, int k, const Tables<T>& t) {
   const int64_t half = int64_t(1) << k, size = 2 * half;
-  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (gid >= lines * size) return;
-  const int64_t line = line_fast ? gid % lines : gid / size;
-  const int64_t o = line_fast ? gid / lines : gid % size;
-  const T* src = in + line * line_stride;
   const int nu = t.nu;
   const int kind = o >= half ? 1 : 0;
   const int64_t m = o - kind * half;
   const T* taps = kind ? t.g : t.h;
   T acc = 0;
-  for (int c = -nu + 1; c <= nu; ++c) acc += taps[c + nu - 1] * src[((2 * m + c) & (size - 1)) * elem_stride];
-  out[line * line_stride + o * elem_stride] = acc;
+  for (int c = -nu + 1; c <= nu; ++c) acc += taps[c + nu - 1] * src[((2 * m + c) & (size - 1)) * es];
+  return acc;
+}
+
+// One level along lines (line_stride apart, element stride elem_stride), one
+// thread per output value; line_fast: consecutive threads take consecutive
+// lines (strided lines).  per: the periodic extension; analysis: the forward
+// DWT level instead of the inverse.
+template <typename T>
+__global__ void k_level(const T* __restrict__ in, T* __restrict__ out, int64_t lines, int64_t line_stride,
+                        int64_t elem_stride, int k, int line_fast, int analysis, Tables<T> t) {
+  const int64_t size = int64_t(2) << k;
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gid >= lines * size) return;
+  const int64_t line = line_fast ? gid % lines : gid / size;
+  const int64_t n = line_fast ? gid / lines : gid % size;
+  const T* src = in + line * line_stride;
+  T v;
+  if (analysis)
+    v = t.per ? analysis_value_per<T>(src, elem_stride, n, k, t) : analysis_value<T>(src, elem_stride, n, k, t);
+  else
+    v = t.per ? synth_value_per<T>(src, elem_stride, n, k, t) : synth_value<T>(src, elem_stride, n, k, t);
+  out[line * line_stride + n * elem_stride] = v;
+}
+
+// One level along `axis` of an s0 x s1 x s2 row-major array (unused axes of
+// extent 1): the elements whose coordinate along the axis is below 2^{k+1}
+// -- and, with `cube` (isotropic basis), whose every coordinate is -- take
+// one level of synthesis (analysis); every other element is copied.
+template <typename T>
+__global__ void k_level_nd(const T* __restrict__ in, T* __restrict__ out, int64_t s0, int64_t s1, int64_t s2,
+                           int axis, int k, int cube, int analysis, Tables<T> t) {
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gid >= s0 * s1 * s2) return;
+  const int64_t i2 = gid % s2, i1 = (gid / s2) % s1, i0 = gid / (s1 * s2);
+  const int64_t size = int64_t(2) << k;
+  const int64_t n = axis == 0 ? i0 : axis == 1 ? i1 : i2;
+  const int64_t es = axis == 0 ? s1 * s2 : axis == 1 ? s2 : 1;
+  const bool inside = n < size && (!cube || (i0 < size && i1 < size && i2 < size));
+  if (!inside) {
+    out[gid] = in[gid];
+    return;
+  }
+  const T* src = in + (gid - n * es);
+  T v;
+  if (analysis)
+    v = t.per ? analysis_value_per<T>(src, es, n, k, t) : analysis_value<T>(src, es, n, k, t);
+  else
+    v = t.per ? synth_value_per<T>(src, es, n, k, t) : synth_value<T>(src, es, n, k, t);
+  out[gid] = v;
 }
 
 // out = in^T for an n x n row-major array (any n), one element per thread.
@@ -341,15 +363,42 @@ __device__ void table_product_t(const T* R, T* xi, int M, int s, int tid, int nt
 }
 
 // ------------------------------------------------------------ line kernels
-// Forward G on lines.  gather == 0: write the N outputs of each line in natural
-// order r = s M + k at out + line * out_ls + r * out_es.  gather == 1: line
-// `line` is natural row r = line of the 2D intermediate (or the single 1D
-// line when dim1 != 0); its samples in Omega go to y.
+// Addressing of the lines of one launch: line l starts at
+// (l / inner) * os + (l % inner) * is, and its elements are es apart.
+struct LineMap {
+  int64_t inner, os, is, es;
+};
+__device__ __forceinline__ int64_t line_base(const LineMap& m, int64_t l) {
+  return (l / m.inner) * m.os + (l % m.inner) * m.is;
+}
+LineMap lines_at(int64_t ls, int64_t es) { return LineMap{int64_t(1) << 62, 0, ls, es}; }
+
+// Row of the Omega bitmask that a gathered / scattered line belongs to.  The
+// line index encodes `lead` natural indices (0: the single 1D line; 1: line =
+// r_0; 2: line = r_0 N_1 + r_1, N_1 = Q 2^{jl1}) of axes with 2^{jl0},
+// 2^{jl1} values per phase; the row is the row-major index of their
+// sequency indices n = s 2^j + seq(k) (natural r = s 2^j + k).
+struct RowMap {
+  int lead, jl0, jl1;
+};
+__device__ __forceinline__ int64_t sequency_row(int64_t r, int jj) {
+  const uint32_t s = uint32_t(r >> jj), k = uint32_t(r & ((int64_t(1) << jj) - 1));
+  return (int64_t(s) << jj) + sequency_of(k, s, jj);
+}
+__device__ __forceinline__ int64_t omega_row(int64_t line, const RowMap& rm, int Q) {
+  if (rm.lead == 0) return 0;
+  if (rm.lead == 1) return sequency_row(line, rm.jl0);
+  const int64_t N1 = int64_t(Q) << rm.jl1;
+  return sequency_row(line / N1, rm.jl0) * N1 + sequency_row(line % N1, rm.jl1);
+}
+
+// Forward G on lines of M = 2^j values.  gather == 0: write the N outputs of
+// each line in natural order r = s M + k at element r of output line `line`.
+// gather == 1: the samples of the line's Omega row go to y (`out`).
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_fwd_lines(const T* __restrict__ in, int64_t in_ls, int64_t in_es, T* __restrict__ out,
-            int64_t out_ls, int64_t out_es, int j, int gather, int dim1, Tables<T> t,
-            OmegaDev om) {
+k_fwd_lines(const T* __restrict__ in, LineMap im, T* __restrict__ out, LineMap omap, int j, int gather, RowMap rm,
+            Tables<T> t, OmegaDev om) {
   extern __shared__ unsigned char smem_raw[];
   const int M = 1 << j, Q = t.Q, tid = threadIdx.x, nt = blockDim.x;
   T* xi = reinterpret_cast<T*>(smem_raw);
@@ -357,32 +406,29 @@ k_fwd_lines(const T* __restrict__ in, int64_t in_ls, int64_t in_es, T* __restric
   int* pre = reinterpret_cast<int*>(L + M);
   int* scratch = pre + (gather && !om.full ? om.wpr : 0);
   const int64_t line = blockIdx.x;
-  for (int p = tid; p < M; p += nt) xi[p] = in[line * in_ls + p * in_es];
+  const int64_t ib = line_base(im, line);
+  for (int p = tid; p < M; p += nt) xi[p] = in[ib + p * im.es];
   int64_t n1 = 0, base = 0;
   const uint32_t* words = nullptr;
   if (gather) {
-    if (!dim1) {
-      const uint32_t s1 = uint32_t(line >> j), k1 = uint32_t(line & (M - 1));
-      n1 = int64_t(s1) * M + sequency_of(k1, s1, j);
-    }
+    n1 = omega_row(line, rm, Q);
     base = om.row_ptr[n1];
     if (!om.full) {
       words = om.mask + n1 * om.wpr;
       row_prefix(words, om.wpr, pre, scratch, tid, nt);
     }
   }
+  const int64_t ob = gather ? 0 : line_base(omap, line);
   __syncthreads();
   for (int s = 0; s < Q; ++s) {
     table_product(xi, L, M, s, tid, nt, t);
     __syncthreads();
     fwht_lds(L, M, tid, nt);
     if (!gather) {
-      for (int k = tid; k < M; k += nt) out[line * out_ls + (int64_t(s) * M + k) * out_es] = L[k];
+      for (int k = tid; k < M; k += nt) out[ob + (int64_t(s) * M + k) * omap.es] = L[k];
     } else if (om.full) {
-      const int64_t N = int64_t(M) * Q;
       for (int b = tid; b < M; b += nt)
         out[base + int64_t(s) * M + b] = L[natural_of(uint32_t(b), uint32_t(s), j)];
-      (void)N;
     } else {
       const int64_t w0 = (int64_t(s) * M) >> 5, w1 = (int64_t(s + 1) * M + 31) >> 5;
       for (int64_t w = w0 + tid; w < w1; w += nt) {
@@ -403,14 +449,13 @@ k_fwd_lines(const T* __restrict__ in, int64_t in_ls, int64_t in_es, T* __restric
   }
 }
 
-// Adjoint G^T on lines.  scatter == 0: read N natural-order values per line
-// from in + line * in_ls + r * in_es.  scatter == 1: line is natural row r of
-// the 2D intermediate (or the 1D line); its Omega samples come from y.
+// Adjoint G^T on lines.  scatter == 0: read the N natural-order values of
+// input line `line` (element r at r * im.es).  scatter == 1: the line's Omega
+// samples come from y (`in`).  The M results go to output line `line`.
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_adj_lines(const T* __restrict__ in, int64_t in_ls, int64_t in_es, T* __restrict__ out,
-            int64_t out_ls, int64_t out_es, int j, int scatter, int dim1, Tables<T> t,
-            OmegaDev om) {
+k_adj_lines(const T* __restrict__ in, LineMap im, T* __restrict__ out, LineMap omap, int j, int scatter, RowMap rm,
+            Tables<T> t, OmegaDev om) {
   extern __shared__ unsigned char smem_raw[];
   const int M = 1 << j, Q = t.Q, tid = threadIdx.x, nt = blockDim.x;
   T* xi = reinterpret_cast<T*>(smem_raw);
@@ -422,20 +467,18 @@ k_adj_lines(const T* __restrict__ in, int64_t in_ls, int64_t in_es, T* __restric
   int64_t n1 = 0, base = 0;
   const uint32_t* words = nullptr;
   if (scatter) {
-    if (!dim1) {
-      const uint32_t s1 = uint32_t(line >> j), k1 = uint32_t(line & (M - 1));
-      n1 = int64_t(s1) * M + sequency_of(k1, s1, j);
-    }
+    n1 = omega_row(line, rm, Q);
     base = om.row_ptr[n1];
     if (!om.full) {
       words = om.mask + n1 * om.wpr;
       row_prefix(words, om.wpr, pre, scratch, tid, nt);
     }
   }
+  const int64_t ib = scatter ? 0 : line_base(im, line);
   __syncthreads();
   for (int s = 0; s < Q; ++s) {
     if (!scatter) {
-      for (int k = tid; k < M; k += nt) R[k] = in[line * in_ls + (int64_t(s) * M + k) * in_es];
+      for (int k = tid; k < M; k += nt) R[k] = in[ib + (int64_t(s) * M + k) * im.es];
     } else if (om.full) {
       for (int b = tid; b < M; b += nt)
         R[natural_of(uint32_t(b), uint32_t(s), j)] = in[base + int64_t(s) * M + b];
@@ -462,7 +505,8 @@ k_adj_lines(const T* __restrict__ in, int64_t in_ls, int64_t in_es, T* __restric
     table_product_t(R, xi, M, s, tid, nt, t);
     __syncthreads();
   }
-  for (int m = tid; m < M; m += nt) out[line * out_ls + m * out_es] = xi[m];
+  const int64_t ob = line_base(omap, line);
+  for (int m = tid; m < M; m += nt) out[ob + m * omap.es] = xi[m];
 }
 
 }  // namespace
@@ -477,6 +521,7 @@ struct wh2wav_plan_s {
   int64_t* d_seg_ptr = nullptr;
   int32_t* d_pos32 = nullptr;
   size_t off_h = 0, off_g = 0, off_T = 0, off_BL = 0, off_BR = 0, off_SL = 0, off_SR = 0;
+  size_t off_T_ax[3] = {0, 0, 0}, off_BL_ax[3] = {0, 0, 0}, off_BR_ax[3] = {0, 0, 0};  // per-axis path
   int device = 0;             // the device current when the plan was made
 };
 
@@ -500,6 +545,18 @@ Tables<T> tables_of(const wh2wav_plan_s* p) {
   return t;
 }
 
+// Tables of axis a on the per-axis path (the interior and band tables carry
+// that axis's 2^{-j_a/2}).
+template <typename T>
+Tables<T> axis_tables_of(const wh2wav_plan_s* p, int a) {
+  Tables<T> t = tables_of<T>(p);
+  const T* base = static_cast<const T*>(p->d_tables);
+  t.tabT = base + p->off_T_ax[a];
+  t.bandL = base + p->off_BL_ax[a];
+  t.bandR = base + p->off_BR_ax[a];
+  return t;
+}
+
 template <typename T>
 wh2wav_fast::Tables<T> fast_tables_of(const wh2wav_plan_s* p) {
   const Tables<T> a = tables_of<T>(p);
@@ -520,7 +577,7 @@ wh2wav_fast::Omega fast_omega_of(const wh2wav_plan_s* p) {
 bool use_fast1d(const wh2wav_plan_s* p) {
   const auto& H = p->host;
   const bool f64 = H.dtype == WH2WAV_F64;
-  return H.dim == 1 && !H.per && wh2wav_fast::supported1d(f64 ? 8 : 4, H.j, H.nu, H.q) && H.j0 <= (f64 ? 13 : 14);
+  return H.dim == 1 && !H.nd && !H.per && wh2wav_fast::supported1d(f64 ? 8 : 4, H.j, H.nu, H.q) && H.j0 <= (f64 ? 13 : 14);
 }
 
 // 1D lines of 128 .. 2048 values: the whole line transform (table product,
@@ -534,7 +591,7 @@ bool use_wave1d(const wh2wav_plan_s* p) {
 
 bool use_fast(const wh2wav_plan_s* p) {
   const auto& H = p->host;
-  return H.dim == 2 && wh2wav_fast::supported(H.dtype == WH2WAV_F64 ? 8 : 4, H.j, H.nu, H.q);
+  return H.dim == 2 && !H.nd && wh2wav_fast::supported(H.dtype == WH2WAV_F64 ? 8 : 4, H.j, H.nu, H.q);
 }
 
 OmegaDev omega_of(const wh2wav_plan_s* p) {
@@ -546,8 +603,8 @@ OmegaDev omega_of(const wh2wav_plan_s* p) {
   return o;
 }
 
-size_t line_smem(const wh2wav_plan_s* p, size_t elem, bool omega_side) {
-  size_t b = 2 * size_t(p->host.M) * elem;
+size_t line_smem(const wh2wav_plan_s* p, size_t elem, bool omega_side, int64_t M = 0) {
+  size_t b = 2 * size_t(M ? M : p->host.M) * elem;
   if (omega_side && !p->host.full_omega) b += sizeof(int) * (size_t(p->host.words_per_row) + kThreads);
   return b;
 }
@@ -575,20 +632,8 @@ int launch_synth(const wh2wav_plan_s* p, const T* in, T* out, int64_t lines, int
                  int k, bool line_fast, bool analysis, hipStream_t st) {
   const int64_t total = lines * (int64_t(2) << k);
   const int64_t blocks = (total + kThreads - 1) / kThreads;
-  if (p->host.per) {
-    if (analysis)
-      hipLaunchKernelGGL(k_analysis_per<T>, dim3(unsigned(blocks)), dim3(kThreads), 0, st, in, out, lines, ls, es,
-                         k, int(line_fast), tables_of<T>(p));
-    else
-      hipLaunchKernelGGL(k_synth_per<T>, dim3(unsigned(blocks)), dim3(kThreads), 0, st, in, out, lines, ls, es, k,
-                         int(line_fast), tables_of<T>(p));
-  } else if (analysis) {
-    hipLaunchKernelGGL(k_analysis<T>, dim3(unsigned(blocks)), dim3(kThreads), 0, st, in, out, lines, ls, es, k,
-                       int(line_fast), tables_of<T>(p));
-  } else {
-    hipLaunchKernelGGL(k_synth<T>, dim3(unsigned(blocks)), dim3(kThreads), 0, st, in, out, lines, ls, es, k,
-                       int(line_fast), tables_of<T>(p));
-  }
+  hipLaunchKernelGGL(k_level<T>, dim3(unsigned(blocks)), dim3(kThreads), 0, st, in, out, lines, ls, es, k,
+                     int(line_fast), int(analysis), tables_of<T>(p));
   HIP_OK(hipGetLastError());
   return WH2WAV_OK;
 }
@@ -680,6 +725,163 @@ int dwt2d_tensor(const wh2wav_plan_s* p, T* in, T* x, T* W, hipStream_t st) {
   return rc;
 }
 
+// ------------------------------------------- three dimensions, unequal sides
+// The per-axis path (Sec. 5: the d-fold inner products split into 1D ones).
+// x (M_0 x M_1 [x M_2], row-major) -> wavelet levels -> xi; G along axis 0
+// (Z0: N_0 x M_1 [x M_2]), along axis 1 in 3D (Z1: N_0 x N_1 x M_2), and
+// along the last axis with the gather onto Omega, each axis with its own
+// tables.  Workspace: XA, XB (M_0 M_1 M_2 each), Z0, Z1.
+
+// Wavelet levels in the order the inverse DWT applies them: (axis, level).
+// Tensor basis: every level of axis 0, then of axis 1, ...  Isotropic: per
+// level, every axis within the cube [0, 2^{k+1})^d.
+std::vector<std::pair<int, int>> nd_levels(const wh2wav::HostPlan& H) {
+  std::vector<std::pair<int, int>> out;
+  if (H.tensor) {
+    for (int a = 0; a < H.dim; ++a)
+      for (int k = H.j0; k < H.ja[a]; ++k) out.emplace_back(a, k);
+  } else {
+    for (int k = H.j0; k < H.j; ++k)
+      for (int a = 0; a < H.dim; ++a) out.emplace_back(a, k);
+  }
+  return out;
+}
+
+struct NdBuffers {
+  size_t xa, xb, z0, z1;  // offsets in elements
+  size_t total;
+};
+NdBuffers nd_buffers(const wh2wav::HostPlan& H) {
+  const size_t mtot = size_t(H.Ma[0] * H.Ma[1] * H.Ma[2]);
+  const size_t z0 = size_t(H.Na[0] * H.Ma[1] * H.Ma[2]);
+  const size_t z1 = H.dim == 3 ? size_t(H.Na[0] * H.Na[1] * H.Ma[2]) : 0;
+  return NdBuffers{0, mtot, 2 * mtot, 2 * mtot + z0, 2 * mtot + z0 + z1};
+}
+
+template <typename T>
+int nd_level(const wh2wav_plan_s* p, const T* in, T* out, int axis, int k, bool analysis, hipStream_t st) {
+  const auto& H = p->host;
+  const int64_t total = H.Ma[0] * H.Ma[1] * H.Ma[2];
+  hipLaunchKernelGGL(k_level_nd<T>, dim3(unsigned((total + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, in,
+                     out, H.Ma[0], H.Ma[1], H.Ma[2], axis, k, H.tensor ? 0 : 1, analysis ? 1 : 0, tables_of<T>(p));
+  HIP_OK(hipGetLastError());
+  return WH2WAV_OK;
+}
+
+// One launch of the line kernels on the per-axis path: G (fwd) or G^T along
+// axis `a`, `lines` lines.
+template <typename T>
+int nd_pass(const wh2wav_plan_s* p, bool fwd, int a, int64_t lines, const T* in, LineMap im, T* out, LineMap om_,
+            int omega_side, RowMap rm, hipStream_t st) {
+  const auto& H = p->host;
+  const size_t smem = line_smem(p, sizeof(T), omega_side != 0, H.Ma[a]);
+  const void* kern = fwd ? (const void*)k_fwd_lines<T> : (const void*)k_adj_lines<T>;
+  int rc = check_and_set_smem<T>(kern, smem);
+  if (rc) return rc;
+  if (fwd)
+    hipLaunchKernelGGL(k_fwd_lines<T>, dim3(unsigned(lines)), dim3(kThreads), smem, st, in, im, out, om_, H.ja[a],
+                       omega_side, rm, axis_tables_of<T>(p, a), omega_of(p));
+  else
+    hipLaunchKernelGGL(k_adj_lines<T>, dim3(unsigned(lines)), dim3(kThreads), smem, st, in, im, out, om_, H.ja[a],
+                       omega_side, rm, axis_tables_of<T>(p, a), omega_of(p));
+  HIP_OK(hipGetLastError());
+  return WH2WAV_OK;
+}
+
+// Forward stages: 0 = inverse DWT into XA, 1 = G along every axis but the
+// last, 2 = G along the last axis with the gather.
+template <typename T>
+int forward_nd(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t st, int stage) {
+  const auto& H = p->host;
+  auto run = [&](int s) { return stage < 0 || stage == s; };
+  if (H.m == 0) return WH2WAV_OK;
+  const NdBuffers b = nd_buffers(H);
+  T* W = static_cast<T*>(ws);
+  T *XA = W + b.xa, *XB = W + b.xb, *Z0 = W + b.z0, *Z1 = W + b.z1;
+  const int64_t M0 = H.Ma[0], M1 = H.Ma[1], M2 = H.Ma[2], N0 = H.Na[0], N1 = H.Na[1];
+  if (run(0)) {
+    const auto levels = nd_levels(H);
+    if (levels.empty()) HIP_OK(hipMemcpyAsync(XA, x, sizeof(T) * size_t(M0 * M1 * M2), hipMemcpyDeviceToDevice, st));
+    const T* src = x;
+    for (size_t i = 0; i < levels.size(); ++i) {  // the last level writes XA
+      T* dst = (levels.size() - 1 - i) % 2 == 0 ? XA : XB;
+      int rc = nd_level<T>(p, src, dst, levels[i].first, levels[i].second, false, st);
+      if (rc) return rc;
+      src = dst;
+    }
+  }
+  const RowMap none{0, 0, 0};
+  int rc = WH2WAV_OK;
+  if (H.dim == 2) {
+    if (run(1)) rc = nd_pass<T>(p, true, 0, M1, XA, lines_at(1, M1), Z0, lines_at(1, M1), 0, none, st);
+    if (rc == WH2WAV_OK && run(2))
+      rc = nd_pass<T>(p, true, 1, N0, Z0, lines_at(M1, 1), y, lines_at(0, 0), 1, RowMap{1, H.ja[0], 0}, st);
+    return rc;
+  }
+  if (run(1)) {
+    rc = nd_pass<T>(p, true, 0, M1 * M2, XA, lines_at(1, M1 * M2), Z0, lines_at(1, M1 * M2), 0, none, st);
+    if (rc == WH2WAV_OK)
+      rc = nd_pass<T>(p, true, 1, N0 * M2, Z0, LineMap{M2, M1 * M2, 1, M2}, Z1, LineMap{M2, N1 * M2, 1, M2}, 0, none,
+                      st);
+  }
+  if (rc == WH2WAV_OK && run(2))
+    rc = nd_pass<T>(p, true, 2, N0 * N1, Z1, lines_at(M2, 1), y, lines_at(0, 0), 1, RowMap{2, H.ja[0], H.ja[1]},
+                    st);
+  return rc;
+}
+
+// Adjoint stages: 0 = G^T along the last axis with the scatter, 1 = G^T
+// along the other axes (into XA), 2 = forward DWT into x.
+template <typename T>
+int adjoint_nd(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t st, int stage) {
+  const auto& H = p->host;
+  auto run = [&](int s) { return stage < 0 || stage == s; };
+  const int64_t M0 = H.Ma[0], M1 = H.Ma[1], M2 = H.Ma[2], N0 = H.Na[0], N1 = H.Na[1];
+  if (H.m == 0) {
+    if (run(2)) {
+      launch_fill<T>(x, M0 * M1 * M2, st);
+      HIP_OK(hipGetLastError());
+    }
+    return WH2WAV_OK;
+  }
+  const NdBuffers b = nd_buffers(H);
+  T* W = static_cast<T*>(ws);
+  T *XA = W + b.xa, *XB = W + b.xb, *Z0 = W + b.z0, *Z1 = W + b.z1;
+  const RowMap none{0, 0, 0};
+  int rc = WH2WAV_OK;
+  if (H.dim == 2) {
+    if (run(0))
+      rc = nd_pass<T>(p, false, 1, N0, y, lines_at(0, 0), Z0, lines_at(M1, 1), 1, RowMap{1, H.ja[0], 0}, st);
+    if (rc == WH2WAV_OK && run(1))
+      rc = nd_pass<T>(p, false, 0, M1, Z0, lines_at(1, M1), XA, lines_at(1, M1), 0, none, st);
+  } else {
+    if (run(0))
+      rc = nd_pass<T>(p, false, 2, N0 * N1, y, lines_at(0, 0), Z1, lines_at(M2, 1), 1, RowMap{2, H.ja[0], H.ja[1]},
+                      st);
+    if (rc == WH2WAV_OK && run(1)) {
+      rc = nd_pass<T>(p, false, 1, N0 * M2, Z1, LineMap{M2, N1 * M2, 1, M2}, Z0, LineMap{M2, M1 * M2, 1, M2}, 0,
+                      none, st);
+      if (rc == WH2WAV_OK)
+        rc = nd_pass<T>(p, false, 0, M1 * M2, Z0, lines_at(1, M1 * M2), XA, lines_at(1, M1 * M2), 0, none, st);
+    }
+  }
+  if (rc || !run(2)) return rc;
+  auto levels = nd_levels(H);
+  if (levels.empty()) {
+    HIP_OK(hipMemcpyAsync(x, XA, sizeof(T) * size_t(M0 * M1 * M2), hipMemcpyDeviceToDevice, st));
+    return WH2WAV_OK;
+  }
+  const T* src = XA;
+  for (size_t i = 0; i < levels.size(); ++i) {  // the transposes in reverse order; the last writes x
+    const auto& lv = levels[levels.size() - 1 - i];
+    T* dst = i + 1 == levels.size() ? x : (i % 2 == 0 ? XB : XA);
+    rc = nd_level<T>(p, src, dst, lv.first, lv.second, true, st);
+    if (rc) return rc;
+    src = dst;
+  }
+  return WH2WAV_OK;
+}
+
 // Forward stages: 0 = inverse DWT, 1 = column pass (2D) / line transform (1D),
 // 2 = row pass with the Omega gather (2D).  stage < 0 runs all of them.
 template <typename T>
@@ -688,6 +890,7 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
   const int64_t M = H.M, N = H.N;
   const Tables<T> t = tables_of<T>(p);
   const OmegaDev om = omega_of(p);
+  if (H.nd) return forward_nd<T>(p, x, y, ws, st, stage);
   if (H.m == 0) return WH2WAV_OK;
   T* W = static_cast<T*>(ws);
   auto run = [&](int s) { return stage < 0 || stage == s; };
@@ -717,7 +920,8 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
       size_t smem = line_smem(p, sizeof(T), true);
       int rc = check_and_set_smem<T>((const void*)k_fwd_lines<T>, smem);
       if (rc) return rc;
-      hipLaunchKernelGGL(k_fwd_lines<T>, dim3(1), dim3(kThreads), smem, st, W, 0, 1, y, 0, 0, H.j, 1, 1, t, om);
+      hipLaunchKernelGGL(k_fwd_lines<T>, dim3(1), dim3(kThreads), smem, st, W, lines_at(0, 1), y, lines_at(0, 0), H.j,
+                         1, RowMap{0, 0, 0}, t, om);
       HIP_OK(hipGetLastError());
     }
     return WH2WAV_OK;
@@ -743,14 +947,14 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
   if (rc) return rc;
   if (run(1)) {  // column pass: G along the first index (rows of xi^T); Z[r, m2] with r natural
     size_t smem0 = line_smem(p, sizeof(T), false);
-    hipLaunchKernelGGL(k_fwd_lines<T>, dim3(unsigned(M)), dim3(kThreads), smem0, st, TMP, M, 1, Z, 1, M, H.j, 0,
-                       0, t, om);
+    hipLaunchKernelGGL(k_fwd_lines<T>, dim3(unsigned(M)), dim3(kThreads), smem0, st, TMP, lines_at(M, 1), Z,
+                       lines_at(1, M), H.j, 0, RowMap{0, 0, 0}, t, om);
     HIP_OK(hipGetLastError());
   }
   if (run(2)) {  // row pass: G along the second index, gather Omega
     size_t smem1 = line_smem(p, sizeof(T), true);
-    hipLaunchKernelGGL(k_fwd_lines<T>, dim3(unsigned(N)), dim3(kThreads), smem1, st, Z, M, 1, y, 0, 0, H.j, 1,
-                       0, t, om);
+    hipLaunchKernelGGL(k_fwd_lines<T>, dim3(unsigned(N)), dim3(kThreads), smem1, st, Z, lines_at(M, 1), y,
+                       lines_at(0, 0), H.j, 1, RowMap{1, H.j, 0}, t, om);
     HIP_OK(hipGetLastError());
   }
   return WH2WAV_OK;
@@ -764,6 +968,7 @@ int adjoint_impl(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t
   const int64_t M = H.M, N = H.N;
   const Tables<T> t = tables_of<T>(p);
   const OmegaDev om = omega_of(p);
+  if (H.nd) return adjoint_nd<T>(p, y, x, ws, st, stage);
   T* W = static_cast<T*>(ws);
   auto run = [&](int s) { return stage < 0 || stage == s; };
   const int64_t xlen = H.dim == 1 ? M : M * M;
@@ -792,7 +997,8 @@ int adjoint_impl(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t
       size_t smem = line_smem(p, sizeof(T), true);
       int rc = check_and_set_smem<T>((const void*)k_adj_lines<T>, smem);
       if (rc) return rc;
-      hipLaunchKernelGGL(k_adj_lines<T>, dim3(1), dim3(kThreads), smem, st, y, 0, 0, W, 0, 1, H.j, 1, 1, t, om);
+      hipLaunchKernelGGL(k_adj_lines<T>, dim3(1), dim3(kThreads), smem, st, y, lines_at(0, 0), W, lines_at(0, 1), H.j,
+                         1, RowMap{0, 0, 0}, t, om);
       HIP_OK(hipGetLastError());
     }
     if (run(2)) {
@@ -819,14 +1025,14 @@ int adjoint_impl(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t
   if (rc) return rc;
   if (run(0)) {
     size_t smem1 = line_smem(p, sizeof(T), true);
-    hipLaunchKernelGGL(k_adj_lines<T>, dim3(unsigned(N)), dim3(kThreads), smem1, st, y, 0, 0, Z, M, 1, H.j, 1, 0,
-                       t, om);
+    hipLaunchKernelGGL(k_adj_lines<T>, dim3(unsigned(N)), dim3(kThreads), smem1, st, y, lines_at(0, 0), Z,
+                       lines_at(M, 1), H.j, 1, RowMap{1, H.j, 0}, t, om);
     HIP_OK(hipGetLastError());
   }
   if (run(1)) {  // column pass, transposed: xi'^T into TMP
     size_t smem0 = line_smem(p, sizeof(T), false);
-    hipLaunchKernelGGL(k_adj_lines<T>, dim3(unsigned(M)), dim3(kThreads), smem0, st, Z, 1, M, TMP, M, 1, H.j, 0,
-                       0, t, om);
+    hipLaunchKernelGGL(k_adj_lines<T>, dim3(unsigned(M)), dim3(kThreads), smem0, st, Z, lines_at(1, M), TMP,
+                       lines_at(M, 1), H.j, 0, RowMap{0, 0, 0}, t, om);
     HIP_OK(hipGetLastError());
   }
   if (run(2) && H.tensor) return dwt2d_tensor<T>(p, TMP, x, W, st);
@@ -850,6 +1056,11 @@ int upload_tables(wh2wav_plan_s* p) {
   put(H.tabBR, &p->off_BR);
   put(H.synL, &p->off_SL);
   put(H.synR, &p->off_SR);
+  for (int a = 0; H.nd && a < H.dim; ++a) {
+    put(H.tabT_ax[a], &p->off_T_ax[a]);
+    put(H.tabBL_ax[a], &p->off_BL_ax[a]);
+    put(H.tabBR_ax[a], &p->off_BR_ax[a]);
+  }
   HIP_OK(hipMalloc(&p->d_tables, sizeof(T) * all.size()));
   HIP_OK(hipMemcpy(p->d_tables, all.data(), sizeof(T) * all.size(), hipMemcpyHostToDevice));
   return WH2WAV_OK;
@@ -898,7 +1109,12 @@ bool handle_live(const void* h) {
 }
 PlanShape plan_shape(wh2wav_plan_t p) {
   const auto& H = p->host;
-  return PlanShape{H.dim, H.j, H.q, H.nu, H.dtype, H.M, H.N, H.m};
+  int64_t xlen = H.dim == 1 ? H.M : H.M * H.M, ntot = H.dim == 1 ? H.N : H.N * H.N;
+  if (H.nd) {
+    xlen = H.Ma[0] * H.Ma[1] * H.Ma[2];
+    ntot = H.Na[0] * H.Na[1] * H.Na[2];
+  }
+  return PlanShape{H.dim, H.j, H.q, H.nu, H.dtype, H.M, H.N, H.m, xlen, ntot};
 }
 }  // namespace wh2wav
 
@@ -918,8 +1134,10 @@ int plan_body(const wh2wav_desc* desc, wh2wav_plan_t* out) {
   const auto& H = p->host;
   if (H.j < 1) return fail(WH2WAV_EUNSUPPORTED, "j must be >= 1");
   const size_t elem = H.dtype == WH2WAV_F64 ? 8 : 4;
+  int64_t Mline = H.M;  // longest line of the LDS line kernels
+  for (int a = 0; H.nd && a < H.dim; ++a) Mline = std::max(Mline, H.Ma[a]);
   if (!use_fast(p) && !use_fast1d(p) &&
-      2 * size_t(H.M) * elem + sizeof(int) * (size_t(H.words_per_row) + kThreads) > kMaxLds)
+      2 * size_t(Mline) * elem + sizeof(int) * (size_t(H.words_per_row) + kThreads) > kMaxLds)
     return fail(WH2WAV_EUNSUPPORTED, "M too large for the LDS line kernels");
   rc = H.dtype == WH2WAV_F64 ? prepare_line_kernels<double>() : prepare_line_kernels<float>();
   if (rc != WH2WAV_OK) return rc;
@@ -973,7 +1191,9 @@ int wh2wav_workspace_size(wh2wav_plan_t p, size_t* bytes) {
   if (!wh2wav::handle_live(p)) return fail(WH2WAV_EINVAL, "not a live plan (destroyed, or never created)");
   const auto& H = p->host;
   const size_t elem = H.dtype == WH2WAV_F64 ? 8 : 4;
-  if (H.dim == 1)
+  if (H.nd)
+    *bytes = nd_buffers(H).total * elem;
+  else if (H.dim == 1)
     *bytes = (2 + size_t(H.Q)) * size_t(H.M) * elem;
   else
     *bytes = (2 * size_t(H.M) * size_t(H.M) + size_t(H.N) * size_t(H.M)) * elem;
@@ -985,7 +1205,8 @@ static int check_call(wh2wav_plan_t p, const void* a, const void* b, void* ws) {
   if (!wh2wav::handle_live(p)) return fail(WH2WAV_EINVAL, "not a live plan (destroyed, or never created)");
   const auto& H = p->host;
   const size_t elem = H.dtype == WH2WAV_F64 ? 8 : 4;
-  const size_t in_out[2] = {size_t(H.dim == 1 ? H.M : H.M * H.M) * elem, size_t(H.m) * elem};
+  const int64_t xlen = H.nd ? H.Ma[0] * H.Ma[1] * H.Ma[2] : (H.dim == 1 ? H.M : H.M * H.M);
+  const size_t in_out[2] = {size_t(xlen) * elem, size_t(H.m) * elem};
   if (!ws) return fail(WH2WAV_EINVAL, "workspace is NULL");
   if ((!a && in_out[0]) || (!b && in_out[1])) return fail(WH2WAV_EINVAL, "x or y is NULL");
   auto overlap = [](const void* p1, size_t n1, const void* p2, size_t n2) {

@@ -24,16 +24,30 @@ _BOUNDARIES = {"bd": _abi.WH2WAV_BD, "per": _abi.WH2WAV_PER}
 _BASES = {"isotropic": _abi.WH2WAV_ISOTROPIC, "tensor": _abi.WH2WAV_TENSOR}
 
 
+def axis_sizes(dim, j, j_axes=None):
+    """Per-axis j of an operator: j_axes (dim entries, 0 taking j) or j on every axis."""
+    if dim == 1:
+        return (j,)
+    js = tuple(j for _ in range(dim)) if j_axes is None else tuple(int(v) or j for v in j_axes)
+    if len(js) != dim:
+        raise ValueError(f"j_axes needs {dim} entries")
+    return js
+
+
 def make_desc(dim, j, q, nu, j0=None, dtype=torch.float64, omega=None, family="db", boundary="bd",
-              basis2d="isotropic"):
+              basis2d="isotropic", j_axes=None):
     """Build a wh2wav_desc; returns (desc, keepalive) -- keep the second alive until planned.
 
     family: "db" (Daubechies) or "sym" (least-asymmetric symlets); boundary:
     "bd" (vanishing-moment-preserving boundary functions) or "per" (periodic);
-    basis2d: "isotropic" (quadtree) or "tensor" (products of 1D basis functions)."""
+    basis2d: "isotropic" (quadtree / octant layout) or "tensor" (products of 1D
+    basis functions), for dim 2 and 3; j_axes: per-axis j (tensor basis), or
+    None for j on every axis."""
     j0 = default_j0(nu) if j0 is None else j0
-    N = 1 << (j + q)
-    total = N ** dim
+    js = axis_sizes(dim, j, j_axes)
+    total = 1
+    for ja in js:
+        total *= 1 << (ja + q)
     if omega is None:
         m, ptr, keep = total, None, None
     else:
@@ -41,9 +55,10 @@ def make_desc(dim, j, q, nu, j0=None, dtype=torch.float64, omega=None, family="d
         m = int(keep.size)
         ptr = keep.ctypes.data_as(_abi.ctypes.POINTER(_abi.ctypes.c_int64)) if m else \
             _abi.ctypes.cast(_abi.ctypes.pointer(_abi.ctypes.c_int64(0)), _abi.ctypes.POINTER(_abi.ctypes.c_int64))
+    jx = (_abi.ctypes.c_int * 3)(*([0, 0, 0] if j_axes is None else list(j_axes) + [0] * (3 - len(j_axes))))
     desc = _abi.wh2wav_desc(dim=dim, j=j, q=q, j0=j0, nu=nu, family=_FAMILIES[family],
                             boundary=_BOUNDARIES[boundary], dtype=_DTYPES[dtype], m=m, omega=ptr,
-                            basis2d=_BASES[basis2d])
+                            basis2d=_BASES[basis2d], j_axes=jx)
     return desc, keep
 
 
@@ -51,14 +66,15 @@ class Wh2Wav:
     """y = P_Omega A x and x = A^T P_Omega^T y on the current CUDA/HIP device."""
 
     def __init__(self, dim, j, q, nu, j0=None, dtype=torch.float64, omega=None, device=None, family="db",
-                 boundary="bd", basis2d="isotropic"):
+                 boundary="bd", basis2d="isotropic", j_axes=None):
         self.dim, self.j, self.q, self.nu, self.family, self.boundary = dim, j, q, nu, family, boundary
         self.basis2d = basis2d
         self.j0 = default_j0(nu) if j0 is None else j0
         self.dtype = dtype
         self.M, self.N = 1 << j, 1 << (j + q)
+        self.j_axes = axis_sizes(dim, j, j_axes)
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
-        desc, keep = make_desc(dim, j, q, nu, self.j0, dtype, omega, family, boundary, basis2d)
+        desc, keep = make_desc(dim, j, q, nu, self.j0, dtype, omega, family, boundary, basis2d, j_axes)
         self.m = int(desc.m)
         with torch.cuda.device(self.device):
             self._plan = _abi.wh2wav_plan(desc)
@@ -68,7 +84,12 @@ class Wh2Wav:
 
     @property
     def x_shape(self):
-        return (self.M,) if self.dim == 1 else (self.M, self.M)
+        return tuple(1 << ja for ja in self.j_axes)
+
+    @property
+    def y_shape(self):
+        """Shape of the full Walsh sample array (N_1, ..., N_dim)."""
+        return tuple(1 << (ja + self.q) for ja in self.j_axes)
 
     def _stream(self):
         return torch.cuda.current_stream(self.device).cuda_stream
@@ -121,11 +142,11 @@ class Wh2WavBatch:
         for sp in specs:
             dtype = sp.get("dtype", torch.float64)
             d, k = make_desc(sp["dim"], sp["j"], sp["q"], sp["nu"], sp.get("j0"), dtype, sp.get("omega"),
-                             sp.get("family", "db"), sp.get("boundary", "bd"), sp.get("basis2d", "isotropic"))
+                             sp.get("family", "db"), sp.get("boundary", "bd"), sp.get("basis2d", "isotropic"),
+                             sp.get("j_axes"))
             descs.append(d)
             keeps.append(k)
-            M = 1 << sp["j"]
-            self.x_shapes.append((M,) if sp["dim"] == 1 else (M, M))
+            self.x_shapes.append(tuple(1 << ja for ja in axis_sizes(sp["dim"], sp["j"], sp.get("j_axes"))))
             self.ms.append(int(d.m))
             self.dtypes.append(dtype)
         with torch.cuda.device(self.device):

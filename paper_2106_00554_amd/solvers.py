@@ -92,7 +92,7 @@ def extreme_singular_values(op, iters=None, seed=0):
 
     With iters >= the number of columns the Krylov space is the whole space and
     the Ritz values are the eigenvalues of A^T A up to rounding."""
-    n = op.M if op.dim == 1 else op.M * op.M
+    n = math.prod(op.x_shape)
     k = n if iters is None else min(iters, n)
     dt = op.dtype
     g = torch.Generator(device="cpu").manual_seed(seed)

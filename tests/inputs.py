@@ -54,6 +54,12 @@ def coefficients_2d(j, j0, seed, exponent=2.0, zero_frac=0.9):
     return X
 
 
+def coefficients_nd(shape, seed, zero_frac=0.5):
+    """Coefficients of the 3D and unequal-sided operators: standard normal, a share zeroed."""
+    rng = rng_for(seed)
+    return _sparsify(rng, rng.standard_normal(tuple(shape)), zero_frac)
+
+
 def _annuli_2d(N, core):
     """Yield index arrays (linear n1 * N + n2) of the core square and the dyadic annuli."""
     n1, n2 = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")

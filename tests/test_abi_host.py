@@ -123,7 +123,45 @@ def test_omega_row_offsets():
     assert np.array_equal(rp, ref)
 
 
-@pytest.mark.parametrize("field,value", [("dim", 3), ("nu", 0), ("nu", 11), ("q", 0), ("j0", 1), ("j", 1),
+@pytest.mark.parametrize("js,tensor", [((3, 3, 3), False), ((2, 3, 4), True), ((4, 2), True), ((3, 5), True)])
+def test_omega_rows_of_three_dimensions_and_unequal_sides(js, tensor):
+    """Rows of the sample bitmask: every axis but the last, row-major; row length N_last."""
+    rng = np.random.default_rng(2)
+    q = 1
+    Ns = [1 << (ja + q) for ja in js]
+    total = int(np.prod(Ns))
+    omega = np.sort(rng.choice(total, total // 7, replace=False))
+    d, keep = desc(2, 3, q, dim=len(js), omega=omega)
+    d.basis2d = abi.WH2WAV_TENSOR if tensor else abi.WH2WAV_ISOTROPIC
+    for a, ja in enumerate(js):
+        d.j_axes[a] = ja
+    rp = np.array(abi.wh2wav_host_table(d, "row_ptr"))
+    ref = np.concatenate([[0], np.cumsum(np.bincount(omega // Ns[-1], minlength=total // Ns[-1]))])
+    assert np.array_equal(rp, ref)
+
+
+@pytest.mark.parametrize("dim,js,basis,code", [
+    (2, (3, 4), 0, "EINVAL"),      # unequal sides need the tensor basis
+    (3, (3, 3, 5), 0, "EINVAL"),
+    (2, (3, 4, 3), 1, "EINVAL"),   # an entry beyond dim
+    (1, (4, 0, 0), 0, "EINVAL"),   # no per-axis sizes in 1D
+    (2, (1, 4), 1, "EINVAL"),      # below j0
+    (3, (10, 10, 10), 1, "EUNSUPPORTED"),  # N_1 N_2 N_3 beyond 2^32
+    (2, (15, 3), 1, "EUNSUPPORTED"),       # N_a beyond 2^15
+])
+def test_axis_validation(dim, js, basis, code):
+    d, _ = desc(2, 3, 1, dim=dim)
+    d.m = 0
+    d.omega = ctypes.cast(ctypes.pointer(ctypes.c_int64(0)), ctypes.POINTER(ctypes.c_int64))
+    d.basis2d = basis
+    for a, ja in enumerate(js):
+        d.j_axes[a] = ja
+    with pytest.raises(abi.Wh2WavError) as e:
+        abi.wh2wav_host_table(d, "h")
+    assert e.value.code == getattr(abi, "WH2WAV_" + code)
+
+
+@pytest.mark.parametrize("field,value", [("dim", 4), ("dim", 0), ("nu", 0), ("nu", 11), ("q", 0), ("j0", 1), ("j", 1),
                                          ("dtype", 5), ("family", 2), ("boundary", 2), ("boundary", -1), ("m", 5),
                                          ("basis2d", 2)])
 def test_descriptor_validation(field, value):
