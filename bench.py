@@ -447,6 +447,7 @@ def round_robin_leg(torch, steps, name="2d_db8_j11_q2_12.5pct", copies=4):
 
 
 def batched_leg(torch, steps):
+    import numpy as np
     from paper_2106_00554_amd.operator import Wh2Wav, Wh2WavBatch
     from tests import inputs
 
@@ -478,13 +479,65 @@ def batched_leg(torch, steps):
 
     batched()
     plain()
-    t_b = timed(batched, steps, torch)
+    batch.set_mode("fused")
+    batched()
+    _, in_fused, launches = batch.mode()
+    # the two designs in turn, three times each on the same box
+    runs = {"branches": [], "fused": []}
+    for _ in range(3):
+        for mode in ("branches", "fused"):
+            batch.set_mode(mode)
+            runs[mode].append(timed(batched, steps, torch))
+    batch.set_mode("branches")
     t_p = timed(plain, max(1, steps // 2), torch)
+    t_b = float(np.median(runs["branches"]))
+    t_f = float(np.median(runs["fused"]))
     n = len(specs)
+    # algorithmic bytes of one forward + adjoint of every instance: x and y
+    # once each, the Omega bitmask, and in 2D one write and one read of the
+    # N x M intermediate, per direction
+    nbytes = 0
+    for f, _ in full:
+        M, N = 1 << f["j"], 1 << (f["j"] + f["q"])
+        xlen, ntot = (M, N) if f["dim"] == 1 else (M * M, N * N)
+        m = ntot if f["omega"] is None else len(f["omega"])
+        nbytes += 2 * (4 * xlen + 4 * m + ntot // 8 + (2 * 4 * M * N if f["dim"] == 2 else 0))
+    best = min(t_b, t_f)
+    # the launch-bound group alone: the 32 2D instances of 128^2 .. 512^2
+    small = [k for k, (f, _) in enumerate(full) if f["dim"] == 2 and f["j"] <= 9]
+    sb = Wh2WavBatch([full[k][0] for k in small])
+    sb.set_schedule(8, 1)
+    sxs = [xs[k] for k in small]
+    sys_ = sb.new_outputs(0)
+    sxa = sb.new_outputs(1)
+
+    def small_batched():
+        sb.forward(sxs, sys_)
+        sb.adjoint(sys_, sxa)
+
+    small_runs = {"branches": [], "fused": []}
+    for mode in ("branches", "fused"):
+        sb.set_mode(mode)
+        small_batched()
+    for _ in range(3):
+        for mode in ("branches", "fused"):
+            sb.set_mode(mode)
+            small_runs[mode].append(timed(small_batched, steps, torch))
+    small_out = {"instances": len(small), "fused_launches_per_direction": sb.mode()[2],
+                 "runs_ms": {k: [round(v * 1e3, 4) for v in vs] for k, vs in small_runs.items()},
+                 "branches_pairs_per_s": len(small) / float(np.median(small_runs["branches"])),
+                 "fused_pairs_per_s": len(small) / float(np.median(small_runs["fused"]))}
+    sb.close()
     return {"instances": n, "groups": "32 x 1D 2^12..2^16, 32 x 2D 128^2..512^2, 32 x 2D 1024^2",
-            "pairs_per_s": n / t_b, "plain_pairs_per_s": n / t_p, "speedup_vs_plain": t_p / t_b,
-            "ms_per_batch_pair": t_b * 1e3, "schedule": {"branches": sched[0], "order": sched[1]},
-            "tuned_ms": best_ms}
+            "small_group": small_out,
+            "pairs_per_s": n / best, "design": "branches" if t_b <= t_f else "fused",
+            "branches_pairs_per_s": n / t_b, "fused_pairs_per_s": n / t_f,
+            "runs_ms": {k: [round(v * 1e3, 4) for v in vs] for k, vs in runs.items()},
+            "fused_instances": in_fused, "fused_launches_per_direction": launches,
+            "plain_pairs_per_s": n / t_p, "speedup_vs_plain": t_p / best,
+            "ms_per_batch_pair": best * 1e3, "schedule": {"branches": sched[0], "order": sched[1]},
+            "algorithmic_bytes_per_pair": nbytes, "hbm_GBs": nbytes / best / 1e9,
+            "hbm_frac": nbytes / best / 1e9 / HBM_PEAK_GBS, "tuned_ms": best_ms}
 
 
 def main():

@@ -203,6 +203,23 @@ int wh2wav_adjoint_batch(wh2wav_batch_t b, const void* const* ys, void* const* x
 int wh2wav_batch_schedule(wh2wav_batch_t b, int* branches, int* order);
 int wh2wav_batch_set_schedule(wh2wav_batch_t b, int branches, int order);
 
+/* Execution mode.  BRANCHES (default): every instance runs its own stage
+ * kernels in the graph branches.  FUSED: the small instances -- 1D lines of
+ * at most 1024 values and square 2D arrays of at most 512^2, isotropic basis,
+ * boundary-corrected or periodic, at least one sample -- run as fused
+ * launches over (instance, stage, tile) work items: one launch per round of
+ * their stages (round r = stage r of every such instance), inside the same
+ * graph beside the branches, which keep the other instances.  Its results
+ * equal the single plans' to rounding (other summation orders), not bit for
+ * bit. */
+enum { WH2WAV_BATCH_BRANCHES = 0, WH2WAV_BATCH_FUSED = 1 };
+int wh2wav_batch_set_mode(wh2wav_batch_t b, int mode);
+
+/* The mode; *fused_instances (may be NULL) receives how many instances the
+ * fused launches take in that mode, *fused_launches (may be NULL) how many
+ * launches they make per forward call. */
+int wh2wav_batch_mode(wh2wav_batch_t b, int* mode, int* fused_instances, int* fused_launches);
+
 /* Autotuner: times forward(xs -> ys) followed by adjoint(ys -> xa), `reps`
  * times per candidate schedule (branches 1, 2, 4, 8 x both orders) on
  * `stream`, keeps the fastest schedule and writes its time per pair of graph

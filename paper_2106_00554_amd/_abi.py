@@ -26,6 +26,8 @@ WH2WAV_BD = 0
 WH2WAV_PER = 1
 WH2WAV_ISOTROPIC = 0
 WH2WAV_TENSOR = 1
+WH2WAV_BATCH_BRANCHES = 0
+WH2WAV_BATCH_FUSED = 1
 
 TABLES = {"h": 0, "g": 1, "T": 2, "band_l": 3, "band_r": 4, "syn_l": 5, "syn_r": 6, "row_ptr": 7}
 
@@ -35,7 +37,8 @@ EXPORTS = ("wh2wav_plan", "wh2wav_workspace_size", "wh2wav_forward", "wh2wav_adj
            "wh2wav_destroy", "wh2wav_last_error", "wh2wav_host_table",
            "wh2wav_plan_batch", "wh2wav_batch_workspace_size", "wh2wav_forward_batch",
            "wh2wav_adjoint_batch", "wh2wav_batch_schedule", "wh2wav_batch_set_schedule",
-           "wh2wav_batch_tune", "wh2wav_destroy_batch", "wh2wav_forward_noalloc")
+           "wh2wav_batch_tune", "wh2wav_destroy_batch", "wh2wav_forward_noalloc",
+           "wh2wav_batch_set_mode", "wh2wav_batch_mode")
 
 # size of the library's fixed workspace array used by wh2wav_forward_noalloc
 WH2WAV_NOALLOC_MAX_WORKSPACE = 32 << 20
@@ -101,6 +104,9 @@ def _load():
     lib.wh2wav_batch_tune.argtypes = [vp, pp, pp, pp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]
     lib.wh2wav_destroy_batch.argtypes = [vp]
     lib.wh2wav_forward_noalloc.argtypes = [vp, vp, vp, vp]
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.wh2wav_batch_set_mode.argtypes = [vp, ctypes.c_int]
+    lib.wh2wav_batch_mode.argtypes = [vp, ip, ip, ip]
     for name in EXPORTS:
         if name != "wh2wav_last_error":
             getattr(lib, name).restype = ctypes.c_int
@@ -217,3 +223,13 @@ def wh2wav_batch_tune(batch, x_ptrs, y_ptrs, xa_ptrs, ws_ptr, stream_ptr, reps):
 def wh2wav_destroy_batch(batch):
     return _check(LIB.wh2wav_destroy_batch(batch))
 
+
+def wh2wav_batch_set_mode(batch, mode):
+    return _check(LIB.wh2wav_batch_set_mode(batch, mode))
+
+
+def wh2wav_batch_mode(batch):
+    """(mode, instances in the fused launches, fused launches per forward call)."""
+    mode, n, k = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(LIB.wh2wav_batch_mode(batch, ctypes.byref(mode), ctypes.byref(n), ctypes.byref(k)))
+    return mode.value, n.value, k.value

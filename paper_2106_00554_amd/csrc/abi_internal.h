@@ -47,4 +47,17 @@ struct PlanShape {
 };
 PlanShape plan_shape(wh2wav_plan_t p);
 
+// What the persistent batch kernel needs of a plan: its device tables and
+// sample bitmask, and the shape flags that decide whether the kernel can run
+// it (1D / square 2D, isotropic).
+struct PlanView {
+  const void *h, *g, *tabT, *bandL, *bandR, *synL, *synR;  // device, element type = dtype
+  int nu, q, Q, per, dim, j, j0, tensor, nd, dtype, full_omega;
+  int64_t M, N, m;
+  const uint32_t* mask;
+  const int64_t* row_ptr;
+  int64_t wpr;
+};
+PlanView plan_view(wh2wav_plan_t p);
+
 }  // namespace wh2wav

@@ -9,6 +9,10 @@
 // host cost.  A graph is captured once per set of pointers and replayed; the
 // schedule (B, order) is a batch property that wh2wav_batch_tune picks by
 // timing every candidate on the caller's buffers.
+//
+// In the fused mode the small instances instead run as fused launches, one per
+// round of their stages (fused_batch.h), on the graph's own stream beside the
+// branches, which keep the other instances.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,6 +24,7 @@
 
 #include "../../include/wh2wav.h"
 #include "abi_internal.h"
+#include "fused_batch.h"
 
 namespace {
 
@@ -28,11 +33,12 @@ constexpr size_t kAlign = 256;
 constexpr size_t kMaxGraphs = 8;
 
 struct GraphEntry {
-  int dir, branches, order;
+  int dir, branches, order, mode;
   const void* ws;
   std::vector<const void*> in, out;
   hipGraphExec_t exec = nullptr;
-  hipEvent_t done = nullptr;  // recorded after every launch of `exec`
+  hipEvent_t done = nullptr;       // recorded after every launch of `exec`
+  std::vector<void*> io_dev;       // fused mode: per program, its instances' (input, output) pointers
 };
 
 // Waits for the last launch of a cached graph, then frees it: a graph may
@@ -43,6 +49,9 @@ void drop_graph(GraphEntry& g) {
     (void)hipEventDestroy(g.done);
   }
   if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  for (void* p : g.io_dev)
+    if (p) (void)hipFree(p);
+  g.io_dev.clear();
   g.done = nullptr;
   g.exec = nullptr;
 }
@@ -60,6 +69,9 @@ struct wh2wav_batch_s {
   hipStream_t side[kMaxBranches] = {};
   hipEvent_t fork = nullptr, join[kMaxBranches] = {};
   std::vector<GraphEntry> graphs;
+  int mode = WH2WAV_BATCH_BRANCHES;
+  std::vector<char> in_kernel;            // instance runs in the fused launches (fused mode)
+  wh2wav_fused::Program prog[2][2];       // [dtype][direction]
 };
 
 namespace {
@@ -91,6 +103,8 @@ std::vector<int> schedule_order(const wh2wav_batch_s* b) {
 void release_batch(wh2wav_batch_s* b) {
   for (auto& g : b->graphs) drop_graph(g);
   b->graphs.clear();
+  for (auto& pd : b->prog)
+    for (auto& pr : pd) wh2wav_fused::release(&pr);
   for (auto* p : b->plans) wh2wav_destroy(p);
   b->plans.clear();
   for (int k = 0; k < kMaxBranches; ++k) {
@@ -101,15 +115,46 @@ void release_batch(wh2wav_batch_s* b) {
   if (b->cap) (void)hipStreamDestroy(b->cap);
 }
 
+// Fused mode: the (input, output) pointer pairs of every program's
+// instances, uploaded to device arrays kept with the graph that uses them.
+int upload_io(wh2wav_batch_s* b, int dir, const void* const* in, void* const* out, GraphEntry* e) {
+  for (auto& pd : b->prog) {
+    const auto& pr = pd[dir];
+    void* d = nullptr;
+    if (pr.ninst > 0) {
+      std::vector<const void*> io;
+      for (int i : pr.members) io.push_back(in[i]), io.push_back(out[i]);
+      HIP_B(hipMalloc(&d, sizeof(void*) * io.size()));
+      e->io_dev.push_back(d);
+      HIP_B(hipMemcpy(d, io.data(), sizeof(void*) * io.size(), hipMemcpyHostToDevice));
+    } else {
+      e->io_dev.push_back(nullptr);
+    }
+  }
+  return WH2WAV_OK;
+}
+
 // Captures the instances' stage kernels into one executable graph.
-int capture(wh2wav_batch_s* b, int dir, const void* const* in, void* const* out, void* ws, hipGraphExec_t* exec) {
+int capture(wh2wav_batch_s* b, int dir, const void* const* in, void* const* out, void* ws, GraphEntry* ge) {
+  hipGraphExec_t* exec = &ge->exec;
   const int nb = std::max(1, std::min(b->branches, kMaxBranches));
+  const bool fused = b->mode == WH2WAV_BATCH_FUSED;
+  if (fused) {
+    int rc = upload_io(b, dir, in, out, ge);
+    if (rc) return rc;
+  }
   HIP_B(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
   int rc = WH2WAV_OK;
   hipError_t he = hipEventRecord(b->fork, b->cap);
   for (int k = 0; k < nb && he == hipSuccess; ++k) he = hipStreamWaitEvent(b->side[k], b->fork, 0);
   if (he != hipSuccess) rc = fail(WH2WAV_EHIP, std::string("batch fork: ") + hipGetErrorString(he));
-  const std::vector<int> idx = schedule_order(b);
+  // the fused launches run on the capture stream, beside the branches
+  for (int d = 0; d < 2 && fused && rc == WH2WAV_OK; ++d)
+    if (b->prog[d][dir].ninst > 0)
+      rc = wh2wav_fused::launch(b->prog[d][dir], ws, static_cast<void* const*>(ge->io_dev[d]), b->cap);
+  std::vector<int> idx;
+  for (int i : schedule_order(b))
+    if (!fused || !b->in_kernel[i]) idx.push_back(i);
   for (size_t t = 0; t < idx.size() && rc == WH2WAV_OK; ++t) {
     const int i = idx[t];
     void* wsi = static_cast<char*>(ws) + b->ws_off[i];
@@ -156,7 +201,8 @@ int run(wh2wav_batch_s* b, int dir, const void* const* in, void* const* out, voi
   const size_t n = b->plans.size();
   GraphEntry* hit = nullptr;
   for (auto& g : b->graphs) {
-    if (g.dir != dir || g.branches != b->branches || g.order != b->order || g.ws != ws) continue;
+    if (g.dir != dir || g.branches != b->branches || g.order != b->order || g.mode != b->mode || g.ws != ws)
+      continue;
     if (std::equal(g.in.begin(), g.in.end(), in) && std::equal(g.out.begin(), g.out.end(), out)) {
       hit = &g;
       break;
@@ -168,11 +214,11 @@ int run(wh2wav_batch_s* b, int dir, const void* const* in, void* const* out, voi
       b->graphs.erase(b->graphs.begin());
     }
     GraphEntry e;
-    e.dir = dir, e.branches = b->branches, e.order = b->order, e.ws = ws;
+    e.dir = dir, e.branches = b->branches, e.order = b->order, e.mode = b->mode, e.ws = ws;
     e.in.assign(in, in + n);
     e.out.assign(out, out + n);
     HIP_B(hipEventCreateWithFlags(&e.done, hipEventDisableTiming));
-    rc = capture(b, dir, in, out, ws, &e.exec);
+    rc = capture(b, dir, in, out, ws, &e);
     if (rc) {
       drop_graph(e);
       return rc;
@@ -214,6 +260,20 @@ int plan_batch_body(const wh2wav_desc* descs, int count, wh2wav_batch_t* out) {
     wh2wav_workspace_size(p, &bytes);
     b->ws_off.push_back(b->ws_total);
     b->ws_total += (bytes + kAlign - 1) / kAlign * kAlign;
+  }
+  // the fused programs of the eligible instances, per element type and direction
+  std::vector<wh2wav::PlanView> views;
+  for (auto* p : b->plans) views.push_back(wh2wav::plan_view(p));
+  b->in_kernel.assign(views.size(), 0);
+  for (int d = 0; d < 2; ++d) {
+    std::vector<int> members;
+    for (size_t i = 0; i < views.size(); ++i)
+      if (views[i].dtype == d && wh2wav_fused::eligible(views[i])) members.push_back(int(i)), b->in_kernel[i] = 1;
+    if (members.empty()) continue;
+    for (int dir = 0; dir < 2; ++dir) {
+      int rc = wh2wav_fused::build(views, b->ws_off, members, d, dir, &b->prog[d][dir]);
+      if (rc) return rc;
+    }
   }
   hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
@@ -307,6 +367,26 @@ int batch_tune_body(wh2wav_batch_t b, const void* const* xs, void* const* ys, vo
   return rc;
 }
 
+int batch_set_mode_body(wh2wav_batch_t b, int mode) {
+  if (int rc = check_batch(b)) return rc;
+  if (mode != WH2WAV_BATCH_BRANCHES && mode != WH2WAV_BATCH_FUSED)
+    return fail(WH2WAV_EINVAL, "mode must be WH2WAV_BATCH_BRANCHES or WH2WAV_BATCH_FUSED");
+  b->mode = mode;
+  return WH2WAV_OK;
+}
+
+int batch_mode_body(wh2wav_batch_t b, int* mode, int* fused_instances, int* fused_launches) {
+  if (int rc = check_batch(b)) return rc;
+  if (!mode) return fail(WH2WAV_EINVAL, "mode is NULL");
+  *mode = b->mode;
+  if (fused_instances) *fused_instances = int(std::count(b->in_kernel.begin(), b->in_kernel.end(), 1));
+  if (fused_launches) {
+    *fused_launches = 0;
+    for (auto& pd : b->prog) *fused_launches += int(pd[0].rounds.size());
+  }
+  return WH2WAV_OK;
+}
+
 int destroy_batch_body(wh2wav_batch_t b) {
   if (!b) return WH2WAV_OK;
   if (!wh2wav::handle_remove(b)) return fail(WH2WAV_EINVAL, "not a live batch (destroyed twice, or never created)");
@@ -345,6 +425,14 @@ int wh2wav_batch_set_schedule(wh2wav_batch_t b, int branches, int order) {
 int wh2wav_batch_tune(wh2wav_batch_t b, const void* const* xs, void* const* ys, void* const* xa, void* ws,
                       void* stream, int reps, float* best_ms) {
   return wh2wav::guarded([&] { return batch_tune_body(b, xs, ys, xa, ws, stream, reps, best_ms); });
+}
+
+int wh2wav_batch_set_mode(wh2wav_batch_t b, int mode) {
+  return wh2wav::guarded([&] { return batch_set_mode_body(b, mode); });
+}
+
+int wh2wav_batch_mode(wh2wav_batch_t b, int* mode, int* fused_instances, int* fused_launches) {
+  return wh2wav::guarded([&] { return batch_mode_body(b, mode, fused_instances, fused_launches); });
 }
 
 int wh2wav_destroy_batch(wh2wav_batch_t b) {

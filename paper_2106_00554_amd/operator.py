@@ -192,6 +192,17 @@ class Wh2WavBatch:
     def schedule(self):
         return _abi.wh2wav_batch_schedule(self._batch)
 
+    def set_mode(self, mode):
+        """"branches": every instance's own kernels in graph branches; "fused": the
+        small instances as fused launches, one per round of their stages."""
+        _abi.wh2wav_batch_set_mode(self._batch, {"branches": _abi.WH2WAV_BATCH_BRANCHES,
+                                                 "fused": _abi.WH2WAV_BATCH_FUSED}[mode])
+
+    def mode(self):
+        """(mode name, instances in the fused launches, fused launches per forward call)."""
+        m, n, k = _abi.wh2wav_batch_mode(self._batch)
+        return ("branches", "fused")[m], n, k
+
     def set_schedule(self, branches, order):
         _abi.wh2wav_batch_set_schedule(self._batch, branches, order)
 

@@ -7,7 +7,11 @@
   new input values and synchronisations in between, each replay checked;
 * every schedule (branches, order) gives the same results (the autotuner's
   test is skipped: see test_tuner);
-* a new set of pointers captures a new graph.
+* a new set of pointers captures a new graph;
+* the fused mode (the small instances as fused launches, one per round of
+  their stages, the rest in branches): every instance equals its single plan
+  to rounding and the oracle, replays are bit for bit the same, and the batch
+  returns to the branch mode bit for bit.
 """
 import numpy as np
 import pytest
@@ -149,3 +153,109 @@ def test_batch_errors():
     with pytest.raises(_abi.Wh2WavError):
         b.set_schedule(9, 0)
     b.close()
+
+
+def _rel(u, v):
+    u, v = u.double(), v.double()
+    nv = float(torch.linalg.vector_norm(v))
+    return float(torch.linalg.vector_norm(u - v)) / (nv if nv > 0 else 1.0)
+
+
+@pytest.mark.skip(reason="the persistent queue kernel (one launch; workgroups taking (instance, stage, tile) "
+                         "items from an atomic counter and waiting on per-stage counters) did not finish in two "
+                         "GPU runs, the second with time-bounded waits; the cause was not found, so that design "
+                         "was removed and the fused rounds replace it (test_fused_mode)")
+def test_persistent_mode(setup):
+    from paper_2106_00554_amd.operator import Wh2WavBatch
+    specs, xs_np, _, singles, xs = setup
+    batch = Wh2WavBatch(specs)
+    batch.set_mode("persistent")
+    mode, in_kernel, _ = batch.mode()
+    # 1D lines up to 1024 values and 2D up to 512^2 with samples: instances 0, 3, 4, 5, 6, 8, 9
+    assert mode == "persistent" and in_kernel == 7
+    ys_ref, xa_ref = _eager(singles, xs)
+    ys = batch.new_outputs(0)
+    xa = batch.new_outputs(1)
+    first = None
+    for r in range(3):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        batch.forward(xs, ys)
+        batch.adjoint(ys_ref, xa)  # the single plans' samples: the adjoints see the same input
+        t1.record()
+        torch.cuda.synchronize()
+        print(f"[persistent] replay {r}: {t0.elapsed_time(t1):.3f} ms, aborted={batch.mode(aborted=True)[2]}",
+              flush=True)
+        _ = [torch.sum(y) for y in ys_ref]  # unrelated eager kernels between replays
+        for i, s in enumerate(specs):
+            tol = 1e-12 if s["dtype"] == F64 else 1e-5
+            assert _rel(ys[i], ys_ref[i]) <= tol, (r, i, "forward", _rel(ys[i], ys_ref[i]))
+            assert _rel(xa[i], xa_ref[i]) <= tol, (r, i, "adjoint", _rel(xa[i], xa_ref[i]))
+        snap = [t.clone() for t in ys + xa]
+        if first is None:
+            first = snap
+        else:
+            assert _same(snap, first), f"replay {r} differs from the first"
+    assert batch.mode(aborted=True)[2] == 0
+    # oracle tie-in through the persistent kernel: the small 2D FP64 instance
+    i = 5
+    s = specs[i]
+    blocks = op.Blocks2D(op.Config(s["nu"], s["j"], s["q"], s["j0"]))
+    y_ref = op.forward_2d_full(blocks, xs_np[i], s["omega"]).reshape(-1)
+    assert np.linalg.norm(ys[i].cpu().numpy() - y_ref) <= 1e-12 * np.linalg.norm(y_ref)
+    # back to the branches: bit for bit the single plans again
+    batch.set_mode("branches")
+    batch.forward(xs, ys)
+    batch.adjoint(ys, xa)
+    torch.cuda.synchronize()
+    assert _same(ys, ys_ref) and _same(xa, xa_ref)
+    batch.close()
+
+
+def test_fused_mode(setup):
+    from paper_2106_00554_amd.operator import Wh2WavBatch
+    specs, xs_np, _, singles, xs = setup
+    batch = Wh2WavBatch(specs)
+    batch.set_mode("fused")
+    mode, in_kernel, launches = batch.mode()
+    # 1D lines up to 1024 values and 2D up to 512^2 with samples: instances 0, 3, 4, 5, 6, 8, 9;
+    # FP32 rounds: copy-in, 2 x 6 levels, 2 passes (512^2 from J0 = 3); FP64: copy-in, 7 levels, pass (1D 1024)
+    # or copy-in, 2 x 7 levels, 2 passes (512^2 from J0 = 2)
+    assert mode == "fused" and in_kernel == 7 and launches == 15 + 17
+    ys_ref, xa_ref = _eager(singles, xs)
+    ys = batch.new_outputs(0)
+    xa = batch.new_outputs(1)
+    first = None
+    for r in range(3):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        batch.forward(xs, ys)
+        batch.adjoint(ys_ref, xa)  # the single plans' samples: the adjoints see the same input
+        t1.record()
+        torch.cuda.synchronize()
+        print(f"[fused] replay {r}: {t0.elapsed_time(t1):.3f} ms", flush=True)
+        _ = [torch.sum(y) for y in ys_ref]  # unrelated eager kernels between replays
+        for i, s in enumerate(specs):
+            tol = 1e-12 if s["dtype"] == F64 else 1e-5
+            assert _rel(ys[i], ys_ref[i]) <= tol, (r, i, "forward", _rel(ys[i], ys_ref[i]))
+            assert _rel(xa[i], xa_ref[i]) <= tol, (r, i, "adjoint", _rel(xa[i], xa_ref[i]))
+        snap = [t.clone() for t in ys + xa]
+        if first is None:
+            first = snap
+        else:
+            assert _same(snap, first), f"replay {r} differs from the first"
+    # oracle tie-in through the fused launches: the small 2D FP64 instance
+    i = 5
+    s = specs[i]
+    blocks = op.Blocks2D(op.Config(s["nu"], s["j"], s["q"], s["j0"]))
+    y_ref = op.forward_2d_full(blocks, xs[i].cpu().numpy(), s["omega"]).reshape(-1)  # xs as the replay test left them
+    assert np.linalg.norm(ys[i].cpu().numpy() - y_ref) <= 1e-12 * np.linalg.norm(y_ref)
+    # back to the branches: bit for bit the single plans again
+    batch.set_mode("branches")
+    batch.forward(xs, ys)
+    batch.adjoint(ys, xa)
+    torch.cuda.synchronize()
+    assert _same(ys, ys_ref) and _same(xa, xa_ref)
+    batch.close()
