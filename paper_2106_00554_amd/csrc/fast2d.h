@@ -15,6 +15,12 @@ struct Tables {
   const T* tabT;   // (2nu-1) * Q, index (l + nu - 1) * Q + s
   const T* bandL;  // (2nu-1) * nu * Q, index (p * nu + m) * Q + s
   const T* bandR;  // (2nu-1) * nu * Q
+  // the same bands, laid out so that the values one lane reads are
+  // contiguous (compile-time offsets from one address):
+  const T* bandLf;  // forward: index (s * (2nu-1) + p) * nu + m
+  const T* bandRf;
+  const T* bandLa;  // adjoint: index (s * nu + m) * (2nu-1) + p
+  const T* bandRa;
   const T* synL;   // (3nu-1) * 2nu
   const T* synR;   // (3nu-1) * 2nu
   int nu, q, Q;

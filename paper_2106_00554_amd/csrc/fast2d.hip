@@ -96,13 +96,21 @@ __device__ __forceinline__ void line_forward(const T (&xi)[R], T (&v)[R], int s,
   // table product wraps around the line, which is the periodised product.
   // Otherwise the boundary values are zeroed (the bands below add them).
   const bool bd = !t.per;
-  T eL[NU], eR[NU];
+  // e[m]: the boundary value that this lane's band row multiplies -- position
+  // m (register m % R of lane m / R) in the left band lanes 0..B-1, position
+  // M-1-m (register R-1-m % R of lane 63 - m / R) in the right band lanes
+  // 64-B..63.  With R >= NU both sit in lanes 0 and 63: one select and one
+  // lane exchange each.
+  T e[NU];
 #pragma unroll
   for (int m = 0; m < NU; ++m) {
-    // position m: register m % R of lane m / R; position M-1-m: register
-    // R-1-m % R of lane 63 - m / R
-    eL[m] = read_lane(xi[m % R], m / R);
-    eR[m] = read_lane(xi[R - 1 - m % R], 63 - m / R);
+    if constexpr (R >= NU) {
+      const T w = lane == 63 ? xi[R - 1 - m] : xi[m];
+      e[m] = shfl_from(w, lane < B ? 0 : 63);
+    } else {
+      const T a = read_lane(xi[m % R], m / R), b = read_lane(xi[R - 1 - m % R], 63 - m / R);
+      e[m] = lane < B ? a : b;
+    }
     // per-element selects (conditional stores would let the compiler merge
     // them into one dynamically indexed store and move x to scratch)
     x[m % R] = bd && lane == m / R ? T(0) : x[m % R];
@@ -114,34 +122,31 @@ __device__ __forceinline__ void line_forward(const T (&xi)[R], T (&v)[R], int s,
   table_product<T, R, NU>(x, v, tap, lane);
   if (bd) {
     // boundary bands (Prop. 4.2): positions p < B and p >= M - B
-    // lanes 0..B-1: left band row p = lane; lanes B..2B-1: right band row
-    // lane - B.  Loads are unconditional (clamped row) so they overlap.
+    // lanes 0..B-1: left band row p = lane; lanes 64-B..63: right band row
+    // lane - (64 - B).  Loads are unconditional (clamped row) so they overlap.
     T bv = T(0);
     {
-      const bool left = lane < B;
-      const int p = left ? lane : (lane < 2 * B ? lane - B : 0);
-      const T* band = left ? t.bandL : t.bandR;
+      const bool left = lane < B, right = lane >= 64 - B;
+      const int p = left ? lane : (right ? lane - (64 - B) : 0);
+      const T* band = (left ? t.bandLf : t.bandRf) + (s * B + p) * NU;  // this row's nu values
 #pragma unroll
-      for (int m = 0; m < NU; ++m) bv = fma(left ? eL[m] : eR[m], band[(p * NU + m) * Q + s], bv);
-      bv = lane < 2 * B ? bv : T(0);
+      for (int m = 0; m < NU; ++m) bv = fma(e[m], band[m], bv);
+      bv = left || right ? bv : T(0);
     }
     if constexpr (R >= B) {
-      // the bands sit in lanes 0 and 63: masked adds, one instruction each
-      T bl[B], br[B];
+      // the bands sit in lanes 0 and 63.  Register k of lane 0 takes lane k
+      // (left band row k for k < B, a zero lane beyond), of lane 63 lane
+      // 64 - R + k (right band row k - (R - B) for k >= R - B, a zero lane
+      // below), of every other lane the zero lane B + k: one lane exchange
+      // and one add per register that a band reaches.
+      const int base = lane == 0 ? 0 : (lane == 63 ? 64 - R : B);
 #pragma unroll
-      for (int e = 0; e < B; ++e) bl[e] = read_lane(bv, e), br[e] = read_lane(bv, B + e);
-      if (lane == 0) {
-#pragma unroll
-        for (int e = 0; e < B; ++e) v[e] += bl[e];
-      }
-      if (lane == 63) {
-#pragma unroll
-        for (int e = 0; e < B; ++e) v[R - B + e] += br[e];
-      }
+      for (int k = 0; k < R; ++k)
+        if (k < B || k >= R - B) v[k] += shfl_from(bv, base + k);
     } else {
 #pragma unroll
       for (int e = 0; e < B; ++e) {
-        const T a = read_lane(bv, e), b = read_lane(bv, B + e);
+        const T a = read_lane(bv, e), b = read_lane(bv, 64 - B + e);
         constexpr int M = 64 * R;
         const int pr = M - B + e;  // right band position
         v[e % R] += lane == e / R ? a : T(0);
@@ -166,6 +171,9 @@ __device__ __forceinline__ void line_adjoint(T (&v)[R], T (&acc)[R], T& eacc, in
   for (int li = 0; li < 2 * NU - 1; ++li) tap[li] = t.tabT[li * Q + s];
   table_product_t<T, R, NU>(v, acc, tap, lane);
   if (t.per) return;  // periodic: the wrapped correlation is the whole adjoint
+  // lanes 0..nu-1: left boundary column m = lane, against positions 0..B-1;
+  // lanes nu..2nu-1: right column lane - nu, against positions M-B..M-1
+  // (unconditional loads, clamped column)
   T rl[B], rr[B];
 #pragma unroll
   for (int e = 0; e < B; ++e) {
@@ -174,18 +182,13 @@ __device__ __forceinline__ void line_adjoint(T (&v)[R], T (&acc)[R], T& eacc, in
     rl[e] = read_lane(v[e % R], e / R);
     rr[e] = read_lane(v[pr % R], pr / R);
   }
-  // lanes 0..nu-1: left boundary column m = lane; lanes nu..2nu-1: right
-  // column lane - nu (unconditional loads, clamped column)
+  const bool left = lane < NU;
+  const int m = left ? lane : (lane < 2 * NU ? lane - NU : 0);
+  const T* band = (left ? t.bandLa : t.bandRa) + (s * NU + m) * B;  // this column's B values
   T el = T(0);
-  {
-    const bool left = lane < NU;
-    const int m = left ? lane : (lane < 2 * NU ? lane - NU : 0);
-    const T* band = left ? t.bandL : t.bandR;
 #pragma unroll
-    for (int p = 0; p < B; ++p) el = fma(band[(p * NU + m) * Q + s], left ? rl[p] : rr[p], el);
-    el = lane < 2 * NU ? el : T(0);
-  }
-  eacc += el;
+  for (int p = 0; p < B; ++p) el = fma(band[p], left ? rl[p] : rr[p], el);
+  eacc += lane < 2 * NU ? el : T(0);
 }
 
 // Boundary positions of acc take their values from eacc (not for the periodic
@@ -195,9 +198,16 @@ __device__ __forceinline__ void place_edges(T (&acc)[R], T eacc, int lane, int p
   if (per) return;
 #pragma unroll
   for (int m = 0; m < NU; ++m) {
-    const T a = read_lane(eacc, m), b = read_lane(eacc, NU + m);
-    acc[m % R] = lane == m / R ? a : acc[m % R];
-    acc[R - 1 - m % R] = lane == 63 - m / R ? b : acc[R - 1 - m % R];
+    if constexpr (R >= NU) {
+      // lane 0 takes column m from lane m, lane 63 column nu + m: one exchange
+      const T a = shfl_from(eacc, lane == 63 ? NU + m : m);
+      acc[m] = lane == 0 ? a : acc[m];
+      acc[R - 1 - m] = lane == 63 ? a : acc[R - 1 - m];
+    } else {
+      const T a = read_lane(eacc, m), b = read_lane(eacc, NU + m);
+      acc[m % R] = lane == m / R ? a : acc[m % R];
+      acc[R - 1 - m % R] = lane == 63 - m / R ? b : acc[R - 1 - m % R];
+    }
   }
 }
 
@@ -257,17 +267,34 @@ __global__ void __launch_bounds__(1024) k_rowpass_fwd(const T* __restrict__ Z, T
   const int64_t N = int64_t(M) * Q;
   {  // one wave per phase: the workgroup has Q waves
     const int s = wave;
-    T v[R];
-    line_forward<T, R, NU>(xi, v, s, t, lane);
-    // The line reaches LDS in two halves (lanes 0..31 hold the positions below
-    // M/2), each followed by the reads of the samples it holds: half a line
-    // of LDS per wave, so that more workgroups fit on a CU.
+    // the samples of this phase line are y[o .. o + cnt), in sequency order;
+    // pos holds each one's natural position (coalesced reads and writes)
     int64_t o = 0;
     int cnt = 0;
     if (!om.full) {
       o = om.seg_ptr[n1 * Q + s];
       cnt = int(om.seg_ptr[n1 * Q + s + 1] - o);
     }
+    const uint16_t* __restrict__ ps = om.pos + o;
+    T* __restrict__ ys = y + o;
+    // positions of samples t0 + lane + 64 u (-1 beyond the line's samples);
+    // the address within a half line is the same for both halves
+    int kk[4], ka[4];
+    auto positions = [&](int t0) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int tt = t0 + lane + 64 * u;
+        const int pv = int(ps[tt < cnt ? tt : cnt - 1]);  // cnt > 0 here
+        kk[u] = tt < cnt ? pv : -1;
+        ka[u] = LB::addr(pv & (HM - 1));
+      }
+    };
+    if (cnt > 0) positions(0);
+    T v[R];
+    line_forward<T, R, NU>(xi, v, s, t, lane);
+    // The line reaches LDS in two halves (lanes 0..31 hold the positions below
+    // M/2), each followed by the reads of the samples it holds: half a line
+    // of LDS per wave, so that more workgroups fit on a CU.
     for (int h = 0; h < 2; ++h) {
       if ((lane >> 5) == h) LB::store(buf, lane & 31, v);
       wave_sync();
@@ -278,22 +305,11 @@ __global__ void __launch_bounds__(1024) k_rowpass_fwd(const T* __restrict__ Z, T
           if ((k >> (LOGM - 1)) == h) yrow[b] = buf[LB::addr(k - h * HM)];
         }
       } else {
-        // the samples of this phase line are y[o .. o + cnt), in sequency
-        // order; pos holds each one's natural position (coalesced reads and
-        // writes)
-        const uint16_t* __restrict__ ps = om.pos + o;
-        T* __restrict__ ys = y + o;
         for (int t0 = 0; t0 < cnt; t0 += 256) {
-          int kk[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int tt = t0 + lane + 64 * u;
-            const int pv = int(ps[tt < cnt ? tt : cnt - 1]);  // cnt > 0 inside the loop
-            kk[u] = tt < cnt ? pv : -1;
-          }
+          if (t0 > 0 || (h == 1 && cnt > 256)) positions(t0);  // more than 256 samples: reload
 #pragma unroll
           for (int u = 0; u < 4; ++u)
-            if (kk[u] >= 0 && (kk[u] >> (LOGM - 1)) == h) ys[t0 + lane + 64 * u] = buf[LB::addr(kk[u] - h * HM)];
+            if (kk[u] >= 0 && (kk[u] >> (LOGM - 1)) == h) ys[t0 + lane + 64 * u] = buf[ka[u]];
         }
       }
       wave_sync();
@@ -368,13 +384,21 @@ __global__ void __launch_bounds__(1024) k_rowpass_adj(const T* __restrict__ y, T
     line_adjoint<T, R, NU>(v, acc, eacc, s, t, lane);
   }
   place_edges<T, R, NU>(acc, eacc, lane, t.per);
-  // cross-wave sum (waves that had no phase contribute zeros)
+  // cross-wave sum (waves that had no phase contribute zeros), a chunk of CW
+  // consecutive positions (contiguous in every wave's buffer) per thread
   LB::store(buf, lane, acc);
   __syncthreads();
-  for (int p = int(threadIdx.x); p < M; p += int(blockDim.x)) {
-    T sum = T(0);
-    for (int w = 0; w < nw; ++w) sum += bufs[w * BUF + LB::addr(p)];
-    Zt[r * M + p] = sum;
+  constexpr int CW = LB::CW;
+  for (int c = int(threadIdx.x); c < M / CW; c += int(blockDim.x)) {
+    const int a = LB::addr(c * CW);
+    T sum[CW], part[CW];
+    load_line<T, CW>(bufs + a, sum);
+    for (int w = 1; w < nw; ++w) {
+      load_line<T, CW>(bufs + w * BUF + a, part);
+#pragma unroll
+      for (int u = 0; u < CW; ++u) sum[u] += part[u];
+    }
+    store_line<T, CW>(Zt + r * M + c * CW, sum);
   }
 }
 

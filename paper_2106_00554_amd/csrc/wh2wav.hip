@@ -165,6 +165,7 @@ struct wh2wav_plan_s {
   int32_t* d_pos32 = nullptr;
   size_t off_h = 0, off_g = 0, off_T = 0, off_BL = 0, off_BR = 0, off_SL = 0, off_SR = 0;
   size_t off_T_ax[3] = {0, 0, 0}, off_BL_ax[3] = {0, 0, 0}, off_BR_ax[3] = {0, 0, 0};  // per-axis path
+  size_t off_BLf = 0, off_BRf = 0, off_BLa = 0, off_BRa = 0;  // band copies of the wave kernels
   int device = 0;             // the device current when the plan was made
 };
 
@@ -205,6 +206,8 @@ wh2wav_fast::Tables<T> fast_tables_of(const wh2wav_plan_s* p) {
   const Tables<T> a = tables_of<T>(p);
   wh2wav_fast::Tables<T> f;
   f.h = a.h, f.g = a.g, f.tabT = a.tabT, f.bandL = a.bandL, f.bandR = a.bandR, f.synL = a.synL, f.synR = a.synR;
+  const T* base = static_cast<const T*>(p->d_tables);
+  f.bandLf = base + p->off_BLf, f.bandRf = base + p->off_BRf, f.bandLa = base + p->off_BLa, f.bandRa = base + p->off_BRa;
   f.nu = a.nu, f.q = a.q, f.Q = a.Q, f.per = a.per;
   return f;
 }
@@ -699,6 +702,20 @@ int upload_tables(wh2wav_plan_s* p) {
   put(H.tabBR, &p->off_BR);
   put(H.synL, &p->off_SL);
   put(H.synR, &p->off_SR);
+  // bands in the layouts of the wave kernels (index maps in fast2d.h)
+  const int nu = H.nu, B = 2 * nu - 1, Q = H.Q;
+  std::vector<double> lf(H.tabBL.size()), rf(lf.size()), la(lf.size()), ra(lf.size());
+  for (int pp = 0; pp < B; ++pp)
+    for (int m = 0; m < nu; ++m)
+      for (int s = 0; s < Q; ++s) {
+        const size_t src = (size_t(pp) * nu + m) * Q + s;
+        lf[(size_t(s) * B + pp) * nu + m] = H.tabBL[src], rf[(size_t(s) * B + pp) * nu + m] = H.tabBR[src];
+        la[(size_t(s) * nu + m) * B + pp] = H.tabBL[src], ra[(size_t(s) * nu + m) * B + pp] = H.tabBR[src];
+      }
+  put(lf, &p->off_BLf);
+  put(rf, &p->off_BRf);
+  put(la, &p->off_BLa);
+  put(ra, &p->off_BRa);
   for (int a = 0; H.nd && a < H.dim; ++a) {
     put(H.tabT_ax[a], &p->off_T_ax[a]);
     put(H.tabBL_ax[a], &p->off_BL_ax[a]);
