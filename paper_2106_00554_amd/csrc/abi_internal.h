@@ -47,7 +47,7 @@ struct PlanShape {
 };
 PlanShape plan_shape(wh2wav_plan_t p);
 
-// What the persistent batch kernel needs of a plan: its device tables and
+// What the fused batch launches need of a plan: its device tables and
 // sample bitmask, and the shape flags that decide whether the kernel can run
 // it (1D / square 2D, isotropic).
 struct PlanView {

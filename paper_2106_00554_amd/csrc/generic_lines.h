@@ -1,7 +1,7 @@
 // Generic device code of the operator: one line of the 1D section per
 // workgroup, in LDS, for every shape; the one-level wavelet synthesis and
 // analysis (boundary-corrected and periodic); the index maps.  Used by the
-// plain kernels of the single-plan path and by the persistent batch kernel.
+// plain kernels of the single-plan path and by the fused batch launches.
 //
 // One 1D line of the operator in the scaling basis B_{phi,j} (the matrix of
 // Sec. 4, called G in Sec. 5) factors through the dyadic cells of [0, 1]:
@@ -154,18 +154,40 @@ __device__ T analysis_value_per(const T* __restrict__ src, int64_t es, int64_t o
   return acc;
 }
 
+// Natural-order Walsh-Hadamard transform of buf[0, M) in LDS by the whole
+// workgroup.  The butterflies of the index bits commute, so they run three
+// bits at a time: each work item loads the 8 values whose indices differ in
+// bits b .. b+2, applies the three butterfly stages in registers and stores
+// them back -- one barrier per three stages.  The last one or two bits, if
+// any, run as a radix-2 or radix-4 pass.
+template <typename T, int F>
+__device__ __forceinline__ void fwht_lds_pass(T* buf, int M, int h, int tid, int nthreads) {
+  for (int g = tid; g < M / F; g += nthreads) {
+    const int base = (g / h) * F * h + (g % h);
+    T v[F];
+#pragma unroll
+    for (int i = 0; i < F; ++i) v[i] = buf[base + i * h];
+#pragma unroll
+    for (int hh = 1; hh < F; hh <<= 1)
+#pragma unroll
+      for (int i = 0; i < F; ++i)
+        if ((i & hh) == 0) {
+          const T a = v[i], c = v[i + hh];
+          v[i] = a + c;
+          v[i + hh] = a - c;
+        }
+#pragma unroll
+    for (int i = 0; i < F; ++i) buf[base + i * h] = v[i];
+  }
+  __syncthreads();
+}
 
 template <typename T>
 __device__ void fwht_lds(T* buf, int M, int tid, int nthreads) {
-  for (int hl = 1; hl < M; hl <<= 1) {
-    for (int b = tid; b < M / 2; b += nthreads) {
-      const int i = ((b / hl) * 2 * hl) + (b % hl);
-      const T a = buf[i], c = buf[i + hl];
-      buf[i] = a + c;
-      buf[i + hl] = a - c;
-    }
-    __syncthreads();
-  }
+  int h = 1;
+  for (; h * 8 <= M; h *= 8) fwht_lds_pass<T, 8>(buf, M, h, tid, nthreads);
+  if (h * 4 == M) fwht_lds_pass<T, 4>(buf, M, h, tid, nthreads);
+  else if (h * 2 == M) fwht_lds_pass<T, 2>(buf, M, h, tid, nthreads);
 }
 
 // Exclusive prefix of popcounts of `words` mask words into pre[] (LDS).
