@@ -401,6 +401,82 @@ __device__ __forceinline__ TileLds<T> load_tables(const Tables<T>& t, T* tab_lds
   return L;
 }
 
+// Synthesis levels j0 .. kc-1 of a line held in LDS by the whole workgroup:
+// a = [a_j0 | d_j0 | ... | d_{kc-1}] (2^kc values) becomes the scaling
+// coefficients at level kc; b is scratch of 2^kc values.  One output pair per
+// work item (twice the items of two-pair runs and half the dependent chain).
+// Every level ends with a barrier.
+template <typename T, int NU>
+__device__ void synth_levels_lds(T* a, T* b, int j0, int kc, const TileLds<T>& tl, const T (&hr)[2 * NU],
+                                 const T (&gr)[2 * NU]) {
+  const int tid = int(threadIdx.x), nt = int(blockDim.x);
+  constexpr int CP = 1, LO = synth_lo<NU>();  // one pair per item: twice the items, half the chain
+  for (int k = j0; k < kc; ++k) {
+    const int half = 1 << k, runs = (half + CP - 1) / CP;
+    for (int item = tid; item < runs; item += nt) {
+      const int i0 = item * CP;
+      T* yo = b + 2 * i0;
+      if (pair_is_interior<NU>(i0, half) && pair_is_interior<NU>(i0 + CP - 1, half)) {
+        T e[CP], o[CP];
+        synth_run<T, NU, CP>(a + i0 + LO, a + half + i0 + LO, 1, hr, gr, e, o);
+#pragma unroll
+        for (int p = 0; p < CP; ++p) yo[2 * p] = e[p], yo[2 * p + 1] = o[p];
+      } else if (half >= CP) {
+        T e[CP], o[CP];
+        synth_run_edge<T, NU, CP>(a, a + half, 1, 0, half - 1, i0, half, hr, gr, tl.sLs, tl.sRs, e, o);
+#pragma unroll
+        for (int p = 0; p < CP; ++p) yo[2 * p] = e[p], yo[2 * p + 1] = o[p];
+      } else {
+        auto A = [&](int m) { return a[m]; };
+        auto D = [&](int m) { return a[half + m]; };
+        for (int p = 0; p < CP && i0 + p < half; ++p) {
+          yo[2 * p] = synth_at<T, NU>(2 * (i0 + p), half, tl.hs, tl.gs, tl.sLs, tl.sRs, A, D);
+          yo[2 * p + 1] = synth_at<T, NU>(2 * (i0 + p) + 1, half, tl.hs, tl.gs, tl.sLs, tl.sRs, A, D);
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < 2 * half; i += nt) a[i] = b[i];
+    __syncthreads();
+  }
+}
+
+// Its transpose: analysis levels kc-1 .. j0 of the line a (2^kc values) into
+// [a_j0 | d_j0 | ... | d_{kc-1}], in a; b is scratch.  Every level ends with
+// a barrier.
+template <typename T, int NU>
+__device__ void analysis_levels_lds(T* a, T* b, int j0, int kc, const TileLds<T>& tl, const T (&hr)[2 * NU],
+                                    const T (&gr)[2 * NU]) {
+  const int tid = int(threadIdx.x), nt = int(blockDim.x);
+  constexpr int CP = 1;  // one output pair per item
+  for (int k = kc - 1; k >= j0; --k) {
+    const int half = 1 << k, size = 2 * half, runs = (half + CP - 1) / CP;
+    for (int item = tid; item < runs; item += nt) {
+      const int m0 = item * CP;
+      if (m0 >= NU && m0 + CP - 1 < half - NU) {
+        T av[CP], dv[CP];
+        analysis_run<T, NU, CP>(a + 2 * m0 - NU + 1, 1, hr, gr, av, dv);
+#pragma unroll
+        for (int p = 0; p < CP; ++p) b[m0 + p] = av[p], b[half + m0 + p] = dv[p];
+      } else if (half >= CP) {
+        T av[CP], dv[CP];
+        analysis_run_edge<T, NU, CP>(a, 1, 0, size - 1, m0, half, hr, gr, tl.sLs, tl.sRs, av, dv);
+#pragma unroll
+        for (int p = 0; p < CP; ++p) b[m0 + p] = av[p], b[half + m0 + p] = dv[p];
+      } else {
+        auto X = [&](int n) { return a[n]; };
+        for (int p = 0; p < CP && m0 + p < half; ++p) {
+          b[m0 + p] = analysis_at<T, NU>(m0 + p, half, tl.hs, tl.gs, tl.sLs, tl.sRs, X);
+          b[half + m0 + p] = analysis_at<T, NU>(half + m0 + p, half, tl.hs, tl.gs, tl.sLs, tl.sRs, X);
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < size; i += nt) a[i] = b[i];
+    __syncthreads();
+  }
+}
+
 template <int NU>
 constexpr int tab_lds_size() {
   return 4 * NU + 2 * (3 * NU - 1) * 2 * NU;

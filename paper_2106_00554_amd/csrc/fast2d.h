@@ -55,6 +55,17 @@ hipError_t idwt2d(const T* x, T* outT, T* s0, T* s1, int64_t M, int j0, int j, c
 // Its transpose: xi'^T (inT) -> quadtree x.
 template <typename T>
 hipError_t dwt2d(const T* inT, T* x, T* s0, T* s1, int64_t M, int j0, int j, const Tables<T>& t, hipStream_t st);
+// The 1D operator on one line of M = 2^logm <= 2048 values in one launch per
+// direction (wavelet levels in LDS fused with the line transform): whether
+// (element size, log2 M, nu, q) fits, and the two directions (x, y device
+// arrays of M and m values; J0 = j0).
+bool line1d_fused(int elem_bytes, int logm, int nu, int q);
+template <typename T>
+hipError_t line1d_fwd_fused(const T* x, T* y, int j0, int logm, const Tables<T>& t, const Omega& om,
+                            hipStream_t st);
+template <typename T>
+hipError_t line1d_adj_fused(const T* y, T* x, int j0, int logm, const Tables<T>& t, const Omega& om,
+                            hipStream_t st);
 // One-time setup (dynamic LDS limits) for the line kernels of (log2 M, nu).
 template <typename T>
 hipError_t prepare_lines(int logm, int nu);

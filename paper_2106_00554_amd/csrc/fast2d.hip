@@ -20,6 +20,9 @@
 // every global access is a contiguous segment; the forward one runs two
 // phases per workgroup, the adjoint fetches the next phase's rows while the
 // current one computes.
+#include <algorithm>
+
+#include "dwt_lines.h"
 #include "fast2d.h"
 #include "wave_ops.h"
 
@@ -248,53 +251,43 @@ struct LineBuf {
 };
 
 // ------------------------------------------------------------- row passes
-template <typename T, int LOGM, int NU>
-__global__ void __launch_bounds__(1024) k_rowpass_fwd(const T* __restrict__ Z, T* __restrict__ y, Tables<T> t,
-                                                     Omega om) {
-  constexpr int M = 1 << LOGM, LOG_R = LOGM - 6, R = 1 << LOG_R;
-  constexpr int HM = M / 2;  // LDS per wave: half a line
+// The gather of one phase line s of Omega row n1: the samples are
+// y[o .. o + cnt), in sequency order, and pos holds each one's natural
+// position (coalesced reads and writes).  prepare() loads the first 256
+// positions, so that their latency overlaps the line transform; run() puts
+// the line into LDS in two halves (lanes 0..31 hold the positions below M/2),
+// each followed by the reads of the samples it holds: half a line of LDS per
+// wave, so that more workgroups fit on a CU.
+template <typename T, int LOGM>
+struct PhaseGather {
+  static constexpr int M = 1 << LOGM, R = M / 64, HM = M / 2;
   using LB = LineBuf<R>;
-  extern __shared__ unsigned char smem_raw[];
-  const int lane = lane_id();
-  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
-  const int Q = t.Q;
-  T* buf = reinterpret_cast<T*>(smem_raw) + wave * HM;
-  const int64_t r = blockIdx.x;
-  T xi[R];
-  load_line<T, R>(Z + r * M + lane * R, xi);
-  const uint32_t s1 = uint32_t(r >> LOGM), k1 = uint32_t(r & (M - 1));
-  const int64_t n1 = int64_t(s1) * M + sequency_of(k1, s1, LOGM);
-  const int64_t N = int64_t(M) * Q;
-  {  // one wave per phase: the workgroup has Q waves
-    const int s = wave;
-    // the samples of this phase line are y[o .. o + cnt), in sequency order;
-    // pos holds each one's natural position (coalesced reads and writes)
+  const uint16_t* ps = nullptr;
+  T* ys = nullptr;
+  int cnt = 0;
+  int kk[4], ka[4];  // positions of samples t0 + lane + 64 u (-1 beyond); their address within a half
+  __device__ __forceinline__ void positions(int t0, int lane) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int tt = t0 + lane + 64 * u;
+      const int pv = int(ps[tt < cnt ? tt : cnt - 1]);  // cnt > 0 here
+      kk[u] = tt < cnt ? pv : -1;
+      ka[u] = LB::addr(pv & (HM - 1));
+    }
+  }
+  __device__ __forceinline__ void prepare(const Omega& om, T* y, int64_t n1, int s, int Q, int lane) {
     int64_t o = 0;
-    int cnt = 0;
     if (!om.full) {
       o = om.seg_ptr[n1 * Q + s];
       cnt = int(om.seg_ptr[n1 * Q + s + 1] - o);
     }
-    const uint16_t* __restrict__ ps = om.pos + o;
-    T* __restrict__ ys = y + o;
-    // positions of samples t0 + lane + 64 u (-1 beyond the line's samples);
-    // the address within a half line is the same for both halves
-    int kk[4], ka[4];
-    auto positions = [&](int t0) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int tt = t0 + lane + 64 * u;
-        const int pv = int(ps[tt < cnt ? tt : cnt - 1]);  // cnt > 0 here
-        kk[u] = tt < cnt ? pv : -1;
-        ka[u] = LB::addr(pv & (HM - 1));
-      }
-    };
-    if (cnt > 0) positions(0);
-    T v[R];
-    line_forward<T, R, NU>(xi, v, s, t, lane);
-    // The line reaches LDS in two halves (lanes 0..31 hold the positions below
-    // M/2), each followed by the reads of the samples it holds: half a line
-    // of LDS per wave, so that more workgroups fit on a CU.
+    ps = om.pos + o;
+    ys = y + o;
+    if (cnt > 0) positions(0, lane);
+  }
+  __device__ __forceinline__ void run(const T (&v)[R], T* buf, const Omega& om, T* y, int64_t n1, int s, int Q,
+                                      int lane) {
+    const int64_t N = int64_t(M) * Q;
     for (int h = 0; h < 2; ++h) {
       if ((lane >> 5) == h) LB::store(buf, lane & 31, v);
       wave_sync();
@@ -306,7 +299,7 @@ __global__ void __launch_bounds__(1024) k_rowpass_fwd(const T* __restrict__ Z, T
         }
       } else {
         for (int t0 = 0; t0 < cnt; t0 += 256) {
-          if (t0 > 0 || (h == 1 && cnt > 256)) positions(t0);  // more than 256 samples: reload
+          if (t0 > 0 || (h == 1 && cnt > 256)) positions(t0, lane);  // more than 256 samples: reload
 #pragma unroll
           for (int u = 0; u < 4; ++u)
             if (kk[u] >= 0 && (kk[u] >> (LOGM - 1)) == h) ys[t0 + lane + 64 * u] = buf[ka[u]];
@@ -315,6 +308,79 @@ __global__ void __launch_bounds__(1024) k_rowpass_fwd(const T* __restrict__ Z, T
       wave_sync();
     }
   }
+};
+
+// The scatter of phase line s of Omega row n1 into a line of LDS (zero where
+// Omega has no sample), then the line into v (layout A).
+template <typename T, int LOGM>
+__device__ __forceinline__ void scatter_phase(const T* __restrict__ y, const Omega& om, int64_t n1, int s, int Q,
+                                              T* buf, T (&v)[1 << (LOGM - 6)], int lane) {
+  constexpr int M = 1 << LOGM, R = M / 64;
+  using LB = LineBuf<R>;
+  const int64_t N = int64_t(M) * Q;
+  if (om.full) {
+    const T* yrow = y + n1 * N + int64_t(s) * M;
+    constexpr int NB = M / 64;
+    T rv[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) rv[i] = yrow[lane + 64 * i];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const uint32_t k = natural_of(uint32_t(lane + 64 * i), uint32_t(s), LOGM);
+      buf[LB::addr(int(k))] = rv[i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = T(0);
+    LB::store(buf, lane, v);
+    const int64_t o = om.seg_ptr[n1 * Q + s];
+    const int cnt = int(om.seg_ptr[n1 * Q + s + 1] - o);
+    const uint16_t* __restrict__ ps = om.pos + o;
+    const T* __restrict__ ys = y + o;
+    wave_sync();  // zero fill of buf before the scatter
+    // coalesced reads of this phase line's samples and their positions
+    for (int t0 = 0; t0 < cnt; t0 += 256) {
+      int kk[4];
+      T rv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int tt = t0 + lane + 64 * u;
+        const int pv = int(ps[tt < cnt ? tt : cnt - 1]);  // cnt > 0 inside the loop
+        kk[u] = tt < cnt ? pv : -1;
+        const T yv = ys[tt < cnt ? tt : cnt - 1];
+        rv[u] = tt < cnt ? yv : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (kk[u] >= 0) buf[LB::addr(kk[u])] = rv[u];
+    }
+  }
+  wave_sync();
+  LB::load(buf, lane, v);
+  wave_sync();
+}
+
+template <typename T, int LOGM, int NU>
+__global__ void __launch_bounds__(1024) k_rowpass_fwd(const T* __restrict__ Z, T* __restrict__ y, Tables<T> t,
+                                                     Omega om) {
+  constexpr int M = 1 << LOGM, LOG_R = LOGM - 6, R = 1 << LOG_R;
+  constexpr int HM = M / 2;  // LDS per wave: half a line
+  extern __shared__ unsigned char smem_raw[];
+  const int lane = lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int Q = t.Q;
+  T* buf = reinterpret_cast<T*>(smem_raw) + wave * HM;
+  const int64_t r = blockIdx.x;
+  T xi[R];
+  load_line<T, R>(Z + r * M + lane * R, xi);
+  const uint32_t s1 = uint32_t(r >> LOGM), k1 = uint32_t(r & (M - 1));
+  const int64_t n1 = int64_t(s1) * M + sequency_of(k1, s1, LOGM);
+  // one wave per phase: the workgroup has Q waves
+  PhaseGather<T, LOGM> g;
+  g.prepare(om, y, n1, wave, Q, lane);
+  T v[R];
+  line_forward<T, R, NU>(xi, v, wave, t, lane);
+  g.run(v, buf, om, y, n1, wave, Q, lane);
 }
 
 template <typename T, int LOGM, int NU>
@@ -333,55 +399,14 @@ __global__ void __launch_bounds__(1024) k_rowpass_adj(const T* __restrict__ y, T
   const int64_t r = blockIdx.x;
   const uint32_t s1 = uint32_t(r >> LOGM), k1 = uint32_t(r & (M - 1));
   const int64_t n1 = int64_t(s1) * M + sequency_of(k1, s1, LOGM);
-  const int64_t N = int64_t(M) * Q;
   T acc[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) acc[i] = T(0);
   T eacc = T(0);
   {  // one wave per phase: the workgroup has Q waves
-    const int s = wave;
     T v[R];
-    if (om.full) {
-      const T* yrow = y + n1 * N + int64_t(s) * M;
-      constexpr int NB = M / 64;
-      T rv[NB];
-#pragma unroll
-      for (int i = 0; i < NB; ++i) rv[i] = yrow[lane + 64 * i];
-#pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        const uint32_t k = natural_of(uint32_t(lane + 64 * i), uint32_t(s), LOGM);
-        buf[LB::addr(int(k))] = rv[i];
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < R; ++i) v[i] = T(0);
-      LB::store(buf, lane, v);
-      const int64_t o = om.seg_ptr[n1 * Q + s];
-      const int cnt = int(om.seg_ptr[n1 * Q + s + 1] - o);
-      const uint16_t* __restrict__ ps = om.pos + o;
-      const T* __restrict__ ys = y + o;
-      wave_sync();  // zero fill of buf before the scatter
-      // coalesced reads of this phase line's samples and their positions
-      for (int t0 = 0; t0 < cnt; t0 += 256) {
-        int kk[4];
-        T rv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int tt = t0 + lane + 64 * u;
-          const int pv = int(ps[tt < cnt ? tt : cnt - 1]);  // cnt > 0 inside the loop
-          kk[u] = tt < cnt ? pv : -1;
-          const T yv = ys[tt < cnt ? tt : cnt - 1];
-          rv[u] = tt < cnt ? yv : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (kk[u] >= 0) buf[LB::addr(kk[u])] = rv[u];
-      }
-    }
-    wave_sync();
-    LB::load(buf, lane, v);
-    wave_sync();
-    line_adjoint<T, R, NU>(v, acc, eacc, s, t, lane);
+    scatter_phase<T, LOGM>(y, om, n1, wave, Q, buf, v, lane);
+    line_adjoint<T, R, NU>(v, acc, eacc, wave, t, lane);
   }
   place_edges<T, R, NU>(acc, eacc, lane, t.per);
   // cross-wave sum (waves that had no phase contribute zeros), a chunk of CW
@@ -400,6 +425,98 @@ __global__ void __launch_bounds__(1024) k_rowpass_adj(const T* __restrict__ y, T
     }
     store_line<T, CW>(Zt + r * M + c * CW, sum);
   }
+}
+
+// ------------------------------------------------- one-dimensional lines
+// The 1D operator on lines of M = 2^LOGM <= 2048 values in one launch per
+// direction: the wavelet levels on the line in LDS (all of them, one
+// workgroup of 1024 threads), and the row-pass line transform of each phase
+// in its own wave with the gather (forward), or the scatter, the transposed
+// line transform, the cross-wave sum and the analysis levels (adjoint).
+
+// LDS of the fused kernels, in elements (besides the static table copy).
+template <int LOGM>
+constexpr int line1d_fwd_lds(int Q) {
+  return (1 << LOGM) + ((Q << LOGM) / 2 > (1 << LOGM) ? (Q << LOGM) / 2 : (1 << LOGM));
+}
+template <int LOGM>
+constexpr int line1d_adj_lds(int Q) {
+  return Q << LOGM;
+}
+
+template <typename T, int LOGM, int NU>
+__global__ void __launch_bounds__(1024) k_line1d_fwd(const T* __restrict__ x, T* __restrict__ y, int j0, Tables<T> t,
+                                                    Omega om) {
+  constexpr int M = 1 << LOGM, R = M / 64, HM = M / 2;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ T tab_lds[lines::tab_lds_size<NU>()];
+  T hr[2 * NU], gr[2 * NU];
+  const lines::TileLds<T> tl = lines::load_tables<T, NU>(t, tab_lds, hr, gr);
+  const int tid = int(threadIdx.x), lane = lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int Q = t.Q;
+  T* a = reinterpret_cast<T*>(smem_raw);  // the line; then a half line per phase wave from a + M
+  T* b = a + M;
+  PhaseGather<T, LOGM> g;
+  if (wave < Q) g.prepare(om, y, 0, wave, Q, lane);
+  for (int i = tid; i < M; i += int(blockDim.x)) a[i] = x[i];
+  __syncthreads();
+  lines::synth_levels_lds<T, NU>(a, b, j0, LOGM, tl, hr, gr);
+  __syncthreads();
+  if (wave >= Q) return;
+  T xi[R];
+  load_line<T, R>(a + lane * R, xi);
+  T v[R];
+  line_forward<T, R, NU>(xi, v, wave, t, lane);
+  g.run(v, b + wave * HM, om, y, 0, wave, Q, lane);
+}
+
+template <typename T, int LOGM, int NU>
+__global__ void __launch_bounds__(1024) k_line1d_adj(const T* __restrict__ y, T* __restrict__ x, int j0, Tables<T> t,
+                                                    Omega om) {
+  constexpr int M = 1 << LOGM, R = M / 64;
+  using LB = LineBuf<R>;
+  constexpr int CW = LB::CW;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ T tab_lds[lines::tab_lds_size<NU>()];
+  T hr[2 * NU], gr[2 * NU];
+  const lines::TileLds<T> tl = lines::load_tables<T, NU>(t, tab_lds, hr, gr);
+  const int tid = int(threadIdx.x), lane = lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int Q = t.Q;
+  T* bufs = reinterpret_cast<T*>(smem_raw);  // a line per phase wave; then the line and scratch
+  if (wave < Q) {
+    T* buf = bufs + wave * M;
+    T v[R], acc[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) acc[i] = T(0);
+    T eacc = T(0);
+    scatter_phase<T, LOGM>(y, om, 0, wave, Q, buf, v, lane);
+    line_adjoint<T, R, NU>(v, acc, eacc, wave, t, lane);
+    place_edges<T, R, NU>(acc, eacc, lane, t.per);
+    LB::store(buf, lane, acc);
+  }
+  __syncthreads();
+  // cross-wave sum into registers (a chunk of CW positions per thread), then
+  // the line in natural order into the first M elements
+  T sum[CW];
+  const int c = tid;
+  if (c < M / CW) {
+    const int ad = LB::addr(c * CW);
+    T part[CW];
+    load_line<T, CW>(bufs + ad, sum);
+    for (int w = 1; w < Q; ++w) {
+      load_line<T, CW>(bufs + w * M + ad, part);
+#pragma unroll
+      for (int u = 0; u < CW; ++u) sum[u] += part[u];
+    }
+  }
+  __syncthreads();
+  if (c < M / CW) store_line<T, CW>(bufs + c * CW, sum);
+  __syncthreads();
+  lines::analysis_levels_lds<T, NU>(bufs, bufs + M, j0, LOGM, tl, hr, gr);
+  __syncthreads();
+  for (int i = tid; i < M; i += int(blockDim.x)) x[i] = bufs[i];
 }
 
 // ---------------------------------------------------------- column passes
@@ -642,6 +759,19 @@ hipError_t launch_colpass_adj(const T* Zt, T* xiT, const Tables<T>& t, hipStream
   return hipGetLastError();
 }
 
+template <typename T, int LOGM, int NU>
+hipError_t launch_line1d_fwd(const T* x, T* y, int j0, const Tables<T>& t, const Omega& om, hipStream_t st) {
+  const size_t smem = size_t(line1d_fwd_lds<LOGM>(t.Q)) * sizeof(T);
+  hipLaunchKernelGGL((k_line1d_fwd<T, LOGM, NU>), dim3(1), dim3(1024), smem, st, x, y, j0, t, om);
+  return hipGetLastError();
+}
+template <typename T, int LOGM, int NU>
+hipError_t launch_line1d_adj(const T* y, T* x, int j0, const Tables<T>& t, const Omega& om, hipStream_t st) {
+  const size_t smem = size_t(line1d_adj_lds<LOGM>(t.Q)) * sizeof(T);
+  hipLaunchKernelGGL((k_line1d_adj<T, LOGM, NU>), dim3(1), dim3(1024), smem, st, y, x, j0, t, om);
+  return hipGetLastError();
+}
+
 // Supported (log2 M, nu).  Lines of M = 128 .. 2048 values (R = 2 .. 32 per
 // lane); boundary values and the table-product halo may span several lanes.
 #define WH2WAV_FAST_CASES(X)                                                       \
@@ -661,6 +791,31 @@ bool supported(int elem_bytes, int logm, int nu, int q) {
   WH2WAV_FAST_CASES(X)
 #undef X
   return false;
+}
+
+bool line1d_fused(int elem_bytes, int logm, int nu, int q) {
+  if (!supported(elem_bytes, logm, nu, q) || logm > 11) return false;
+  const int Q = 1 << q, M = 1 << logm;
+  const long long tab = (4LL * nu + 2LL * (3 * nu - 1) * 2 * nu) * elem_bytes;
+  const long long fwd = (M + std::max((Q * M) / 2, M)) * 1LL * elem_bytes, adj = 1LL * Q * M * elem_bytes;
+  return std::max(fwd, adj) + tab <= 160 * 1024;
+}
+
+template <typename T>
+hipError_t line1d_fwd_fused(const T* x, T* y, int j0, int logm, const Tables<T>& t, const Omega& om,
+                            hipStream_t st) {
+#define X(L, V) if (logm == L && t.nu == V) return launch_line1d_fwd<T, L, V>(x, y, j0, t, om, st);
+  WH2WAV_FAST_CASES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+template <typename T>
+hipError_t line1d_adj_fused(const T* y, T* x, int j0, int logm, const Tables<T>& t, const Omega& om,
+                            hipStream_t st) {
+#define X(L, V) if (logm == L && t.nu == V) return launch_line1d_adj<T, L, V>(y, x, j0, t, om, st);
+  WH2WAV_FAST_CASES(X)
+#undef X
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -705,6 +860,13 @@ hipError_t prepare_lines_impl() {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_colpass_adj<T, LOGM, NU, colpass_adj_groups<T, LOGM, NU>()>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  const int tab = lines::tab_lds_size<NU>() * int(sizeof(T));  // the static table copy of the fused 1D kernels
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_line1d_fwd<T, LOGM, NU>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lim - tab);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_line1d_adj<T, LOGM, NU>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lim - tab);
   return e;
 }
 
@@ -736,6 +898,14 @@ template hipError_t colpass_fwd<float>(const float*, float*, int, const Tables<f
 template hipError_t colpass_fwd<double>(const double*, double*, int, const Tables<double>&, hipStream_t);
 template hipError_t colpass_adj<float>(const float*, float*, int, const Tables<float>&, hipStream_t);
 template hipError_t colpass_adj<double>(const double*, double*, int, const Tables<double>&, hipStream_t);
+template hipError_t line1d_fwd_fused<float>(const float*, float*, int, int, const Tables<float>&, const Omega&,
+                                            hipStream_t);
+template hipError_t line1d_fwd_fused<double>(const double*, double*, int, int, const Tables<double>&, const Omega&,
+                                             hipStream_t);
+template hipError_t line1d_adj_fused<float>(const float*, float*, int, int, const Tables<float>&, const Omega&,
+                                            hipStream_t);
+template hipError_t line1d_adj_fused<double>(const double*, double*, int, int, const Tables<double>&, const Omega&,
+                                             hipStream_t);
 template hipError_t transpose<float>(const float*, float*, int64_t, hipStream_t);
 template hipError_t transpose<double>(const double*, double*, int64_t, hipStream_t);
 

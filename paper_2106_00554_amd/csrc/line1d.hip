@@ -48,35 +48,7 @@ __global__ void __launch_bounds__(1024) k_synth1d_coarse(const T* __restrict__ x
   T* b = a + S;
   for (int i = tid; i < S; i += 1024) a[i] = x[i];
   __syncthreads();
-  constexpr int CP = 1, LO = synth_lo<NU>();  // one pair per item: twice the items, half the chain
-  for (int k = j0; k < kc; ++k) {
-    const int half = 1 << k, runs = (half + CP - 1) / CP;
-    for (int item = tid; item < runs; item += 1024) {
-      const int i0 = item * CP;
-      T* yo = b + 2 * i0;
-      if (pair_is_interior<NU>(i0, half) && pair_is_interior<NU>(i0 + CP - 1, half)) {
-        T e[CP], o[CP];
-        synth_run<T, NU, CP>(a + i0 + LO, a + half + i0 + LO, 1, hr, gr, e, o);
-#pragma unroll
-        for (int p = 0; p < CP; ++p) yo[2 * p] = e[p], yo[2 * p + 1] = o[p];
-      } else if (half >= CP) {
-        T e[CP], o[CP];
-        synth_run_edge<T, NU, CP>(a, a + half, 1, 0, half - 1, i0, half, hr, gr, tl.sLs, tl.sRs, e, o);
-#pragma unroll
-        for (int p = 0; p < CP; ++p) yo[2 * p] = e[p], yo[2 * p + 1] = o[p];
-      } else {
-        auto A = [&](int m) { return a[m]; };
-        auto D = [&](int m) { return a[half + m]; };
-        for (int p = 0; p < CP && i0 + p < half; ++p) {
-          yo[2 * p] = synth_at<T, NU>(2 * (i0 + p), half, tl.hs, tl.gs, tl.sLs, tl.sRs, A, D);
-          yo[2 * p + 1] = synth_at<T, NU>(2 * (i0 + p) + 1, half, tl.hs, tl.gs, tl.sLs, tl.sRs, A, D);
-        }
-      }
-    }
-    __syncthreads();
-    for (int i = tid; i < 2 * half; i += 1024) a[i] = b[i];
-    __syncthreads();
-  }
+  synth_levels_lds<T, NU>(a, b, j0, kc, tl, hr, gr);
   for (int i = tid; i < S; i += 1024) out[i] = a[i];
 }
 
@@ -94,33 +66,7 @@ __global__ void __launch_bounds__(1024) k_analysis1d_coarse(const T* __restrict_
   T* b = a + S;
   for (int i = tid; i < S; i += 1024) a[i] = in[i];
   __syncthreads();
-  constexpr int CP = 1;  // one output pair per item
-  for (int k = kc - 1; k >= j0; --k) {
-    const int half = 1 << k, size = 2 * half, runs = (half + CP - 1) / CP;
-    for (int item = tid; item < runs; item += 1024) {
-      const int m0 = item * CP;
-      if (m0 >= NU && m0 + CP - 1 < half - NU) {
-        T av[CP], dv[CP];
-        analysis_run<T, NU, CP>(a + 2 * m0 - NU + 1, 1, hr, gr, av, dv);
-#pragma unroll
-        for (int p = 0; p < CP; ++p) b[m0 + p] = av[p], b[half + m0 + p] = dv[p];
-      } else if (half >= CP) {
-        T av[CP], dv[CP];
-        analysis_run_edge<T, NU, CP>(a, 1, 0, size - 1, m0, half, hr, gr, tl.sLs, tl.sRs, av, dv);
-#pragma unroll
-        for (int p = 0; p < CP; ++p) b[m0 + p] = av[p], b[half + m0 + p] = dv[p];
-      } else {
-        auto X = [&](int n) { return a[n]; };
-        for (int p = 0; p < CP && m0 + p < half; ++p) {
-          b[m0 + p] = analysis_at<T, NU>(m0 + p, half, tl.hs, tl.gs, tl.sLs, tl.sRs, X);
-          b[half + m0 + p] = analysis_at<T, NU>(half + m0 + p, half, tl.hs, tl.gs, tl.sLs, tl.sRs, X);
-        }
-      }
-    }
-    __syncthreads();
-    for (int i = tid; i < size; i += 1024) a[i] = b[i];
-    __syncthreads();
-  }
+  analysis_levels_lds<T, NU>(a, b, j0, kc, tl, hr, gr);
   for (int i = tid; i < S; i += 1024) x[i] = a[i];
 }
 

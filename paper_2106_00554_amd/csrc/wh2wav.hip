@@ -235,6 +235,13 @@ bool use_wave1d(const wh2wav_plan_s* p) {
          (H.full_omega || !H.pos16.empty());
 }
 
+// 1D lines of the wave kernels whose LDS holds the whole operator: one launch
+// per direction (wavelet levels fused with the line transform).
+bool use_line1d_fused(const wh2wav_plan_s* p) {
+  const auto& H = p->host;
+  return use_wave1d(p) && wh2wav_fast::line1d_fused(H.dtype == WH2WAV_F64 ? 8 : 4, H.j, H.nu, H.q);
+}
+
 bool use_fast(const wh2wav_plan_s* p) {
   const auto& H = p->host;
   return H.dim == 2 && !H.nd && wh2wav_fast::supported(H.dtype == WH2WAV_F64 ? 8 : 4, H.j, H.nu, H.q);
@@ -544,6 +551,10 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
     T* S0 = W + M;
     T* L = S0 + M;
     const auto ft = fast_tables_of<T>(p);
+    if (stage < 0 && use_line1d_fused(p)) {
+      HIP_OK(wh2wav_fast::line1d_fwd_fused<T>(x, y, H.j0, H.j, ft, fast_omega_of(p), st));
+      return WH2WAV_OK;
+    }
     if (run(0)) HIP_OK(wh2wav_fast::idwt1d<T>(x, W, S0, H.j0, H.j, ft, st));
     if (use_wave1d(p)) {
       if (run(1)) HIP_OK(wh2wav_fast::rowpass_fwd<T>(W, y, H.j, ft, fast_omega_of(p), 1, st));
@@ -629,6 +640,10 @@ int adjoint_impl(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t
     T* S0 = W + M;
     T* L = S0 + M;
     const auto ft = fast_tables_of<T>(p);
+    if (stage < 0 && use_line1d_fused(p)) {
+      HIP_OK(wh2wav_fast::line1d_adj_fused<T>(y, x, H.j0, H.j, ft, fast_omega_of(p), st));
+      return WH2WAV_OK;
+    }
     if (use_wave1d(p)) {
       if (run(0)) HIP_OK(wh2wav_fast::rowpass_adj<T>(y, W, H.j, ft, fast_omega_of(p), 1, st));
     } else if (run(0)) {

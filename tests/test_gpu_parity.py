@@ -414,3 +414,30 @@ def test_parity_tensor_basis(nu, j, q, j0, dens, boundary, dtype):
     y, xa = gpu_pair(2, nu, j, q, j0, dtype, x, omega, yv, boundary=boundary, basis2d="tensor")
     assert rel(y, y_ref) < TOL[dtype], rel(y, y_ref)
     assert rel(xa, x_ref) < TOL[dtype], rel(xa, x_ref)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("nu,j,q,j0,dens", [(4, 10, 1, 3, None), (8, 11, 2, 4, 0.2), (2, 7, 4, 2, 0.3),
+                                            (6, 9, 3, 4, None), (3, 8, 1, 3, 0.0)])
+def test_1d_one_launch_equals_the_stages(nu, j, q, j0, dens, dtype):
+    """1D lines of up to 2048 values run as one launch per direction (wavelet
+    levels in LDS fused with the line transform); the staged calls run the
+    separate kernels.  Both use the same device arithmetic: equal bit for bit."""
+    from paper_2106_00554_amd import _abi
+    from paper_2106_00554_amd.operator import Wh2Wav
+    cfg = op.Config(nu, j, q, j0)
+    seed = 500 + 10 * nu + j
+    omega = None if dens is None else (np.zeros(0, np.int64) if dens == 0 else
+                                       inputs.uniform_omega(cfg.N, dens, seed + 1))
+    opr = Wh2Wav(1, j, q, nu, j0, dtype, omega)
+    x = torch.tensor(inputs.coefficients_1d(j, j0, seed), dtype=dtype, device="cuda")
+    yv = torch.tensor(inputs.sample_vector(opr.m, seed + 2), dtype=dtype, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    y_whole, x_whole = opr.forward(x), opr.adjoint(yv)
+    y_st, x_st = torch.empty_like(y_whole), torch.empty_like(x_whole)
+    for s in range(_abi.wh2wav_stage_count(opr._plan, 0)):
+        _abi.wh2wav_forward_stage(opr._plan, s, x.data_ptr(), y_st.data_ptr(), opr.workspace.data_ptr(), st)
+    for s in range(_abi.wh2wav_stage_count(opr._plan, 1)):
+        _abi.wh2wav_adjoint_stage(opr._plan, s, yv.data_ptr(), x_st.data_ptr(), opr.workspace.data_ptr(), st)
+    torch.cuda.synchronize()
+    assert torch.equal(y_st, y_whole) and torch.equal(x_st, x_whole)
