@@ -5,8 +5,9 @@
 // S X S^T, S the one-level synthesis matrix (interior columns: the filters h, g
 // at stride 2; boundary columns: the dense blocks built by the planner).  The
 // transpose (the forward DWT) is S^T X S.
-//   * Levels with an output block of at most 8 x 8 run in one workgroup with
-//     the block in LDS.
+//   * The coarse levels run in one workgroup with the block in LDS: output
+//     blocks of at most 8 x 8; with nu <= 4 up to 64 x 64, and the whole
+//     transform of an FP32 array of at most 128 x 128.
 //   * Every larger level is one launch over 2D output tiles (16 x 16 up to
 //     64 x 64 by level size).  Synthesis tiles, and analysis tiles of the
 //     largest size, filter in two passes: the first reads its lines straight
@@ -556,12 +557,19 @@ __global__ void __launch_bounds__(1024) k_analysis2d_coarse(const T* __restrict_
     for (int c = lane; c < S; c += 64) x[int64_t(i) * ld_x + c] = blk[i * P + c];
 }
 
-template <typename T>
-constexpr int coarse_limit() {
-  // log2 of the largest block the one-workgroup kernel handles: every level
-  // with a 16 x 16 or larger output runs as a multi-workgroup tile launch,
-  // since one workgroup issues from a single CU
-  return 3;
+// log2 of the largest block the one-workgroup kernel handles, for a j-level
+// transform.  With nu <= 4 the levels up to a 64 x 64 output cost less in one
+// workgroup than as a launch each (db4, 512^2: 78 -> 73 us per FP32 pair,
+// 95 -> 89 us per FP64 pair), and an FP32 transform of at most 128 x 128 runs
+// whole in one launch; the 128 x 128 level of a larger array is faster as a
+// tile launch.  With nu > 4 the boundary rows fill most of the small levels
+// and every level with a 16 x 16 or larger output runs as a tile launch.  The
+// kernel's loads take blocks of at most 128 columns, and its LDS (two
+// padded blocks) holds 128 x 128 in FP32, 64 x 64 in FP64.
+template <typename T, int NU>
+constexpr int coarse_limit(int j) {
+  if (NU > 4) return 3;
+  return sizeof(T) == 4 && j <= 7 ? 7 : 6;
 }
 
 // Largest input window (rows of one half) over the tiles of a level, from
@@ -671,8 +679,8 @@ hipError_t idwt2d_impl(const T* x, T* outT, T* s0, T* s1, int64_t M, int j0, int
   if (j0 == j) return copy_transposed<T, NU>(x, outT, M, j, t, st);
   // Coarse levels in one workgroup, unless the coarsest block is already too
   // large for LDS (then the first tiled level reads LL_{j0} from x).
-  const bool coarse = j0 < coarse_limit<T>();
-  const int kc = coarse ? (j < coarse_limit<T>() ? j : coarse_limit<T>()) : j0;
+  const bool coarse = j0 < coarse_limit<T, NU>(j);
+  const int kc = coarse ? (j < coarse_limit<T, NU>(j) ? j : coarse_limit<T, NU>(j)) : j0;
   const bool last = kc == j;
   hipError_t e = hipSuccess;
   if (coarse) {
@@ -707,8 +715,8 @@ template <typename T, int NU>
 hipError_t dwt2d_impl(const T* inT, T* x, T* s0, T* s1, int64_t M, int j0, int j, const Tables<T>& t,
                       hipStream_t st) {
   if (j0 == j) return copy_transposed<T, NU>(inT, x, M, j, t, st);
-  const bool coarse = j0 < coarse_limit<T>();
-  const int kc = coarse ? (j < coarse_limit<T>() ? j : coarse_limit<T>()) : j0;
+  const bool coarse = j0 < coarse_limit<T, NU>(j);
+  const int kc = coarse ? (j < coarse_limit<T, NU>(j) ? j : coarse_limit<T, NU>(j)) : j0;
   const int S = 1 << kc;
   hipError_t e = hipSuccess;
   const T* src = inT;
