@@ -477,6 +477,62 @@ __device__ void analysis_levels_lds(T* a, T* b, int j0, int kc, const TileLds<T>
   }
 }
 
+// The periodic extension (Sec. 3.2): synthesis levels j0 .. kc-1 of a line
+// in LDS with every index taken modulo the level's length (no boundary
+// functions); layout, scratch and barriers as synth_levels_lds.  Output pair
+// i reads a and d at i + synth_off(c) for each tap c.
+template <typename T, int NU>
+__device__ void synth_levels_lds_per(T* a, T* b, int j0, int kc, const T (&hr)[2 * NU], const T (&gr)[2 * NU]) {
+  const int tid = int(threadIdx.x), nt = int(blockDim.x);
+  for (int k = j0; k < kc; ++k) {
+    const int half = 1 << k;
+    for (int i = tid; i < half; i += nt) {
+      T e = T(0), o = T(0);
+#pragma unroll
+      for (int c = -NU + 1; c <= NU; ++c) {
+        const int m = (i + synth_off<NU>(c)) & (half - 1);
+        const T va = a[m], vd = a[half + m];
+        if (((c % 2) + 2) % 2 == 0) {
+          e = fma(va, hr[c + NU - 1], e);
+          e = fma(vd, gr[c + NU - 1], e);
+        } else {
+          o = fma(va, hr[c + NU - 1], o);
+          o = fma(vd, gr[c + NU - 1], o);
+        }
+      }
+      b[2 * i] = e;
+      b[2 * i + 1] = o;
+    }
+    __syncthreads();
+    for (int i = tid; i < 2 * half; i += nt) a[i] = b[i];
+    __syncthreads();
+  }
+}
+
+// Its transpose: a_m = sum_c h_c v((2m + c) mod 2^{k+1}), d_m the same with g,
+// levels kc-1 .. j0.
+template <typename T, int NU>
+__device__ void analysis_levels_lds_per(T* a, T* b, int j0, int kc, const T (&hr)[2 * NU], const T (&gr)[2 * NU]) {
+  const int tid = int(threadIdx.x), nt = int(blockDim.x);
+  for (int k = kc - 1; k >= j0; --k) {
+    const int half = 1 << k, size = 2 * half;
+    for (int m = tid; m < half; m += nt) {
+      T sa = T(0), sd = T(0);
+#pragma unroll
+      for (int c = 0; c < 2 * NU; ++c) {
+        const T v = a[(2 * m + c - NU + 1) & (size - 1)];
+        sa = fma(hr[c], v, sa);
+        sd = fma(gr[c], v, sd);
+      }
+      b[m] = sa;
+      b[half + m] = sd;
+    }
+    __syncthreads();
+    for (int i = tid; i < size; i += nt) a[i] = b[i];
+    __syncthreads();
+  }
+}
+
 template <int NU>
 constexpr int tab_lds_size() {
   return 4 * NU + 2 * (3 * NU - 1) * 2 * NU;

@@ -52,6 +52,40 @@ __global__ void __launch_bounds__(1024) k_synth1d_coarse(const T* __restrict__ x
   for (int i = tid; i < S; i += 1024) out[i] = a[i];
 }
 
+// Every wavelet level of `lines` lines of 2^j values, one line per
+// workgroup in LDS: line r is in[r ld_in .. r ld_in + 2^j) and goes to
+// out[r ld_out ..].  Synthesis (levels j0 .. j-1, C_{psi,j} order to the
+// scaling coefficients at level j) or, with ANALYSIS, its transpose;
+// boundary-corrected or periodic as the tables say.  in and out may be the
+// same array (each workgroup reads its whole line before it writes).
+template <typename T, int NU, bool ANALYSIS>
+__global__ void __launch_bounds__(256) k_lines_levels(const T* in, int64_t ld_in, T* out, int64_t ld_out, int j0,
+                                                      int j, Tables<T> t) {
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ T tab_lds[tab_lds_size<NU>()];
+  T hr[2 * NU], gr[2 * NU];
+  const TileLds<T> tl = load_tables<T, NU>(t, tab_lds, hr, gr);
+  const int S = 1 << j, tid = int(threadIdx.x);
+  T* a = reinterpret_cast<T*>(smem_raw);
+  T* b = a + S;
+  const T* src = in + int64_t(blockIdx.x) * ld_in;
+  for (int i = tid; i < S; i += 256) a[i] = src[i];
+  __syncthreads();
+  if (t.per) {
+    if constexpr (ANALYSIS)
+      analysis_levels_lds_per<T, NU>(a, b, j0, j, hr, gr);
+    else
+      synth_levels_lds_per<T, NU>(a, b, j0, j, hr, gr);
+  } else {
+    if constexpr (ANALYSIS)
+      analysis_levels_lds<T, NU>(a, b, j0, j, tl, hr, gr);
+    else
+      synth_levels_lds<T, NU>(a, b, j0, j, tl, hr, gr);
+  }
+  T* dst = out + int64_t(blockIdx.x) * ld_out;
+  for (int i = tid; i < S; i += 256) dst[i] = a[i];
+}
+
 // Analysis levels kc-1 .. j0 of the line in[0, 2^kc) in one workgroup; writes
 // [a_j0 | d_j0 | ... | d_{kc-1}] to x[0, 2^kc).
 template <typename T, int NU>
@@ -354,13 +388,30 @@ hipError_t line1d_adj_impl(const T* y, T* L, T* xi, int j, const Tables<T>& t, c
 }
 
 template <typename T, int NU>
+hipError_t lines_levels_impl(const T* in, int64_t ld_in, T* out, int64_t ld_out, int64_t lines, int j0, int j,
+                             int analysis, const Tables<T>& t, hipStream_t st) {
+  if (j < 1 || j > lds_line_log<T>() || j0 < 0 || j0 > j || lines < 1 || lines > (int64_t(1) << 30))
+    return hipErrorInvalidValue;
+  const size_t smem = 2 * (size_t(1) << j) * sizeof(T);
+  if (analysis)
+    hipLaunchKernelGGL((k_lines_levels<T, NU, true>), dim3(unsigned(lines)), dim3(256), smem, st, in, ld_in, out,
+                       ld_out, j0, j, t);
+  else
+    hipLaunchKernelGGL((k_lines_levels<T, NU, false>), dim3(unsigned(lines)), dim3(256), smem, st, in, ld_in, out,
+                       ld_out, j0, j, t);
+  return hipGetLastError();
+}
+
+template <typename T, int NU>
 hipError_t prepare1d_impl() {
   const int lim = 160 * 1024 - int(tab_lds_size<NU>() * sizeof(T));
-  hipError_t e = hipFuncSetAttribute((const void*)k_synth1d_coarse<T, NU>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     lim);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_analysis1d_coarse<T, NU>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  return e;
+  const void* kernels[] = {(const void*)k_synth1d_coarse<T, NU>, (const void*)k_analysis1d_coarse<T, NU>,
+                           (const void*)k_lines_levels<T, NU, false>, (const void*)k_lines_levels<T, NU, true>};
+  for (const void* f : kernels) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 #define WH2WAV_1D_NUS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
@@ -403,6 +454,15 @@ hipError_t line1d_adj(const T* y, T* L, T* xi, int j, const Tables<T>& t, const 
   return hipErrorInvalidValue;
 }
 template <typename T>
+hipError_t lines_levels(const T* in, int64_t ld_in, T* out, int64_t ld_out, int64_t lines, int j0, int j,
+                        int analysis, const Tables<T>& t, hipStream_t st) {
+#define X(V) if (t.nu == V) return lines_levels_impl<T, V>(in, ld_in, out, ld_out, lines, j0, j, analysis, t, st);
+  WH2WAV_1D_NUS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+bool lines_levels_fit(int elem_bytes, int j) { return j >= 1 && j <= (elem_bytes == 4 ? 14 : 13); }
+template <typename T>
 hipError_t prepare_1d(int nu) {
 #define X(V) if (nu == V) return prepare1d_impl<T, V>();
   WH2WAV_1D_NUS(X)
@@ -417,6 +477,8 @@ hipError_t prepare_1d(int nu) {
                                     hipStream_t);                                                                \
   template hipError_t line1d_adj<T>(const T*, T*, T*, int, const Tables<T>&, const int32_t*, int64_t, int,         \
                                     hipStream_t);                                                                \
+  template hipError_t lines_levels<T>(const T*, int64_t, T*, int64_t, int64_t, int, int, int, const Tables<T>&,   \
+                                      hipStream_t);                                                              \
   template hipError_t prepare_1d<T>(int);
 INST_(float)
 INST_(double)

@@ -357,20 +357,49 @@ int tensor_level(const wh2wav_plan_s* p, T* cur, T* tmp, bool columns, int k, bo
   return WH2WAV_OK;
 }
 
-// Tensor basis, forward first stage: x -> xi^T (out); W scratch.
+// The square tensor basis with lines of at most the LDS line length and a
+// side of at least 32 takes the line kernels: every level of a line in one
+// workgroup, and the 32 x 32-tile transpose between the two axes.
+bool tensor_lines(const wh2wav_plan_s* p) {
+  const auto& H = p->host;
+  return H.tensor && !H.nd && H.dim == 2 && H.M >= 32 &&
+         wh2wav_fast::lines_levels_fit(H.dtype == WH2WAV_F64 ? 8 : 4, H.j);
+}
+
+// Tensor basis, forward first stage: x -> xi^T (out); W scratch.  With the
+// line kernels: U = x W^T (every row of x through the 1D synthesis), its
+// transpose W x^T, and every row of that again: W x^T W^T = xi^T.
 template <typename T>
 int idwt2d_tensor(const wh2wav_plan_s* p, const T* x, T* out, T* W, hipStream_t st) {
   const auto& H = p->host;
+  if (tensor_lines(p)) {
+    const auto ft = fast_tables_of<T>(p);
+    const int64_t M = H.M;
+    HIP_OK(wh2wav_fast::lines_levels<T>(x, M, W, M, M, H.j0, H.j, 0, ft, st));
+    HIP_OK(wh2wav_fast::transpose<T>(W, out, M, st));
+    HIP_OK(wh2wav_fast::lines_levels<T>(out, M, out, M, M, H.j0, H.j, 0, ft, st));
+    return WH2WAV_OK;
+  }
   int rc = launch_transpose<T>(x, out, H.M, st);
   for (int k = H.j0; k < H.j && rc == WH2WAV_OK; ++k) rc = tensor_level<T>(p, out, W, true, k, false, st);
   for (int k = H.j0; k < H.j && rc == WH2WAV_OK; ++k) rc = tensor_level<T>(p, out, W, false, k, false, st);
   return rc;
 }
 
-// Its transpose: xi'^T (in, overwritten) -> x; W scratch.
+// Its transpose: xi'^T (in, overwritten) -> x; W scratch.  With the line
+// kernels: every row of xi'^T through the 1D analysis (xi'^T W), the
+// transpose W^T xi', and every row again: W^T xi' W = x.
 template <typename T>
 int dwt2d_tensor(const wh2wav_plan_s* p, T* in, T* x, T* W, hipStream_t st) {
   const auto& H = p->host;
+  if (tensor_lines(p)) {
+    const auto ft = fast_tables_of<T>(p);
+    const int64_t M = H.M;
+    HIP_OK(wh2wav_fast::lines_levels<T>(in, M, in, M, M, H.j0, H.j, 1, ft, st));
+    HIP_OK(wh2wav_fast::transpose<T>(in, W, M, st));
+    HIP_OK(wh2wav_fast::lines_levels<T>(W, M, x, M, M, H.j0, H.j, 1, ft, st));
+    return WH2WAV_OK;
+  }
   int rc = WH2WAV_OK;
   for (int k = H.j - 1; k >= H.j0 && rc == WH2WAV_OK; --k) rc = tensor_level<T>(p, in, W, false, k, true, st);
   for (int k = H.j - 1; k >= H.j0 && rc == WH2WAV_OK; --k) rc = tensor_level<T>(p, in, W, true, k, true, st);
@@ -836,6 +865,8 @@ int plan_body(const wh2wav_desc* desc, wh2wav_plan_t* out) {
     if (e == hipSuccess && use_fast(p))
       e = H.dtype == WH2WAV_F64 ? wh2wav_fast::prepare_lines<double>(H.j, H.nu)
                                 : wh2wav_fast::prepare_lines<float>(H.j, H.nu);
+    if (e == hipSuccess && tensor_lines(p))
+      e = H.dtype == WH2WAV_F64 ? wh2wav_fast::prepare_1d<double>(H.nu) : wh2wav_fast::prepare_1d<float>(H.nu);
     if (e != hipSuccess) return fail(WH2WAV_EHIP, std::string("kernel setup: ") + hipGetErrorString(e));
   }
   if (use_fast1d(p)) {

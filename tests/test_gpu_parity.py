@@ -394,6 +394,8 @@ CASES_TENSOR = [
     (2, 4, 1, 2, None, "bd"), (4, 6, 2, 3, 0.3, "bd"), (3, 5, 1, 3, 0.25, "per"),   # generic line kernels
     (4, 8, 1, 3, 0.2, "bd"), (8, 9, 1, 4, 0.15, "bd"), (2, 10, 1, 2, 0.2, "per"),  # wave line kernels
     (6, 7, 2, 4, None, "bd"),
+    (2, 6, 1, 6, 0.3, "bd"),     # no wavelet level (j0 = j)
+    (8, 8, 2, 4, 0.2, "per"),    # db8 periodic on the one-workgroup line kernels
 ]
 
 
