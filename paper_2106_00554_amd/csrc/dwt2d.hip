@@ -58,7 +58,7 @@ __device__ __forceinline__ void tile_of(int t, int n, int& tr, int& tc) {
 // Analysis level k: input xi (size x size; trans: read in^T); output quadrants:
 // LL -> ll[a][b], other bands -> det[row][col].  Tile: TH x TH outputs in each
 // of the four quadrants at the same (a0, b0); 256 threads; runs of P outputs.
-template <typename T, int NU, int TH, int P>
+template <typename T, int NU, int TH, int P, bool PER>
 __global__ void __launch_bounds__(256) k_analysis2d_tile(const T* __restrict__ in, int64_t ld_in, int trans,
                                                          T* __restrict__ ll, int64_t ld_ll, T* __restrict__ det,
                                                          int64_t ld_det, int k, Tables<T> t) {
@@ -72,8 +72,13 @@ __global__ void __launch_bounds__(256) k_analysis2d_tile(const T* __restrict__ i
   tile_of(int(blockIdx.x), ntile, tr, tc);
   const int a0 = tr * TH, b0 = tc * TH;
   int rlo, rhi, clo, chi;
-  analysis_input_range<NU>(a0, a0 + TH, half, rlo, rhi);
-  analysis_input_range<NU>(b0, b0 + TH, half, clo, chi);
+  if constexpr (PER) {
+    analysis_input_range_per<NU>(a0, a0 + TH, rlo, rhi);
+    analysis_input_range_per<NU>(b0, b0 + TH, clo, chi);
+  } else {
+    analysis_input_range<NU>(a0, a0 + TH, half, rlo, rhi);
+    analysis_input_range<NU>(b0, b0 + TH, half, clo, chi);
+  }
   const int nr = rhi - rlo + 1, nc = chi - clo + 1;
   const int W = nc + 1;
   constexpr int YW = 2 * TH + 1;
@@ -93,9 +98,13 @@ __global__ void __launch_bounds__(256) k_analysis2d_tile(const T* __restrict__ i
       for (int v = 0; v < IJ; ++v) {
         const int b = lane + 64 * v;
         // unconditional load (the window's first element when outside it), so
-        // that all loads are in flight together
+        // that all loads are in flight together; the periodic extension
+        // takes the indices modulo the level's size (the window stays
+        // unwrapped in LDS, so every run below reads it as an interior run)
         const bool inside = a < no && b < ni;
-        const T val = in[inside ? (ob + a) * ld_in + ib + b : ob * ld_in + ib];
+        int64_t oa = ob + (inside ? a : 0), ibb = ib + (inside ? b : 0);
+        if constexpr (PER) oa &= 2 * half - 1, ibb &= 2 * half - 1;
+        const T val = in[oa * ld_in + ibb];
         r[u][v] = inside ? val : T(0);
       }
     }
@@ -124,7 +133,7 @@ __global__ void __launch_bounds__(256) k_analysis2d_tile(const T* __restrict__ i
     const T* xr = Xs + i2 * W;
     const int m0 = b0 + u * P;
     T* yr = Ys + i2 * YW + u * P;
-    if (m0 >= NU && m0 + P - 1 < half - NU) {
+    if (PER || (m0 >= NU && m0 + P - 1 < half - NU)) {
       T a[P], d[P];
       analysis_run<T, NU, P>(xr + 2 * m0 - NU + 1 - clo, 1, hr, gr, a, d);
 #pragma unroll
@@ -142,7 +151,7 @@ __global__ void __launch_bounds__(256) k_analysis2d_tile(const T* __restrict__ i
   for (int item = int(threadIdx.x); item < 2 * TH * RUNS; item += 256) {
     const int oc = item % (2 * TH), u = item / (2 * TH);
     const int m0 = a0 + u * P;
-    if (m0 >= NU && m0 + P - 1 < half - NU) {
+    if (PER || (m0 >= NU && m0 + P - 1 < half - NU)) {
       T a[P], d[P];
       analysis_run<T, NU, P>(Ys + (2 * m0 - NU + 1 - rlo) * YW + oc, YW, hr, gr, a, d);
 #pragma unroll
@@ -179,7 +188,7 @@ __global__ void __launch_bounds__(256) k_analysis2d_tile(const T* __restrict__ i
 // Synthesis level k: X[r][c] = (r < half && c < half) ? ll[r][c] : det[r][c]
 // (ll and det share the row stride ld); out = S X S^T (trans: out^T).  Tile:
 // TS x TS outputs, 256 threads, runs of P output pairs.
-template <typename T, int NU, int TS, int P>
+template <typename T, int NU, int TS, int P, bool PER>
 __global__ void __launch_bounds__(256) k_synth2d_direct(const T* __restrict__ ll, const T* __restrict__ det,
                                                         int64_t ld, T* __restrict__ out, int64_t ld_out, int k,
                                                         int trans, Tables<T> t) {
@@ -192,24 +201,40 @@ __global__ void __launch_bounds__(256) k_synth2d_direct(const T* __restrict__ ll
   tile_of(int(blockIdx.x), ntile, tr, tc);
   const int r0 = tr * TS, c0 = tc * TS;
   int rlo, rhi, clo, chi;
-  synth_input_range<NU>(r0, r0 + TS, half, rlo, rhi);
-  synth_input_range<NU>(c0, c0 + TS, half, clo, chi);
+  if constexpr (PER) {
+    synth_input_range_per<NU>(r0, r0 + TS, rlo, rhi);
+    synth_input_range_per<NU>(c0, c0 + TS, clo, chi);
+  } else {
+    synth_input_range<NU>(r0, r0 + TS, half, rlo, rhi);
+    synth_input_range<NU>(c0, c0 + TS, half, clo, chi);
+  }
   const int nc = chi - clo + 1, W2 = 2 * nc;
   const int YW = W2 + 1;                      // odd: conflict-free in both directions
   T* Ys = reinterpret_cast<T*>(smem_raw);     // TS x YW: column-filtered rows r0 .. r0+TS-1
   const TileLds<T> tl = load_tables<T, NU>(t, tab_lds, hr, gr);
   // tiles whose rows reach a boundary read the boundary blocks from LDS
-  if (!(pair_is_interior<NU>(r0 >> 1, half) && pair_is_interior<NU>((r0 >> 1) + TS / 2 - 1, half))) __syncthreads();
-  constexpr int RUNS = TS / (2 * P), LO = synth_lo<NU>(), NT = 256;
-  // pass 1, columns: item = (window column j, run u of P output row pairs)
+  if (!PER && !(pair_is_interior<NU>(r0 >> 1, half) && pair_is_interior<NU>((r0 >> 1) + TS / 2 - 1, half)))
+    __syncthreads();
+  constexpr int RUNS = TS / (2 * P), LO = synth_lo<NU>(), HI = synth_hi<NU>(), NT = 256;
+  // pass 1, columns: item = (window column j, run u of P output row pairs);
+  // the periodic extension reads window column clo + j modulo half, and a
+  // run that crosses an end reads its rows modulo half
   for (int item = int(threadIdx.x); item < W2 * RUNS; item += NT) {
     const int j = item % W2, u = item / W2;
-    const int col = j < nc ? clo + j : half + clo + (j - nc);
+    const int col = PER ? (j < nc ? ((clo + j) & (half - 1)) : half + ((clo + j - nc) & (half - 1)))
+                        : (j < nc ? clo + j : half + clo + (j - nc));
     const T* ca = (col < half ? ll : det) + col;  // rows 0 .. half-1
     const T* cd = det + int64_t(half) * ld + col;  // rows half .. size-1
     const int i0 = (r0 >> 1) + u * P;
     T e[P], o[P];
-    if (pair_is_interior<NU>(i0, half) && pair_is_interior<NU>(i0 + P - 1, half)) {
+    if constexpr (PER) {
+      if (i0 + LO >= 0 && i0 + P - 1 + HI <= half - 1) {
+        const int64_t off = int64_t(i0 + LO) * ld;
+        synth_run<T, NU, P>(ca + off, cd + off, int(ld), hr, gr, e, o);
+      } else {
+        synth_run_wrap<T, NU, P>(ca, cd, int(ld), i0, half, hr, gr, e, o);
+      }
+    } else if (pair_is_interior<NU>(i0, half) && pair_is_interior<NU>(i0 + P - 1, half)) {
       const int64_t off = int64_t(i0 + LO) * ld;
       synth_run<T, NU, P>(ca + off, cd + off, int(ld), hr, gr, e, o);
     } else {
@@ -237,7 +262,7 @@ __global__ void __launch_bounds__(256) k_synth2d_direct(const T* __restrict__ ll
   if (item < TS * RUNS) {
     const T* yr = Ys + r * YW;
     const int i0 = (c0 >> 1) + u * P;
-    if (pair_is_interior<NU>(i0, half) && pair_is_interior<NU>(i0 + P - 1, half))
+    if (PER || (pair_is_interior<NU>(i0, half) && pair_is_interior<NU>(i0 + P - 1, half)))
       synth_run<T, NU, P>(yr + i0 + LO - clo, yr + nc + i0 + LO - clo, 1, hr, gr, e, o);
     else
       synth_run_edge<T, NU, P>(yr, yr + nc, 1, clo, chi, i0, half, hr, gr, tl.sLs, tl.sRs, e, o);
@@ -278,7 +303,7 @@ __global__ void __launch_bounds__(256) k_synth2d_direct(const T* __restrict__ ll
 // S^T in S when trans = 0, and G = S^T in S with in holding xi^T when trans =
 // 1, so that the coefficients are G^T (quadrants LH and HL exchange).  Tile:
 // TH x TH outputs in each quadrant of G at (A0, B0), 256 threads, runs of P.
-template <typename T, int NU, int TH, int P>
+template <typename T, int NU, int TH, int P, bool PER>
 __global__ void __launch_bounds__(256) k_analysis2d_direct(const T* __restrict__ in, int64_t ld_in, int trans,
                                                            T* __restrict__ ll, int64_t ld_ll, T* __restrict__ det,
                                                            int64_t ld_det, int k, Tables<T> t) {
@@ -291,22 +316,32 @@ __global__ void __launch_bounds__(256) k_analysis2d_direct(const T* __restrict__
   tile_of(int(blockIdx.x), ntile, tr, tc);
   const int A0 = tr * TH, B0 = tc * TH;
   int plo, phi, qlo, qhi;
-  analysis_input_range<NU>(A0, A0 + TH, half, plo, phi);
-  analysis_input_range<NU>(B0, B0 + TH, half, qlo, qhi);
+  if constexpr (PER) {
+    analysis_input_range_per<NU>(A0, A0 + TH, plo, phi);
+    analysis_input_range_per<NU>(B0, B0 + TH, qlo, qhi);
+  } else {
+    analysis_input_range<NU>(A0, A0 + TH, half, plo, phi);
+    analysis_input_range<NU>(B0, B0 + TH, half, qlo, qhi);
+  }
   const int nq = qhi - qlo + 1;
   const int YW = nq + 1;
   T* Ys = reinterpret_cast<T*>(smem_raw);  // 2TH x YW: a rows, then d rows
   const TileLds<T> tl = load_tables<T, NU>(t, tab_lds, hr, gr);
   // tiles whose rows reach a boundary read the boundary blocks from LDS
-  if (!(A0 >= NU && A0 + TH - 1 < half - NU)) __syncthreads();
+  if (!PER && !(A0 >= NU && A0 + TH - 1 < half - NU)) __syncthreads();
   constexpr int RUNS = TH / P, NT = 256;
-  // pass 1, along the row index of `in`: item = (window column jq, run u)
+  const int size = 2 * half;
+  // pass 1, along the row index of `in`: item = (window column jq, run u);
+  // the periodic extension reads window column qlo + jq modulo size, and a
+  // run that crosses an end reads its rows modulo size
   for (int item = int(threadIdx.x); item < nq * RUNS; item += NT) {
     const int jq = item % nq, u = item / nq;
-    const T* cx = in + qlo + jq;
+    const T* cx = in + (PER ? ((qlo + jq) & (size - 1)) : qlo + jq);
     const int m0 = A0 + u * P;
     T a[P], d[P];
-    if (m0 >= NU && m0 + P - 1 < half - NU)
+    if (PER && !(2 * m0 - NU + 1 >= 0 && 2 * (m0 + P - 1) + NU <= size - 1))
+      analysis_run_wrap<T, NU, P>(cx, int(ld_in), m0, size, hr, gr, a, d);
+    else if (PER || (m0 >= NU && m0 + P - 1 < half - NU))
       analysis_run<T, NU, P>(cx + int64_t(2 * m0 - NU + 1) * ld_in, int(ld_in), hr, gr, a, d);
     else
       analysis_run_edge<T, NU, P>(cx + int64_t(plo) * ld_in, int(ld_in), plo, phi, m0, half, hr, gr, tl.sLs,
@@ -328,7 +363,7 @@ __global__ void __launch_bounds__(256) k_analysis2d_direct(const T* __restrict__
   T a[P], d[P];
   if (item < 2 * TH * RUNS) {
     const T* yr = Ys + rho * YW;
-    if (m0 >= NU && m0 + P - 1 < half - NU)
+    if (PER || (m0 >= NU && m0 + P - 1 < half - NU))
       analysis_run<T, NU, P>(yr + 2 * m0 - NU + 1 - qlo, 1, hr, gr, a, d);
     else
       analysis_run_edge<T, NU, P>(yr, 1, qlo, qhi, m0, half, hr, gr, tl.sLs, tl.sRs, a, d);
@@ -377,7 +412,7 @@ __global__ void __launch_bounds__(256) k_analysis2d_direct(const T* __restrict__
 // One workgroup: levels j0 .. kc-1 (output block 2^kc) with the block in LDS.
 // Input x (quadtree, row stride ld_x).  Output: the 2^kc block into out
 // (trans: transposed).
-template <typename T, int NU>
+template <typename T, int NU, bool PER>
 __global__ void __launch_bounds__(1024) k_synth2d_coarse(const T* __restrict__ x, int64_t ld_x, T* __restrict__ out,
                                                          int64_t ld_out, int j0, int kc, int trans, Tables<T> t) {
   extern __shared__ unsigned char smem_raw[];
@@ -406,7 +441,9 @@ __global__ void __launch_bounds__(1024) k_synth2d_coarse(const T* __restrict__ x
       }
   }
   __syncthreads();
-  constexpr int CP = 2, LO = synth_lo<NU>();
+  constexpr int CP = 2, LO = synth_lo<NU>(), HI = synth_hi<NU>();
+  // the periodic extension: runs that cross an end read modulo half
+  auto wraps = [&](int i0, int half) { return i0 + LO < 0 || i0 + CP - 1 + HI > half - 1; };
   for (int k = j0; k < kc; ++k) {
     const int half = 1 << k, size = 2 * half;
     const int runs = (half + CP - 1) / CP;
@@ -415,7 +452,16 @@ __global__ void __launch_bounds__(1024) k_synth2d_coarse(const T* __restrict__ x
       const int i = item % size, i0 = (item / size) * CP;
       const T* xr = blk + i * P;
       T* yr = tmp + i * P + 2 * i0;
-      if (pair_is_interior<NU>(i0, half) && pair_is_interior<NU>(i0 + CP - 1, half)) {
+      if (PER && half < CP) {
+        T e[1], o[1];
+        synth_run_wrap<T, NU, 1>(xr, xr + half, 1, i0, half, hr, gr, e, o);
+        yr[0] = e[0], yr[1] = o[0];
+      } else if (PER && wraps(i0, half)) {
+        T e[CP], o[CP];
+        synth_run_wrap<T, NU, CP>(xr, xr + half, 1, i0, half, hr, gr, e, o);
+#pragma unroll
+        for (int p = 0; p < CP; ++p) yr[2 * p] = e[p], yr[2 * p + 1] = o[p];
+      } else if (PER || (pair_is_interior<NU>(i0, half) && pair_is_interior<NU>(i0 + CP - 1, half))) {
         T e[CP], o[CP];
         synth_run<T, NU, CP>(xr + i0 + LO, xr + half + i0 + LO, 1, hr, gr, e, o);
 #pragma unroll
@@ -439,7 +485,16 @@ __global__ void __launch_bounds__(1024) k_synth2d_coarse(const T* __restrict__ x
     for (int item = int(threadIdx.x); item < size * runs; item += 1024) {
       const int c = item % size, i0 = (item / size) * CP;
       T* oc = blk + 2 * i0 * P + c;
-      if (pair_is_interior<NU>(i0, half) && pair_is_interior<NU>(i0 + CP - 1, half)) {
+      if (PER && half < CP) {
+        T e[1], o[1];
+        synth_run_wrap<T, NU, 1>(tmp + c, tmp + half * P + c, P, i0, half, hr, gr, e, o);
+        oc[0] = e[0], oc[P] = o[0];
+      } else if (PER && wraps(i0, half)) {
+        T e[CP], o[CP];
+        synth_run_wrap<T, NU, CP>(tmp + c, tmp + half * P + c, P, i0, half, hr, gr, e, o);
+#pragma unroll
+        for (int p = 0; p < CP; ++p) oc[2 * p * P] = e[p], oc[(2 * p + 1) * P] = o[p];
+      } else if (PER || (pair_is_interior<NU>(i0, half) && pair_is_interior<NU>(i0 + CP - 1, half))) {
         T e[CP], o[CP];
         synth_run<T, NU, CP>(tmp + (i0 + LO) * P + c, tmp + (half + i0 + LO) * P + c, P, hr, gr, e, o);
 #pragma unroll
@@ -467,7 +522,7 @@ __global__ void __launch_bounds__(1024) k_synth2d_coarse(const T* __restrict__ x
 
 // One workgroup: analysis levels kc-1 down to j0 on the 2^kc block read from
 // in (trans: in^T); writes the whole 2^kc block of the quadtree into x.
-template <typename T, int NU>
+template <typename T, int NU, bool PER>
 __global__ void __launch_bounds__(1024) k_analysis2d_coarse(const T* __restrict__ in, int64_t ld_in, int trans,
                                                             T* __restrict__ x, int64_t ld_x, int j0, int kc,
                                                             Tables<T> t) {
@@ -503,6 +558,8 @@ __global__ void __launch_bounds__(1024) k_analysis2d_coarse(const T* __restrict_
   }
   __syncthreads();
   constexpr int CP = 2;
+  // the periodic extension: runs that cross an end read modulo size
+  auto wraps = [&](int m0, int size) { return 2 * m0 - NU + 1 < 0 || 2 * (m0 + CP - 1) + NU > size - 1; };
   for (int k = kc - 1; k >= j0; --k) {
     const int half = 1 << k, size = 2 * half;
     const int runs = (half + CP - 1) / CP;
@@ -511,7 +568,16 @@ __global__ void __launch_bounds__(1024) k_analysis2d_coarse(const T* __restrict_
       const int i = item % size, m0 = (item / size) * CP;
       const T* xr = blk + i * P;
       T* yr = tmp + i * P + m0;
-      if (m0 >= NU && m0 + CP - 1 < half - NU) {
+      if (PER && half < CP) {
+        T a[1], d[1];
+        analysis_run_wrap<T, NU, 1>(xr, 1, m0, size, hr, gr, a, d);
+        yr[0] = a[0], yr[half] = d[0];
+      } else if (PER && wraps(m0, size)) {
+        T a[CP], d[CP];
+        analysis_run_wrap<T, NU, CP>(xr, 1, m0, size, hr, gr, a, d);
+#pragma unroll
+        for (int p = 0; p < CP; ++p) yr[p] = a[p], yr[half + p] = d[p];
+      } else if (PER || (m0 >= NU && m0 + CP - 1 < half - NU)) {
         T a[CP], d[CP];
         analysis_run<T, NU, CP>(xr + 2 * m0 - NU + 1, 1, hr, gr, a, d);
 #pragma unroll
@@ -533,7 +599,16 @@ __global__ void __launch_bounds__(1024) k_analysis2d_coarse(const T* __restrict_
     // columns: work item = (column, run of CP outputs)
     for (int item = int(threadIdx.x); item < size * runs; item += 1024) {
       const int c = item % size, m0 = (item / size) * CP;
-      if (m0 >= NU && m0 + CP - 1 < half - NU) {
+      if (PER && half < CP) {
+        T a[1], d[1];
+        analysis_run_wrap<T, NU, 1>(tmp + c, P, m0, size, hr, gr, a, d);
+        blk[m0 * P + c] = a[0], blk[(half + m0) * P + c] = d[0];
+      } else if (PER && wraps(m0, size)) {
+        T a[CP], d[CP];
+        analysis_run_wrap<T, NU, CP>(tmp + c, P, m0, size, hr, gr, a, d);
+#pragma unroll
+        for (int p = 0; p < CP; ++p) blk[(m0 + p) * P + c] = a[p], blk[(half + m0 + p) * P + c] = d[p];
+      } else if (PER || (m0 >= NU && m0 + CP - 1 < half - NU)) {
         T a[CP], d[CP];
         analysis_run<T, NU, CP>(tmp + (2 * m0 - NU + 1) * P + c, P, hr, gr, a, d);
 #pragma unroll
@@ -574,22 +649,28 @@ constexpr int coarse_limit(int j) {
 
 // Largest input window (rows of one half) over the tiles of a level, from
 // the same range functions the kernels use.
-template <int NU>
+template <int NU, bool PER>
 int max_synth_window(int half, int ts) {
   int w = 0;
   for (int n0 = 0; n0 < 2 * half; n0 += ts) {
     int lo, hi;
-    synth_input_range<NU>(n0, n0 + ts, half, lo, hi);
+    if (PER)
+      synth_input_range_per<NU>(n0, n0 + ts, lo, hi);
+    else
+      synth_input_range<NU>(n0, n0 + ts, half, lo, hi);
     w = hi - lo + 1 > w ? hi - lo + 1 : w;
   }
   return w;
 }
-template <int NU>
+template <int NU, bool PER>
 int max_analysis_window(int half, int th) {
   int w = 0;
   for (int m0 = 0; m0 < half; m0 += th) {
     int lo, hi;
-    analysis_input_range<NU>(m0, m0 + th, half, lo, hi);
+    if (PER)
+      analysis_input_range_per<NU>(m0, m0 + th, lo, hi);
+    else
+      analysis_input_range<NU>(m0, m0 + th, half, lo, hi);
     w = hi - lo + 1 > w ? hi - lo + 1 : w;
   }
   return w;
@@ -623,43 +704,43 @@ constexpr TileShape analysis_shape(int half, int nu) {
   return s.t < nu ? TileShape{16, 2} : s;
 }
 
-template <typename T, int NU, int TS, int P>
+template <typename T, int NU, bool PER, int TS, int P>
 hipError_t launch_synth_direct(const T* ll, const T* det, T* dst, int64_t M, int k, int trans, const Tables<T>& t,
                                hipStream_t st) {
   const int half = 1 << k, size = 2 * half;
   if (size % TS || TS < NU) return hipErrorInvalidValue;
-  const int nc = max_synth_window<NU>(half, TS);
+  const int nc = max_synth_window<NU, PER>(half, TS);
   const size_t smem = size_t(TS) * (2 * nc + 1) * sizeof(T);
   const int ntile = size / TS;
-  hipLaunchKernelGGL((k_synth2d_direct<T, NU, TS, P>), dim3(unsigned(ntile * ntile)), dim3(256), smem, st, ll, det, M,
-                     dst, M, k, trans, t);
+  hipLaunchKernelGGL((k_synth2d_direct<T, NU, TS, P, PER>), dim3(unsigned(ntile * ntile)), dim3(256), smem, st, ll,
+                     det, M, dst, M, k, trans, t);
   return hipGetLastError();
 }
 
-template <typename T, int NU, int TH, int P>
+template <typename T, int NU, bool PER, int TH, int P>
 hipError_t launch_analysis_direct(const T* src, int trans, T* dst, T* x, int64_t M, int k, const Tables<T>& t,
                                   hipStream_t st) {
   const int half = 1 << k;
   if (half % TH || TH < NU) return hipErrorInvalidValue;
-  const int nq = max_analysis_window<NU>(half, TH);
+  const int nq = max_analysis_window<NU, PER>(half, TH);
   const size_t smem = size_t(2 * TH) * (nq + 1) * sizeof(T);
   const int ntile = half / TH;
-  hipLaunchKernelGGL((k_analysis2d_direct<T, NU, TH, P>), dim3(unsigned(ntile * ntile)), dim3(256), smem, st, src, M,
-                     trans, dst, M, x, M, k, t);
+  hipLaunchKernelGGL((k_analysis2d_direct<T, NU, TH, P, PER>), dim3(unsigned(ntile * ntile)), dim3(256), smem, st,
+                     src, M, trans, dst, M, x, M, k, t);
   return hipGetLastError();
 }
 
-template <typename T, int NU, int TH, int P>
+template <typename T, int NU, bool PER, int TH, int P>
 hipError_t launch_analysis(const T* src, int trans, T* dst, T* x, int64_t M, int k, const Tables<T>& t,
                            hipStream_t st) {
   const int half = 1 << k;
   if (half % TH || TH < NU) return hipErrorInvalidValue;
-  const int nr = max_analysis_window<NU>(half, TH);
+  const int nr = max_analysis_window<NU, PER>(half, TH);
   if (nr > analysis_window_max<NU, TH>()) return hipErrorInvalidValue;  // the kernel's load window
   const size_t smem = (size_t(nr) * (nr + 1) + size_t(nr) * (2 * TH + 1)) * sizeof(T);
   const int ntile = half / TH;
-  hipLaunchKernelGGL((k_analysis2d_tile<T, NU, TH, P>), dim3(unsigned(ntile * ntile)), dim3(256), smem, st, src, M,
-                     trans, dst, M, x, M, k, t);
+  hipLaunchKernelGGL((k_analysis2d_tile<T, NU, TH, P, PER>), dim3(unsigned(ntile * ntile)), dim3(256), smem, st, src,
+                     M, trans, dst, M, x, M, k, t);
   return hipGetLastError();
 }
 
@@ -669,11 +750,13 @@ template <typename T, int NU>
 hipError_t copy_transposed(const T* in, T* out, int64_t M, int j, const Tables<T>& t, hipStream_t st) {
   if (M >= 32) return transpose<T>(in, out, M, st);
   const size_t smem = 2 * size_t(M) * (M + 1) * sizeof(T);
-  hipLaunchKernelGGL((k_synth2d_coarse<T, NU>), dim3(1), dim3(1024), smem, st, in, M, out, M, j, j, 1, t);
+  hipLaunchKernelGGL((k_synth2d_coarse<T, NU, false>), dim3(1), dim3(1024), smem, st, in, M, out, M, j, j, 1, t);
   return hipGetLastError();
 }
 
-template <typename T, int NU>
+// PER: the periodic extension (indices modulo each level's size, no
+// boundary functions) in the same kernels.
+template <typename T, int NU, bool PER>
 hipError_t idwt2d_impl(const T* x, T* outT, T* s0, T* s1, int64_t M, int j0, int j, const Tables<T>& t,
                        hipStream_t st) {
   if (j0 == j) return copy_transposed<T, NU>(x, outT, M, j, t, st);
@@ -687,7 +770,7 @@ hipError_t idwt2d_impl(const T* x, T* outT, T* s0, T* s1, int64_t M, int j0, int
     const int S = 1 << kc;
     const size_t smem_c = 2 * size_t(S) * (S + 1) * sizeof(T);
     T* prev = last ? outT : s0;
-    hipLaunchKernelGGL((k_synth2d_coarse<T, NU>), dim3(1), dim3(1024), smem_c, st, x, M, prev, M, j0, kc,
+    hipLaunchKernelGGL((k_synth2d_coarse<T, NU, PER>), dim3(1), dim3(1024), smem_c, st, x, M, prev, M, j0, kc,
                        last ? 1 : 0, t);
     e = hipGetLastError();
     if (e != hipSuccess || last) return e;
@@ -698,20 +781,20 @@ hipError_t idwt2d_impl(const T* x, T* outT, T* s0, T* s1, int64_t M, int j0, int
     T* dst = fin ? outT : (ll == s0 ? s1 : s0);
     const TileShape sh = synth_shape<T>(2 << k);
     if (sh.t == 64)
-      e = launch_synth_direct<T, NU, 64, 8>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
+      e = launch_synth_direct<T, NU, PER, 64, 8>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
     else if (sh.t == 32)
-      e = launch_synth_direct<T, NU, 32, 2>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
+      e = launch_synth_direct<T, NU, PER, 32, 2>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
     else if (sh.p == 1)
-      e = launch_synth_direct<T, NU, 16, 1>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
+      e = launch_synth_direct<T, NU, PER, 16, 1>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
     else
-      e = launch_synth_direct<T, NU, 16, 2>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
+      e = launch_synth_direct<T, NU, PER, 16, 2>(ll, x, dst, M, k, fin ? 1 : 0, t, st);
     if (e != hipSuccess) return e;
     ll = dst;
   }
   return hipSuccess;
 }
 
-template <typename T, int NU>
+template <typename T, int NU, bool PER>
 hipError_t dwt2d_impl(const T* inT, T* x, T* s0, T* s1, int64_t M, int j0, int j, const Tables<T>& t,
                       hipStream_t st) {
   if (j0 == j) return copy_transposed<T, NU>(inT, x, M, j, t, st);
@@ -726,35 +809,36 @@ hipError_t dwt2d_impl(const T* inT, T* x, T* s0, T* s1, int64_t M, int j0, int j
     T* dst = (!coarse && k == kc) ? x : ((src == s0) ? s1 : s0);
     const TileShape sh = analysis_shape<T>(1 << k, NU);
     if (sh.t == 32)
-      e = launch_analysis_direct<T, NU, 32, 8>(src, trans, dst, x, M, k, t, st);
+      e = launch_analysis_direct<T, NU, PER, 32, 8>(src, trans, dst, x, M, k, t, st);
     else if (sh.t == 16)
-      e = launch_analysis<T, NU, 16, 2>(src, trans, dst, x, M, k, t, st);
+      e = launch_analysis<T, NU, PER, 16, 2>(src, trans, dst, x, M, k, t, st);
     else if (sh.p == 1)
-      e = launch_analysis<T, NU, 8, 1>(src, trans, dst, x, M, k, t, st);
+      e = launch_analysis<T, NU, PER, 8, 1>(src, trans, dst, x, M, k, t, st);
     else
-      e = launch_analysis<T, NU, 8, 2>(src, trans, dst, x, M, k, t, st);
+      e = launch_analysis<T, NU, PER, 8, 2>(src, trans, dst, x, M, k, t, st);
     if (e != hipSuccess) return e;
     src = dst;
     trans = 0;
   }
   if (!coarse) return hipSuccess;
   const size_t smem_c = 2 * size_t(S) * (S + 1) * sizeof(T);
-  hipLaunchKernelGGL((k_analysis2d_coarse<T, NU>), dim3(1), dim3(1024), smem_c, st, src, M, trans, x, M, j0, kc, t);
+  hipLaunchKernelGGL((k_analysis2d_coarse<T, NU, PER>), dim3(1), dim3(1024), smem_c, st, src, M, trans, x, M, j0, kc,
+                     t);
   return hipGetLastError();
 }
 
 // Raise the dynamic-LDS limit of the kernels that need more than 64 KB (once
 // per plan, outside any stream work).
-template <typename T, int NU>
+template <typename T, int NU, bool PER>
 hipError_t prepare_impl() {
   // 160 KB per workgroup, less the static table each kernel keeps in LDS
   const int lim = 160 * 1024 - int(tab_lds_size<NU>() * sizeof(T));
   const void* kernels[] = {
-      (const void*)k_synth2d_coarse<T, NU>,         (const void*)k_analysis2d_coarse<T, NU>,
-      (const void*)k_analysis2d_tile<T, NU, 16, 2>, (const void*)k_analysis2d_tile<T, NU, 8, 2>,
-      (const void*)k_analysis2d_tile<T, NU, 8, 1>,  (const void*)k_synth2d_direct<T, NU, 64, 8>,
-      (const void*)k_synth2d_direct<T, NU, 32, 2>,  (const void*)k_synth2d_direct<T, NU, 16, 2>,
-      (const void*)k_synth2d_direct<T, NU, 16, 1>,  (const void*)k_analysis2d_direct<T, NU, 32, 8>,
+      (const void*)k_synth2d_coarse<T, NU, PER>,         (const void*)k_analysis2d_coarse<T, NU, PER>,
+      (const void*)k_analysis2d_tile<T, NU, 16, 2, PER>, (const void*)k_analysis2d_tile<T, NU, 8, 2, PER>,
+      (const void*)k_analysis2d_tile<T, NU, 8, 1, PER>,  (const void*)k_synth2d_direct<T, NU, 64, 8, PER>,
+      (const void*)k_synth2d_direct<T, NU, 32, 2, PER>,  (const void*)k_synth2d_direct<T, NU, 16, 2, PER>,
+      (const void*)k_synth2d_direct<T, NU, 16, 1, PER>,  (const void*)k_analysis2d_direct<T, NU, 32, 8, PER>,
   };
   for (const void* f : kernels) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
@@ -769,7 +853,11 @@ hipError_t prepare_impl() {
 
 template <typename T>
 hipError_t prepare_dwt2d(int nu) {
-#define X(V) if (nu == V) return prepare_impl<T, V>();
+#define X(V) \
+  if (nu == V) { \
+    const hipError_t e = prepare_impl<T, V, false>(); \
+    return e == hipSuccess ? prepare_impl<T, V, true>() : e; \
+  }
   WH2WAV_DWT_NUS(X)
 #undef X
   return hipErrorInvalidValue;
@@ -780,7 +868,10 @@ template hipError_t prepare_dwt2d<double>(int);
 template <typename T>
 hipError_t idwt2d(const T* x, T* outT, T* s0, T* s1, int64_t M, int j0, int j, const Tables<T>& t,
                   hipStream_t st) {
-#define X(V) if (t.nu == V) return idwt2d_impl<T, V>(x, outT, s0, s1, M, j0, j, t, st);
+#define X(V) \
+  if (t.nu == V) \
+    return t.per ? idwt2d_impl<T, V, true>(x, outT, s0, s1, M, j0, j, t, st) \
+                 : idwt2d_impl<T, V, false>(x, outT, s0, s1, M, j0, j, t, st);
   WH2WAV_DWT_NUS(X)
 #undef X
   return hipErrorInvalidValue;
@@ -789,7 +880,10 @@ hipError_t idwt2d(const T* x, T* outT, T* s0, T* s1, int64_t M, int j0, int j, c
 template <typename T>
 hipError_t dwt2d(const T* inT, T* x, T* s0, T* s1, int64_t M, int j0, int j, const Tables<T>& t,
                  hipStream_t st) {
-#define X(V) if (t.nu == V) return dwt2d_impl<T, V>(inT, x, s0, s1, M, j0, j, t, st);
+#define X(V) \
+  if (t.nu == V) \
+    return t.per ? dwt2d_impl<T, V, true>(inT, x, s0, s1, M, j0, j, t, st) \
+                 : dwt2d_impl<T, V, false>(inT, x, s0, s1, M, j0, j, t, st);
   WH2WAV_DWT_NUS(X)
 #undef X
   return hipErrorInvalidValue;

@@ -104,6 +104,20 @@ __host__ __device__ __forceinline__ void analysis_input_range(int m0, int m1, in
   (void)ROWS;
 }
 
+// Periodic extension: the input index ranges of synthesis outputs [n0, n1)
+// and of analysis outputs [m0, m1), unclamped (taken modulo the line length
+// where they are read).
+template <int NU>
+__host__ __device__ __forceinline__ void synth_input_range_per(int n0, int n1, int& lo, int& hi) {
+  lo = (n0 - NU) >> 1;
+  hi = (n1 - 1 + NU) >> 1;
+}
+template <int NU>
+__host__ __device__ __forceinline__ void analysis_input_range_per(int m0, int m1, int& lo, int& hi) {
+  lo = 2 * m0 - NU + 1;
+  hi = 2 * (m1 - 1) + NU;
+}
+
 // Interior synthesis pair i: every filter tap of outputs 2i and 2i+1 lands on
 // an interior coefficient (3nu-1 <= 2i and 2i+1 <= size-3nu).
 template <int NU>
@@ -129,6 +143,13 @@ __host__ __device__ constexpr int synth_hi() {
   return v;
 }
 
+// The filter taps of P consecutive synthesis pairs i0 .. i0+P-1 applied to
+// a(i0 + lo + u) = a[u], d(i0 + lo + u) = d[u].
+template <typename T, int NU, int P>
+__device__ __forceinline__ void synth_math(const T (&a)[P + synth_hi<NU>() - synth_lo<NU>()],
+                                           const T (&d)[P + synth_hi<NU>() - synth_lo<NU>()],
+                                           const T (&hr)[2 * NU], const T (&gr)[2 * NU], T (&e)[P], T (&o)[P]);
+
 // P consecutive interior synthesis pairs i0 .. i0+P-1 of one line.  pa points
 // at a(i0 + lo), pd at d(i0 + lo); consecutive m are `stride` elements apart.
 // Inputs are read once into registers and reused by every tap.
@@ -142,6 +163,31 @@ __device__ __forceinline__ void synth_run(const T* __restrict__ pa, const T* __r
     a[u] = pa[u * stride];
     d[u] = pd[u * stride];
   }
+  synth_math<T, NU, P>(a, d, hr, gr, e, o);
+}
+
+// The same run for the periodic extension (Sec. 3.2), any i0: pa and pd point
+// at a(0) and d(0), and the coefficient index is taken modulo half.
+template <typename T, int NU, int P>
+__device__ __forceinline__ void synth_run_wrap(const T* __restrict__ pa, const T* __restrict__ pd, int stride, int i0,
+                                               int half, const T (&hr)[2 * NU], const T (&gr)[2 * NU], T (&e)[P],
+                                               T (&o)[P]) {
+  constexpr int LO = synth_lo<NU>(), L = P + synth_hi<NU>() - LO;
+  T a[L], d[L];
+#pragma unroll
+  for (int u = 0; u < L; ++u) {
+    const int m = (i0 + LO + u) & (half - 1);
+    a[u] = pa[m * stride];
+    d[u] = pd[m * stride];
+  }
+  synth_math<T, NU, P>(a, d, hr, gr, e, o);
+}
+
+template <typename T, int NU, int P>
+__device__ __forceinline__ void synth_math(const T (&a)[P + synth_hi<NU>() - synth_lo<NU>()],
+                                           const T (&d)[P + synth_hi<NU>() - synth_lo<NU>()],
+                                           const T (&hr)[2 * NU], const T (&gr)[2 * NU], T (&e)[P], T (&o)[P]) {
+  constexpr int LO = synth_lo<NU>();
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     T ae = T(0), ao = T(0);
@@ -161,6 +207,12 @@ __device__ __forceinline__ void synth_run(const T* __restrict__ pa, const T* __r
   }
 }
 
+// The filter taps of P consecutive analysis outputs m0 .. m0+P-1 applied to
+// x(2 m0 - nu + 1 + u) = v[u].
+template <typename T, int NU, int P>
+__device__ __forceinline__ void analysis_math(const T (&v)[2 * P + 2 * NU - 2], const T (&hr)[2 * NU],
+                                              const T (&gr)[2 * NU], T (&a)[P], T (&d)[P]);
+
 // P consecutive interior analysis outputs m0 .. m0+P-1 (scaling and wavelet
 // coefficient of each); px points at x(2 m0 - nu + 1).
 template <typename T, int NU, int P>
@@ -170,6 +222,25 @@ __device__ __forceinline__ void analysis_run(const T* __restrict__ px, int strid
   T v[L];
 #pragma unroll
   for (int u = 0; u < L; ++u) v[u] = px[u * stride];
+  analysis_math<T, NU, P>(v, hr, gr, a, d);
+}
+
+// The same run for the periodic extension, any m0: px points at x(0), and
+// the input index is taken modulo size = 2 half.
+template <typename T, int NU, int P>
+__device__ __forceinline__ void analysis_run_wrap(const T* __restrict__ px, int stride, int m0, int size,
+                                                  const T (&hr)[2 * NU], const T (&gr)[2 * NU], T (&a)[P],
+                                                  T (&d)[P]) {
+  constexpr int L = 2 * P + 2 * NU - 2;
+  T v[L];
+#pragma unroll
+  for (int u = 0; u < L; ++u) v[u] = px[((2 * m0 - NU + 1 + u) & (size - 1)) * stride];
+  analysis_math<T, NU, P>(v, hr, gr, a, d);
+}
+
+template <typename T, int NU, int P>
+__device__ __forceinline__ void analysis_math(const T (&v)[2 * P + 2 * NU - 2], const T (&hr)[2 * NU],
+                                              const T (&gr)[2 * NU], T (&a)[P], T (&d)[P]) {
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     T sa = T(0), sd = T(0);

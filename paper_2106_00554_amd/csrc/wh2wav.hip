@@ -300,43 +300,6 @@ int launch_transpose(const T* in, T* out, int64_t n, hipStream_t st) {
   return WH2WAV_OK;
 }
 
-// Periodic extension, 2D inverse DWT x -> xi^T (out).  Each isotropic level
-// S X S^T runs as one-level synthesis along the columns, then along the rows
-// of the top-left 2^{k+1} block.  The levels run in the transposed frame:
-// the same synthesis applied to x^T (whose blocks are the transposed bands)
-// yields xi^T.  W, Z: M x M scratch.
-template <typename T>
-int idwt2d_per(const wh2wav_plan_s* p, const T* x, T* out, T* W, T* Z, hipStream_t st) {
-  const auto& H = p->host;
-  const int64_t M = H.M;
-  if (H.j0 == H.j) return launch_transpose<T>(x, out, M, st);
-  int rc = launch_transpose<T>(x, W, M, st);
-  for (int k = H.j0; k < H.j && rc == WH2WAV_OK; ++k) {
-    const int64_t size = int64_t(2) << k;
-    rc = launch_synth<T>(p, W, Z, size, 1, M, k, true, false, st);  // columns
-    if (rc == WH2WAV_OK) rc = launch_synth<T>(p, Z, k + 1 == H.j ? out : W, size, M, 1, k, false, false, st);
-  }
-  return rc;
-}
-
-// Its transpose: xi'^T (in) -> x.  in is read only by the first level.
-template <typename T>
-int dwt2d_per(const wh2wav_plan_s* p, const T* in, T* x, T* W, T* Z, hipStream_t st) {
-  const auto& H = p->host;
-  const int64_t M = H.M;
-  if (H.j0 == H.j) return launch_transpose<T>(in, x, M, st);
-  const T* src = in;
-  int rc = WH2WAV_OK;
-  for (int k = H.j - 1; k >= H.j0 && rc == WH2WAV_OK; --k) {
-    const int64_t size = int64_t(2) << k;
-    rc = launch_synth<T>(p, src, Z, size, M, 1, k, false, true, st);  // rows
-    if (rc == WH2WAV_OK) rc = launch_synth<T>(p, Z, W, size, 1, M, k, true, true, st);  // columns
-    src = W;
-  }
-  if (rc == WH2WAV_OK) rc = launch_transpose<T>(W, x, M, st);
-  return rc;
-}
-
 // Tensor-product basis: x[c1][c2] is the coefficient of r_{c1} (x) r_{c2}, so
 // xi = W x W^T with W the 1D multilevel synthesis (boundary-corrected or
 // periodic, as the plan says).  In the transposed frame xi^T = W x^T W^T: the
@@ -618,10 +581,7 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
   if (run(0) && H.tensor) {  // xi^T into TMP; W serves as scratch
     int rc = idwt2d_tensor<T>(p, x, TMP, W, st);
     if (rc) return rc;
-  } else if (run(0) && H.per) {  // xi^T into TMP; W and Z serve as scratch
-    int rc = idwt2d_per<T>(p, x, TMP, W, Z, st);
-    if (rc) return rc;
-  } else if (run(0)) {  // xi^T into TMP (tiled 2D wavelet kernels, every shape); W and Z serve as scratch
+  } else if (run(0)) {  // xi^T into TMP (tiled 2D wavelet kernels, every shape, boundary or periodic); W and Z serve as scratch
     HIP_OK(wh2wav_fast::idwt2d<T>(x, TMP, W, Z, M, H.j0, H.j, fast_tables_of<T>(p), st));
   }
   if (fast) {
@@ -707,7 +667,6 @@ int adjoint_impl(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t
     if (run(0)) HIP_OK(wh2wav_fast::rowpass_adj<T>(y, Z, H.j, fast_tables_of<T>(p), fast_omega_of(p), N, st));
     if (run(1)) HIP_OK(wh2wav_fast::colpass_adj<T>(Z, TMP, H.j, fast_tables_of<T>(p), st));
     if (run(2) && H.tensor) return dwt2d_tensor<T>(p, TMP, x, W, st);
-    if (run(2) && H.per) return dwt2d_per<T>(p, TMP, x, W, Z, st);
     if (run(2)) HIP_OK(wh2wav_fast::dwt2d<T>(TMP, x, W, Z, M, H.j0, H.j, fast_tables_of<T>(p), st));
     return WH2WAV_OK;
   }
@@ -726,7 +685,6 @@ int adjoint_impl(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t
     HIP_OK(hipGetLastError());
   }
   if (run(2) && H.tensor) return dwt2d_tensor<T>(p, TMP, x, W, st);
-  if (run(2) && H.per) return dwt2d_per<T>(p, TMP, x, W, Z, st);
   if (run(2)) HIP_OK(wh2wav_fast::dwt2d<T>(TMP, x, W, Z, M, H.j0, H.j, fast_tables_of<T>(p), st));
   return WH2WAV_OK;
 }
