@@ -96,13 +96,14 @@ hipError_t line1d_fwd(const T* xi, T* L, T* y, int j, const Tables<T>& t, const 
 template <typename T>
 hipError_t line1d_adj(const T* y, T* L, T* xi, int j, const Tables<T>& t, const int32_t* pos, int64_t m, int full,
                       hipStream_t st);
-// Every wavelet level of `lines` lines of 2^j values (rows of a row-major
-// array, line strides ld_in and ld_out; in == out allowed), one line per
+// Every wavelet level of `lines` lines of 2^j values, one line per
 // workgroup in LDS: synthesis j0 .. j-1, or with `analysis` its transpose.
-// lines_levels_fit: whether a line of 2^j values of this element size fits.
+// Line r starts at (r / inner) os + r % inner, its values es apart, in `in`
+// and `out` alike (in == out allowed).  lines_levels_fit: whether a line of
+// 2^j values of this element size fits.
 bool lines_levels_fit(int elem_bytes, int j);
 template <typename T>
-hipError_t lines_levels(const T* in, int64_t ld_in, T* out, int64_t ld_out, int64_t lines, int j0, int j,
+hipError_t lines_levels(const T* in, T* out, int64_t lines, int64_t inner, int64_t os, int64_t es, int j0, int j,
                         int analysis, const Tables<T>& t, hipStream_t st);
 // One-time setup (dynamic LDS limits) of the 1D wavelet kernels of order nu.
 template <typename T>

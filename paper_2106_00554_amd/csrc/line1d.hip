@@ -53,14 +53,17 @@ __global__ void __launch_bounds__(1024) k_synth1d_coarse(const T* __restrict__ x
 }
 
 // Every wavelet level of `lines` lines of 2^j values, one line per
-// workgroup in LDS: line r is in[r ld_in .. r ld_in + 2^j) and goes to
-// out[r ld_out ..].  Synthesis (levels j0 .. j-1, C_{psi,j} order to the
-// scaling coefficients at level j) or, with ANALYSIS, its transpose;
-// boundary-corrected or periodic as the tables say.  in and out may be the
-// same array (each workgroup reads its whole line before it writes).
+// workgroup in LDS: line r starts at (r / inner) os + r % inner and its
+// values are es apart, in `in` and in `out` alike (rows of a row-major array:
+// inner 1, os the row length, es 1; an axis of a d-dimensional array: inner
+// and es the product of the later extents, os 2^j times that).  Synthesis
+// (levels j0 .. j-1, C_{psi,j} order to the scaling coefficients at level
+// j) or, with ANALYSIS, its transpose; boundary-corrected or periodic as the
+// tables say.  in and out may be the same array (each workgroup reads its
+// whole line before it writes).
 template <typename T, int NU, bool ANALYSIS>
-__global__ void __launch_bounds__(256) k_lines_levels(const T* in, int64_t ld_in, T* out, int64_t ld_out, int j0,
-                                                      int j, Tables<T> t) {
+__global__ void __launch_bounds__(256) k_lines_levels(const T* in, T* out, int64_t inner, int64_t os, int64_t es,
+                                                      int j0, int j, Tables<T> t) {
   extern __shared__ unsigned char smem_raw[];
   __shared__ T tab_lds[tab_lds_size<NU>()];
   T hr[2 * NU], gr[2 * NU];
@@ -68,8 +71,8 @@ __global__ void __launch_bounds__(256) k_lines_levels(const T* in, int64_t ld_in
   const int S = 1 << j, tid = int(threadIdx.x);
   T* a = reinterpret_cast<T*>(smem_raw);
   T* b = a + S;
-  const T* src = in + int64_t(blockIdx.x) * ld_in;
-  for (int i = tid; i < S; i += 256) a[i] = src[i];
+  const int64_t r = blockIdx.x, base = (r / inner) * os + r % inner;
+  for (int i = tid; i < S; i += 256) a[i] = in[base + i * es];
   __syncthreads();
   if (t.per) {
     if constexpr (ANALYSIS)
@@ -82,8 +85,7 @@ __global__ void __launch_bounds__(256) k_lines_levels(const T* in, int64_t ld_in
     else
       synth_levels_lds<T, NU>(a, b, j0, j, tl, hr, gr);
   }
-  T* dst = out + int64_t(blockIdx.x) * ld_out;
-  for (int i = tid; i < S; i += 256) dst[i] = a[i];
+  for (int i = tid; i < S; i += 256) out[base + i * es] = a[i];
 }
 
 // Analysis levels kc-1 .. j0 of the line in[0, 2^kc) in one workgroup; writes
@@ -388,17 +390,18 @@ hipError_t line1d_adj_impl(const T* y, T* L, T* xi, int j, const Tables<T>& t, c
 }
 
 template <typename T, int NU>
-hipError_t lines_levels_impl(const T* in, int64_t ld_in, T* out, int64_t ld_out, int64_t lines, int j0, int j,
+hipError_t lines_levels_impl(const T* in, T* out, int64_t lines, int64_t inner, int64_t os, int64_t es, int j0, int j,
                              int analysis, const Tables<T>& t, hipStream_t st) {
-  if (j < 1 || j > lds_line_log<T>() || j0 < 0 || j0 > j || lines < 1 || lines > (int64_t(1) << 30))
+  if (j < 1 || j > lds_line_log<T>() || j0 < 0 || j0 > j || lines < 1 || lines > (int64_t(1) << 30) || inner < 1 ||
+      os < 1 || es < 1)
     return hipErrorInvalidValue;
   const size_t smem = 2 * (size_t(1) << j) * sizeof(T);
   if (analysis)
-    hipLaunchKernelGGL((k_lines_levels<T, NU, true>), dim3(unsigned(lines)), dim3(256), smem, st, in, ld_in, out,
-                       ld_out, j0, j, t);
+    hipLaunchKernelGGL((k_lines_levels<T, NU, true>), dim3(unsigned(lines)), dim3(256), smem, st, in, out, inner, os,
+                       es, j0, j, t);
   else
-    hipLaunchKernelGGL((k_lines_levels<T, NU, false>), dim3(unsigned(lines)), dim3(256), smem, st, in, ld_in, out,
-                       ld_out, j0, j, t);
+    hipLaunchKernelGGL((k_lines_levels<T, NU, false>), dim3(unsigned(lines)), dim3(256), smem, st, in, out, inner, os,
+                       es, j0, j, t);
   return hipGetLastError();
 }
 
@@ -454,9 +457,9 @@ hipError_t line1d_adj(const T* y, T* L, T* xi, int j, const Tables<T>& t, const 
   return hipErrorInvalidValue;
 }
 template <typename T>
-hipError_t lines_levels(const T* in, int64_t ld_in, T* out, int64_t ld_out, int64_t lines, int j0, int j,
+hipError_t lines_levels(const T* in, T* out, int64_t lines, int64_t inner, int64_t os, int64_t es, int j0, int j,
                         int analysis, const Tables<T>& t, hipStream_t st) {
-#define X(V) if (t.nu == V) return lines_levels_impl<T, V>(in, ld_in, out, ld_out, lines, j0, j, analysis, t, st);
+#define X(V) if (t.nu == V) return lines_levels_impl<T, V>(in, out, lines, inner, os, es, j0, j, analysis, t, st);
   WH2WAV_1D_NUS(X)
 #undef X
   return hipErrorInvalidValue;
@@ -477,8 +480,8 @@ hipError_t prepare_1d(int nu) {
                                     hipStream_t);                                                                \
   template hipError_t line1d_adj<T>(const T*, T*, T*, int, const Tables<T>&, const int32_t*, int64_t, int,         \
                                     hipStream_t);                                                                \
-  template hipError_t lines_levels<T>(const T*, int64_t, T*, int64_t, int64_t, int, int, int, const Tables<T>&,   \
-                                      hipStream_t);                                                              \
+  template hipError_t lines_levels<T>(const T*, T*, int64_t, int64_t, int64_t, int64_t, int, int, int,             \
+                                      const Tables<T>&, hipStream_t);                                            \
   template hipError_t prepare_1d<T>(int);
 INST_(float)
 INST_(double)

@@ -338,9 +338,9 @@ int idwt2d_tensor(const wh2wav_plan_s* p, const T* x, T* out, T* W, hipStream_t 
   if (tensor_lines(p)) {
     const auto ft = fast_tables_of<T>(p);
     const int64_t M = H.M;
-    HIP_OK(wh2wav_fast::lines_levels<T>(x, M, W, M, M, H.j0, H.j, 0, ft, st));
+    HIP_OK(wh2wav_fast::lines_levels<T>(x, W, M, 1, M, 1, H.j0, H.j, 0, ft, st));
     HIP_OK(wh2wav_fast::transpose<T>(W, out, M, st));
-    HIP_OK(wh2wav_fast::lines_levels<T>(out, M, out, M, M, H.j0, H.j, 0, ft, st));
+    HIP_OK(wh2wav_fast::lines_levels<T>(out, out, M, 1, M, 1, H.j0, H.j, 0, ft, st));
     return WH2WAV_OK;
   }
   int rc = launch_transpose<T>(x, out, H.M, st);
@@ -358,9 +358,9 @@ int dwt2d_tensor(const wh2wav_plan_s* p, T* in, T* x, T* W, hipStream_t st) {
   if (tensor_lines(p)) {
     const auto ft = fast_tables_of<T>(p);
     const int64_t M = H.M;
-    HIP_OK(wh2wav_fast::lines_levels<T>(in, M, in, M, M, H.j0, H.j, 1, ft, st));
+    HIP_OK(wh2wav_fast::lines_levels<T>(in, in, M, 1, M, 1, H.j0, H.j, 1, ft, st));
     HIP_OK(wh2wav_fast::transpose<T>(in, W, M, st));
-    HIP_OK(wh2wav_fast::lines_levels<T>(W, M, x, M, M, H.j0, H.j, 1, ft, st));
+    HIP_OK(wh2wav_fast::lines_levels<T>(W, x, M, 1, M, 1, H.j0, H.j, 1, ft, st));
     return WH2WAV_OK;
   }
   int rc = WH2WAV_OK;
@@ -413,6 +413,30 @@ int nd_level(const wh2wav_plan_s* p, const T* in, T* out, int axis, int k, bool 
   return WH2WAV_OK;
 }
 
+// Tensor basis on the per-axis path: every level of an axis in one launch of
+// the LDS line kernels (lines along the axis, values strided by the product
+// of the later extents), when every axis's lines fit.
+bool nd_tensor_lines(const wh2wav_plan_s* p) {
+  const auto& H = p->host;
+  if (!H.nd || !H.tensor) return false;
+  for (int a = 0; a < H.dim; ++a)
+    if (!wh2wav_fast::lines_levels_fit(H.dtype == WH2WAV_F64 ? 8 : 4, H.ja[a])) return false;
+  return true;
+}
+
+// All levels along axis a of the M_0 x M_1 x M_2 array (synthesis, or the
+// analysis with `analysis`), src -> dst (the same array allowed).
+template <typename T>
+int nd_axis_levels(const wh2wav_plan_s* p, const T* src, T* dst, int a, bool analysis, hipStream_t st) {
+  const auto& H = p->host;
+  int64_t es = 1;
+  for (int b = a + 1; b < 3; ++b) es *= H.Ma[b];
+  const int64_t lines = H.Ma[0] * H.Ma[1] * H.Ma[2] / H.Ma[a];
+  HIP_OK(wh2wav_fast::lines_levels<T>(src, dst, lines, es, H.Ma[a] * es, es, H.j0, H.ja[a], analysis ? 1 : 0,
+                                      fast_tables_of<T>(p), st));
+  return WH2WAV_OK;
+}
+
 // One launch of the line kernels on the per-axis path: G (fwd) or G^T along
 // axis `a`, `lines` lines.
 template <typename T>
@@ -444,7 +468,14 @@ int forward_nd(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t s
   T* W = static_cast<T*>(ws);
   T *XA = W + b.xa, *XB = W + b.xb, *Z0 = W + b.z0, *Z1 = W + b.z1;
   const int64_t M0 = H.Ma[0], M1 = H.Ma[1], M2 = H.Ma[2], N0 = H.Na[0], N1 = H.Na[1];
-  if (run(0)) {
+  if (run(0) && nd_tensor_lines(p)) {  // axis by axis, x -> XA, then in place
+    const T* src = x;
+    for (int a = 0; a < H.dim; ++a) {
+      int rc = nd_axis_levels<T>(p, src, XA, a, false, st);
+      if (rc) return rc;
+      src = XA;
+    }
+  } else if (run(0)) {
     const auto levels = nd_levels(H);
     if (levels.empty()) HIP_OK(hipMemcpyAsync(XA, x, sizeof(T) * size_t(M0 * M1 * M2), hipMemcpyDeviceToDevice, st));
     const T* src = x;
@@ -511,6 +542,13 @@ int adjoint_nd(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t s
     }
   }
   if (rc || !run(2)) return rc;
+  if (nd_tensor_lines(p)) {  // axis by axis in reverse order, in place on XA; the last writes x
+    for (int a = H.dim - 1; a >= 0; --a) {
+      rc = nd_axis_levels<T>(p, XA, a == 0 ? x : XA, a, true, st);
+      if (rc) return rc;
+    }
+    return WH2WAV_OK;
+  }
   auto levels = nd_levels(H);
   if (levels.empty()) {
     HIP_OK(hipMemcpyAsync(x, XA, sizeof(T) * size_t(M0 * M1 * M2), hipMemcpyDeviceToDevice, st));
@@ -825,6 +863,10 @@ int plan_body(const wh2wav_desc* desc, wh2wav_plan_t* out) {
                                 : wh2wav_fast::prepare_lines<float>(H.j, H.nu);
     if (e == hipSuccess && tensor_lines(p))
       e = H.dtype == WH2WAV_F64 ? wh2wav_fast::prepare_1d<double>(H.nu) : wh2wav_fast::prepare_1d<float>(H.nu);
+    if (e != hipSuccess) return fail(WH2WAV_EHIP, std::string("kernel setup: ") + hipGetErrorString(e));
+  }
+  if (nd_tensor_lines(p)) {
+    hipError_t e = H.dtype == WH2WAV_F64 ? wh2wav_fast::prepare_1d<double>(H.nu) : wh2wav_fast::prepare_1d<float>(H.nu);
     if (e != hipSuccess) return fail(WH2WAV_EHIP, std::string("kernel setup: ") + hipGetErrorString(e));
   }
   if (use_fast1d(p)) {
