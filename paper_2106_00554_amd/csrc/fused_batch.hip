@@ -111,9 +111,11 @@ __global__ void __launch_bounds__(kThreads) k_round(const Inst<T>* __restrict__ 
         if (S.out_too) buffer<T>(I, kOut, ws, io, S.inst)[pos] = v;
       }
     } else if (S.kind == kFwdLines) {
-      fwd_line<T>(src, S.im, dst, S.omap, S.j, S.gather, S.rm, I.t, I.om, tile, smem_raw);
+      fwd_line<T>(src, S.im, dst, S.omap, S.j, S.gather, S.rm, I.t, I.om, tile, smem_raw, int(threadIdx.x),
+                  int(blockDim.x));
     } else {
-      adj_line<T>(src, S.im, dst, S.omap, S.j, S.gather, S.rm, I.t, I.om, tile, smem_raw);
+      adj_line<T>(src, S.im, dst, S.omap, S.j, S.gather, S.rm, I.t, I.om, tile, smem_raw, int(threadIdx.x),
+                  int(blockDim.x));
     }
     __syncthreads();  // the next item reuses the LDS
   }

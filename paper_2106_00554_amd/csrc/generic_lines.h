@@ -304,16 +304,18 @@ __device__ __forceinline__ int64_t omega_row(int64_t line, const RowMap& rm, int
   return sequency_row(line / N1, rm.jl0) * N1 + sequency_row(line % N1, rm.jl1);
 }
 
-// Forward G on line `line` of M = 2^j values, by the whole workgroup (blockDim
-// threads, all of which must call it; smem: 2 M values and, when gathering
-// from a sparse Omega, wpr + blockDim ints).  gather == 0: write the N
+// Forward G on line `line` of M = 2^j values, by a group of nt threads
+// (thread tid of the group; smem: the group's 2 M values and, when gathering
+// from a sparse Omega, wpr + nt ints).  Every thread of the workgroup must
+// call it, with groups of the same size: its barriers are workgroup-wide,
+// and every group passes the same sequence of them.  gather == 0: write the N
 // outputs in natural order r = s M + k at element r of output line `line`.
 // gather == 1: the samples of the line's Omega row go to y (`out`).
 template <typename T>
 __device__ void fwd_line(const T* __restrict__ in, const LineMap& im, T* __restrict__ out, const LineMap& omap, int j,
          int gather, const RowMap& rm,
-            const Tables<T>& t, const OmegaDev& om, int64_t line, unsigned char* smem) {
-  const int M = 1 << j, Q = t.Q, tid = threadIdx.x, nt = blockDim.x;
+            const Tables<T>& t, const OmegaDev& om, int64_t line, unsigned char* smem, int tid, int nt) {
+  const int M = 1 << j, Q = t.Q;
   T* xi = reinterpret_cast<T*>(smem);
   T* L = xi + M;
   int* pre = reinterpret_cast<int*>(L + M);
@@ -368,8 +370,8 @@ __device__ void fwd_line(const T* __restrict__ in, const LineMap& im, T* __restr
 template <typename T>
 __device__ void adj_line(const T* __restrict__ in, const LineMap& im, T* __restrict__ out, const LineMap& omap, int j,
          int scatter, const RowMap& rm,
-            const Tables<T>& t, const OmegaDev& om, int64_t line, unsigned char* smem) {
-  const int M = 1 << j, Q = t.Q, tid = threadIdx.x, nt = blockDim.x;
+            const Tables<T>& t, const OmegaDev& om, int64_t line, unsigned char* smem, int tid, int nt) {
+  const int M = 1 << j, Q = t.Q;
   T* xi = reinterpret_cast<T*>(smem);
   T* R = xi + M;
   int* pre = reinterpret_cast<int*>(R + M);

@@ -135,21 +135,27 @@ void launch_fill(T* out, int64_t n, hipStream_t st) {
 // ------------------------------------------------------------ line kernels
 LineMap lines_at(int64_t ls, int64_t es) { return LineMap{int64_t(1) << 62, 0, ls, es}; }
 
-// G (k_fwd_lines) and G^T (k_adj_lines) on one line per workgroup.
+// G (k_fwd_lines) and G^T (k_adj_lines): lpw lines per workgroup, each by
+// blockDim / lpw threads in its own lbytes of LDS (short lines share a
+// workgroup instead of leaving most of its threads idle).
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_fwd_lines(const T* __restrict__ in, LineMap im, T* __restrict__ out, LineMap omap, int j, int gather, RowMap rm,
-            Tables<T> t, OmegaDev om) {
+            Tables<T> t, OmegaDev om, int lpw, int lbytes) {
   extern __shared__ unsigned char smem_raw[];
-  fwd_line<T>(in, im, out, omap, j, gather, rm, t, om, int64_t(blockIdx.x), smem_raw);
+  const int G = int(blockDim.x) / lpw, sub = int(threadIdx.x) / G;
+  fwd_line<T>(in, im, out, omap, j, gather, rm, t, om, int64_t(blockIdx.x) * lpw + sub, smem_raw + sub * lbytes,
+              int(threadIdx.x) % G, G);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_adj_lines(const T* __restrict__ in, LineMap im, T* __restrict__ out, LineMap omap, int j, int scatter, RowMap rm,
-            Tables<T> t, OmegaDev om) {
+            Tables<T> t, OmegaDev om, int lpw, int lbytes) {
   extern __shared__ unsigned char smem_raw[];
-  adj_line<T>(in, im, out, omap, j, scatter, rm, t, om, int64_t(blockIdx.x), smem_raw);
+  const int G = int(blockDim.x) / lpw, sub = int(threadIdx.x) / G;
+  adj_line<T>(in, im, out, omap, j, scatter, rm, t, om, int64_t(blockIdx.x) * lpw + sub, smem_raw + sub * lbytes,
+              int(threadIdx.x) % G, G);
 }
 
 }  // namespace
@@ -256,12 +262,6 @@ OmegaDev omega_of(const wh2wav_plan_s* p) {
   return o;
 }
 
-size_t line_smem(const wh2wav_plan_s* p, size_t elem, bool omega_side, int64_t M = 0) {
-  size_t b = 2 * size_t(M ? M : p->host.M) * elem;
-  if (omega_side && !p->host.full_omega) b += sizeof(int) * (size_t(p->host.words_per_row) + kThreads);
-  return b;
-}
-
 constexpr size_t kMaxLds = 160 * 1024;
 
 // The dynamic-LDS limit of the line kernels is raised once per plan
@@ -270,6 +270,32 @@ template <typename T>
 int check_and_set_smem(const void* kernel, size_t bytes) {
   (void)kernel;
   if (bytes > kMaxLds) return fail(WH2WAV_EUNSUPPORTED, "line too long for the LDS line kernels");
+  return WH2WAV_OK;
+}
+
+// G (fwd) or G^T on `lines` lines of 2^j values through the generic line
+// kernels.  Lines shorter than a workgroup share one: lpw of them, each with
+// kThreads / lpw threads and its own LDS.
+template <typename T>
+int launch_lines(const wh2wav_plan_s* p, bool fwd, int64_t lines, int j, const T* in, LineMap im, T* out,
+                 LineMap om_, int omega_side, RowMap rm, const Tables<T>& tab, hipStream_t st) {
+  const int64_t M = int64_t(1) << j;
+  int lpw = int(kThreads / (M < kThreads ? M : kThreads));
+  while (lpw > 1 && lines % lpw) lpw >>= 1;
+  const int G = kThreads / lpw;
+  size_t lb = 2 * size_t(M) * sizeof(T);
+  if (omega_side && !p->host.full_omega) lb += sizeof(int) * (size_t(p->host.words_per_row) + G);
+  lb = (lb + 15) / 16 * 16;
+  int rc = check_and_set_smem<T>(nullptr, lb * lpw);
+  if (rc) return rc;
+  const dim3 grid(unsigned(lines / lpw));
+  if (fwd)
+    hipLaunchKernelGGL(k_fwd_lines<T>, grid, dim3(kThreads), lb * lpw, st, in, im, out, om_, j, omega_side, rm, tab,
+                       omega_of(p), lpw, int(lb));
+  else
+    hipLaunchKernelGGL(k_adj_lines<T>, grid, dim3(kThreads), lb * lpw, st, in, im, out, om_, j, omega_side, rm, tab,
+                       omega_of(p), lpw, int(lb));
+  HIP_OK(hipGetLastError());
   return WH2WAV_OK;
 }
 
@@ -442,19 +468,7 @@ int nd_axis_levels(const wh2wav_plan_s* p, const T* src, T* dst, int a, bool ana
 template <typename T>
 int nd_pass(const wh2wav_plan_s* p, bool fwd, int a, int64_t lines, const T* in, LineMap im, T* out, LineMap om_,
             int omega_side, RowMap rm, hipStream_t st) {
-  const auto& H = p->host;
-  const size_t smem = line_smem(p, sizeof(T), omega_side != 0, H.Ma[a]);
-  const void* kern = fwd ? (const void*)k_fwd_lines<T> : (const void*)k_adj_lines<T>;
-  int rc = check_and_set_smem<T>(kern, smem);
-  if (rc) return rc;
-  if (fwd)
-    hipLaunchKernelGGL(k_fwd_lines<T>, dim3(unsigned(lines)), dim3(kThreads), smem, st, in, im, out, om_, H.ja[a],
-                       omega_side, rm, axis_tables_of<T>(p, a), omega_of(p));
-  else
-    hipLaunchKernelGGL(k_adj_lines<T>, dim3(unsigned(lines)), dim3(kThreads), smem, st, in, im, out, om_, H.ja[a],
-                       omega_side, rm, axis_tables_of<T>(p, a), omega_of(p));
-  HIP_OK(hipGetLastError());
-  return WH2WAV_OK;
+  return launch_lines<T>(p, fwd, lines, p->host.ja[a], in, im, out, om_, omega_side, rm, axis_tables_of<T>(p, a), st);
 }
 
 // Forward stages: 0 = inverse DWT into XA, 1 = G along every axis but the
@@ -572,7 +586,6 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
   const auto& H = p->host;
   const int64_t M = H.M, N = H.N;
   const Tables<T> t = tables_of<T>(p);
-  const OmegaDev om = omega_of(p);
   if (H.nd) return forward_nd<T>(p, x, y, ws, st, stage);
   if (H.m == 0) return WH2WAV_OK;
   T* W = static_cast<T*>(ws);
@@ -595,7 +608,10 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
   }
   if (H.dim == 1) {
     T* TMP = W + M;
-    if (run(0)) {
+    const bool one_launch = wh2wav_fast::lines_levels_fit(H.dtype == WH2WAV_F64 ? 8 : 4, H.j);
+    if (run(0) && one_launch) {  // every level of the line in one workgroup
+      HIP_OK(wh2wav_fast::lines_levels<T>(x, W, 1, 1, M, 1, H.j0, H.j, 0, fast_tables_of<T>(p), st));
+    } else if (run(0)) {
       HIP_OK(hipMemcpyAsync(W, x, sizeof(T) * M, hipMemcpyDeviceToDevice, st));
       for (int k = H.j0; k < H.j; ++k) {
         int rc = launch_synth<T>(p, W, TMP, 1, 0, 1, k, false, false, st);
@@ -604,12 +620,8 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
       }
     }
     if (run(1)) {
-      size_t smem = line_smem(p, sizeof(T), true);
-      int rc = check_and_set_smem<T>((const void*)k_fwd_lines<T>, smem);
+      int rc = launch_lines<T>(p, true, 1, H.j, W, lines_at(0, 1), y, lines_at(0, 0), 1, RowMap{0, 0, 0}, t, st);
       if (rc) return rc;
-      hipLaunchKernelGGL(k_fwd_lines<T>, dim3(1), dim3(kThreads), smem, st, W, lines_at(0, 1), y, lines_at(0, 0), H.j,
-                         1, RowMap{0, 0, 0}, t, om);
-      HIP_OK(hipGetLastError());
     }
     return WH2WAV_OK;
   }
@@ -627,21 +639,12 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
     if (run(2)) HIP_OK(wh2wav_fast::rowpass_fwd<T>(Z, y, H.j, fast_tables_of<T>(p), fast_omega_of(p), N, st));
     return WH2WAV_OK;
   }
-  int rc = check_and_set_smem<T>((const void*)k_fwd_lines<T>, line_smem(p, sizeof(T), true));
-  if (rc) return rc;
-  if (run(1)) {  // column pass: G along the first index (rows of xi^T); Z[r, m2] with r natural
-    size_t smem0 = line_smem(p, sizeof(T), false);
-    hipLaunchKernelGGL(k_fwd_lines<T>, dim3(unsigned(M)), dim3(kThreads), smem0, st, TMP, lines_at(M, 1), Z,
-                       lines_at(1, M), H.j, 0, RowMap{0, 0, 0}, t, om);
-    HIP_OK(hipGetLastError());
-  }
-  if (run(2)) {  // row pass: G along the second index, gather Omega
-    size_t smem1 = line_smem(p, sizeof(T), true);
-    hipLaunchKernelGGL(k_fwd_lines<T>, dim3(unsigned(N)), dim3(kThreads), smem1, st, Z, lines_at(M, 1), y,
-                       lines_at(0, 0), H.j, 1, RowMap{1, H.j, 0}, t, om);
-    HIP_OK(hipGetLastError());
-  }
-  return WH2WAV_OK;
+  int rc = WH2WAV_OK;
+  if (run(1))  // column pass: G along the first index (rows of xi^T); Z[r, m2] with r natural
+    rc = launch_lines<T>(p, true, M, H.j, TMP, lines_at(M, 1), Z, lines_at(1, M), 0, RowMap{0, 0, 0}, t, st);
+  if (rc == WH2WAV_OK && run(2))  // row pass: G along the second index, gather Omega
+    rc = launch_lines<T>(p, true, N, H.j, Z, lines_at(M, 1), y, lines_at(0, 0), 1, RowMap{1, H.j, 0}, t, st);
+  return rc;
 }
 
 // Adjoint stages: 0 = row pass with the Omega scatter (2D) / line transform
@@ -651,7 +654,6 @@ int adjoint_impl(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t
   const auto& H = p->host;
   const int64_t M = H.M, N = H.N;
   const Tables<T> t = tables_of<T>(p);
-  const OmegaDev om = omega_of(p);
   if (H.nd) return adjoint_nd<T>(p, y, x, ws, st, stage);
   T* W = static_cast<T*>(ws);
   auto run = [&](int s) { return stage < 0 || stage == s; };
@@ -682,14 +684,13 @@ int adjoint_impl(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t
   if (H.dim == 1) {
     T* TMP = W + M;
     if (run(0)) {
-      size_t smem = line_smem(p, sizeof(T), true);
-      int rc = check_and_set_smem<T>((const void*)k_adj_lines<T>, smem);
+      int rc = launch_lines<T>(p, false, 1, H.j, y, lines_at(0, 0), W, lines_at(0, 1), 1, RowMap{0, 0, 0}, t, st);
       if (rc) return rc;
-      hipLaunchKernelGGL(k_adj_lines<T>, dim3(1), dim3(kThreads), smem, st, y, lines_at(0, 0), W, lines_at(0, 1), H.j,
-                         1, RowMap{0, 0, 0}, t, om);
-      HIP_OK(hipGetLastError());
     }
-    if (run(2)) {
+    const bool one_launch = wh2wav_fast::lines_levels_fit(H.dtype == WH2WAV_F64 ? 8 : 4, H.j);
+    if (run(2) && one_launch) {
+      HIP_OK(wh2wav_fast::lines_levels<T>(W, x, 1, 1, M, 1, H.j0, H.j, 1, fast_tables_of<T>(p), st));
+    } else if (run(2)) {
       for (int k = H.j - 1; k >= H.j0; --k) {
         int rc = launch_synth<T>(p, W, TMP, 1, 0, 1, k, false, true, st);
         if (rc) return rc;
@@ -708,20 +709,12 @@ int adjoint_impl(const wh2wav_plan_s* p, const T* y, T* x, void* ws, hipStream_t
     if (run(2)) HIP_OK(wh2wav_fast::dwt2d<T>(TMP, x, W, Z, M, H.j0, H.j, fast_tables_of<T>(p), st));
     return WH2WAV_OK;
   }
-  int rc = check_and_set_smem<T>((const void*)k_adj_lines<T>, line_smem(p, sizeof(T), true));
+  int rc = WH2WAV_OK;
+  if (run(0))
+    rc = launch_lines<T>(p, false, N, H.j, y, lines_at(0, 0), Z, lines_at(M, 1), 1, RowMap{1, H.j, 0}, t, st);
+  if (rc == WH2WAV_OK && run(1))  // column pass, transposed: xi'^T into TMP
+    rc = launch_lines<T>(p, false, M, H.j, Z, lines_at(1, M), TMP, lines_at(M, 1), 0, RowMap{0, 0, 0}, t, st);
   if (rc) return rc;
-  if (run(0)) {
-    size_t smem1 = line_smem(p, sizeof(T), true);
-    hipLaunchKernelGGL(k_adj_lines<T>, dim3(unsigned(N)), dim3(kThreads), smem1, st, y, lines_at(0, 0), Z,
-                       lines_at(M, 1), H.j, 1, RowMap{1, H.j, 0}, t, om);
-    HIP_OK(hipGetLastError());
-  }
-  if (run(1)) {  // column pass, transposed: xi'^T into TMP
-    size_t smem0 = line_smem(p, sizeof(T), false);
-    hipLaunchKernelGGL(k_adj_lines<T>, dim3(unsigned(M)), dim3(kThreads), smem0, st, Z, lines_at(1, M), TMP,
-                       lines_at(M, 1), H.j, 0, RowMap{0, 0, 0}, t, om);
-    HIP_OK(hipGetLastError());
-  }
   if (run(2) && H.tensor) return dwt2d_tensor<T>(p, TMP, x, W, st);
   if (run(2)) HIP_OK(wh2wav_fast::dwt2d<T>(TMP, x, W, Z, M, H.j0, H.j, fast_tables_of<T>(p), st));
   return WH2WAV_OK;
@@ -865,7 +858,7 @@ int plan_body(const wh2wav_desc* desc, wh2wav_plan_t* out) {
       e = H.dtype == WH2WAV_F64 ? wh2wav_fast::prepare_1d<double>(H.nu) : wh2wav_fast::prepare_1d<float>(H.nu);
     if (e != hipSuccess) return fail(WH2WAV_EHIP, std::string("kernel setup: ") + hipGetErrorString(e));
   }
-  if (nd_tensor_lines(p)) {
+  if (nd_tensor_lines(p) || (H.dim == 1 && !use_fast1d(p))) {
     hipError_t e = H.dtype == WH2WAV_F64 ? wh2wav_fast::prepare_1d<double>(H.nu) : wh2wav_fast::prepare_1d<float>(H.nu);
     if (e != hipSuccess) return fail(WH2WAV_EHIP, std::string("kernel setup: ") + hipGetErrorString(e));
   }
