@@ -35,7 +35,8 @@ More legs are reported in the same JSON line (skip with --no-extras):
   (about 600 MB live, beyond the 256 MB MALL), pairs/s and the row passes'
   per-launch time and HBM rate;
 * "variants": symlets, the periodic extension and the tensor-product basis on
-  the roofline workload's shape, and two shapes of the generic line kernels;
+  the roofline workload's shape, 1024^2 db10, 4096^2 db4 (generic line
+  kernels), 64^3 db4 and 2048 x 256 db4 (tensor basis);
 * "batched": 96 uneven instances (1D 2^12..2^16, 2D 128^2..512^2 and 1024^2,
   db2/db4/db8, q = 1, 2, 10-30 % Omega, FP32) as one graph launch per
   direction (eight branches, largest instances first), against per-instance
@@ -340,9 +341,10 @@ def small_configs_leg(torch, steps, outputs=None):
 
 def variants_leg(torch, steps):
     """Pairs/s of the widened operators on the roofline workload's shape and of
-    shapes served by the generic kernels: symlets, the periodic extension and
-    the tensor-product basis at 2048^2 db8 q = 2 (12.5 % Omega), the generic
-    line kernels at 1024^2 db10 q = 1 and 4096^2 db4 q = 1 (10 % Omega), and
+    other shapes: symlets, the periodic extension and the tensor-product basis
+    at 2048^2 db8 q = 2 (12.5 % Omega), the longest filters at 1024^2 db10
+    q = 1 and the generic line kernels (lines beyond the wave kernels) at
+    4096^2 db4 q = 1 (10 % Omega), and
     the per-axis path: 64^3 db4 q = 1 (isotropic, 12.5 % Omega) and unequal
     sides 2048 x 256 db4 q = 1 (tensor basis, 12.5 % Omega); all FP32."""
     from paper_2106_00554_amd.operator import Wh2Wav
@@ -356,7 +358,7 @@ def variants_leg(torch, steps):
              ("db8_tensor", dict(nu=8, j=11, q=2, j0=4, basis2d="tensor"), X, omega)]
     for nu, j, q, j0, dens in ((10, 10, 1, 5, 0.1), (4, 12, 1, 3, 0.1)):
         N = 1 << (j + q)
-        cases.append((f"db{nu}_{1 << j}sq_generic", dict(nu=nu, j=j, q=q, j0=j0),
+        cases.append((f"db{nu}_{1 << j}sq" + ("_generic" if j > 11 else ""), dict(nu=nu, j=j, q=q, j0=j0),
                       inputs.coefficients_2d(j, j0, 700 + j), inputs.multilevel_omega_2d(N, dens, 701 + j)))
     cases.append(("db4_64cube_3d", dict(dim=3, nu=4, j=6, q=1, j0=3), inputs.coefficients_nd((64, 64, 64), 760),
                   inputs.uniform_omega(128 ** 3, 0.125, 761)))

@@ -137,6 +137,7 @@ __device__ __forceinline__ void line_forward(const T (&xi)[R], T (&v)[R], int s,
       bv = left || right ? bv : T(0);
     }
     if constexpr (R >= B) {
+      static_assert(R + 2 * B <= 64, "the other lanes must read zero lanes B .. B + R - 1");
       // the bands sit in lanes 0 and 63.  Register k of lane 0 takes lane k
       // (left band row k for k < B, a zero lane beyond), of lane 63 lane
       // 64 - R + k (right band row k - (R - B) for k >= R - B, a zero lane
@@ -774,11 +775,13 @@ hipError_t launch_line1d_adj(const T* y, T* x, int j0, const Tables<T>& t, const
 
 // Supported (log2 M, nu).  Lines of M = 128 .. 2048 values (R = 2 .. 32 per
 // lane); boundary values and the table-product halo may span several lanes.
+// (log2 M, nu) of the wave kernels.  nu = 9, 10 stop at M = 1024: the band
+// exchange of the forward line needs R + 2 (2 nu - 1) <= 64 (R = M / 64).
 #define WH2WAV_FAST_CASES(X)                                                       \
-  X(7, 2) X(7, 3) X(7, 4) X(7, 5) X(7, 6) X(7, 7) X(7, 8)                          \
-  X(8, 2) X(8, 3) X(8, 4) X(8, 5) X(8, 6) X(8, 7) X(8, 8)                          \
-  X(9, 2) X(9, 3) X(9, 4) X(9, 5) X(9, 6) X(9, 7) X(9, 8)                          \
-  X(10, 2) X(10, 3) X(10, 4) X(10, 5) X(10, 6) X(10, 7) X(10, 8)                   \
+  X(7, 2) X(7, 3) X(7, 4) X(7, 5) X(7, 6) X(7, 7) X(7, 8) X(7, 9) X(7, 10)         \
+  X(8, 2) X(8, 3) X(8, 4) X(8, 5) X(8, 6) X(8, 7) X(8, 8) X(8, 9) X(8, 10)         \
+  X(9, 2) X(9, 3) X(9, 4) X(9, 5) X(9, 6) X(9, 7) X(9, 8) X(9, 9) X(9, 10)         \
+  X(10, 2) X(10, 3) X(10, 4) X(10, 5) X(10, 6) X(10, 7) X(10, 8) X(10, 9) X(10, 10) \
   X(11, 2) X(11, 3) X(11, 4) X(11, 5) X(11, 6) X(11, 7) X(11, 8)
 
 }  // namespace

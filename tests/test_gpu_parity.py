@@ -50,6 +50,7 @@ CASES_1D = [
     (4, 8, 4, 3, 0.3),  # q = 4: sixteen phase waves per workgroup
     (10, 7, 1, 5, 0.4),  # the longest filters
     (5, 8, 1, 4, 0.3), (7, 9, 1, 4, None), (9, 6, 2, 5, 0.5),  # the remaining orders
+    (9, 9, 1, 5, 0.3), (10, 10, 2, 5, None),  # nu = 9, 10 on the wave line kernels
 ]
 
 
@@ -294,6 +295,7 @@ CASES_2D_WAVE = [
     (3, 7, 4, 3, 0.2),  # q = 4: sixteen phase waves per row workgroup
     (5, 8, 1, 4, 0.2), (7, 9, 2, 4, None), (5, 10, 1, 4, 0.25), (7, 7, 1, 4, 0.3),  # odd orders 5 and 7
     (4, 11, 1, 3, 0.1), (2, 11, 1, 2, None),  # 2048-value lines: two phase groups in the adjoint column pass (FP32)
+    (9, 8, 1, 5, 0.2), (10, 10, 1, 5, None), (10, 7, 2, 5, 0.3), (9, 10, 2, 5, 0.25),  # nu = 9, 10 up to M = 1024
 ]
 
 
