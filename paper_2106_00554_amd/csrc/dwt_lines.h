@@ -548,6 +548,73 @@ __device__ void analysis_levels_lds(T* a, T* b, int j0, int kc, const TileLds<T>
   }
 }
 
+// Synthesis levels j0 .. kc-1 with three line buffers of 2^kc values: src
+// holds [a_j0 | d_j0 | ... | d_{kc-1}] and is only read (every level reads
+// its details there), the approximations alternate between fin and tmp so
+// that the last level writes fin.  Every level writes a buffer that it does
+// not read: one barrier per level and no copy back.
+template <typename T, int NU>
+__device__ void synth_levels_lds3(const T* src, T* fin, T* tmp, int j0, int kc, const TileLds<T>& tl,
+                                  const T (&hr)[2 * NU], const T (&gr)[2 * NU]) {
+  const int tid = int(threadIdx.x), nt = int(blockDim.x);
+  constexpr int LO = synth_lo<NU>();
+  if (j0 == kc) {
+    for (int i = tid; i < (1 << kc); i += nt) fin[i] = src[i];
+    __syncthreads();
+    return;
+  }
+  const T* ap = src;  // approximations of the current level
+  for (int k = j0; k < kc; ++k) {
+    const int half = 1 << k;
+    const T* dp = src + half;  // its details
+    T* out = ((kc - 1 - k) % 2 == 0) ? fin : tmp;
+    for (int i0 = tid; i0 < half; i0 += nt) {
+      T e[1], o[1];
+      if (pair_is_interior<NU>(i0, half)) {
+        synth_run<T, NU, 1>(ap + i0 + LO, dp + i0 + LO, 1, hr, gr, e, o);
+      } else {
+        synth_run_edge<T, NU, 1>(ap, dp, 1, 0, half - 1, i0, half, hr, gr, tl.sLs, tl.sRs, e, o);
+      }
+      out[2 * i0] = e[0];
+      out[2 * i0 + 1] = o[0];
+    }
+    __syncthreads();
+    ap = out;
+  }
+}
+
+// Its transpose with three buffers: line (2^kc values, read by the first
+// level, then scratch), tmp, and fin, which receives [a_j0 | d_j0 | ... |
+// d_{kc-1}]: every level writes its details into fin at their final place
+// and its approximations into the buffer it does not read (fin at the last
+// level).  One barrier per level.
+template <typename T, int NU>
+__device__ void analysis_levels_lds3(T* line, T* fin, T* tmp, int j0, int kc, const TileLds<T>& tl,
+                                     const T (&hr)[2 * NU], const T (&gr)[2 * NU]) {
+  const int tid = int(threadIdx.x), nt = int(blockDim.x);
+  if (j0 == kc) {
+    for (int i = tid; i < (1 << kc); i += nt) fin[i] = line[i];
+    __syncthreads();
+    return;
+  }
+  T* ap = line;
+  for (int k = kc - 1; k >= j0; --k) {
+    const int half = 1 << k, size = 2 * half;
+    T* aout = k == j0 ? fin : (ap == line ? tmp : line);
+    for (int m0 = tid; m0 < half; m0 += nt) {
+      T av[1], dv[1];
+      if (m0 >= NU && m0 < half - NU)
+        analysis_run<T, NU, 1>(ap + 2 * m0 - NU + 1, 1, hr, gr, av, dv);
+      else
+        analysis_run_edge<T, NU, 1>(ap, 1, 0, size - 1, m0, half, hr, gr, tl.sLs, tl.sRs, av, dv);
+      aout[m0] = av[0];
+      fin[half + m0] = dv[0];
+    }
+    __syncthreads();
+    ap = aout;
+  }
+}
+
 // The periodic extension (Sec. 3.2): synthesis levels j0 .. kc-1 of a line
 // in LDS with every index taken modulo the level's length (no boundary
 // functions); layout, scratch and barriers as synth_levels_lds.  Output pair

@@ -436,13 +436,17 @@ __global__ void __launch_bounds__(1024) k_rowpass_adj(const T* __restrict__ y, T
 // line transform, the cross-wave sum and the analysis levels (adjoint).
 
 // LDS of the fused kernels, in elements (besides the static table copy).
+// forward: the final line, then two lines for the wavelet levels (their
+// input and scratch), which the phase waves then reuse for the gather (half a
+// line each); adjoint: a line per phase wave, at least three lines for the
+// levels.
 template <int LOGM>
 constexpr int line1d_fwd_lds(int Q) {
-  return (1 << LOGM) + ((Q << LOGM) / 2 > (1 << LOGM) ? (Q << LOGM) / 2 : (1 << LOGM));
+  return (1 << LOGM) + ((Q << LOGM) / 2 > (2 << LOGM) ? (Q << LOGM) / 2 : (2 << LOGM));
 }
 template <int LOGM>
 constexpr int line1d_adj_lds(int Q) {
-  return Q << LOGM;
+  return (Q > 3 ? Q : 3) << LOGM;
 }
 
 template <typename T, int LOGM, int NU>
@@ -457,13 +461,12 @@ __global__ void __launch_bounds__(1024) k_line1d_fwd(const T* __restrict__ x, T*
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int Q = t.Q;
   T* a = reinterpret_cast<T*>(smem_raw);  // the line; then a half line per phase wave from a + M
-  T* b = a + M;
+  T* b = a + M;                            // the coefficients, then scratch of the levels
   PhaseGather<T, LOGM> g;
   if (wave < Q) g.prepare(om, y, 0, wave, Q, lane);
-  for (int i = tid; i < M; i += int(blockDim.x)) a[i] = x[i];
+  for (int i = tid; i < M; i += int(blockDim.x)) b[i] = x[i];
   __syncthreads();
-  lines::synth_levels_lds<T, NU>(a, b, j0, LOGM, tl, hr, gr);
-  __syncthreads();
+  lines::synth_levels_lds3<T, NU>(b, a, b + M, j0, LOGM, tl, hr, gr);
   if (wave >= Q) return;
   T xi[R];
   load_line<T, R>(a + lane * R, xi);
@@ -515,9 +518,8 @@ __global__ void __launch_bounds__(1024) k_line1d_adj(const T* __restrict__ y, T*
   __syncthreads();
   if (c < M / CW) store_line<T, CW>(bufs + c * CW, sum);
   __syncthreads();
-  lines::analysis_levels_lds<T, NU>(bufs, bufs + M, j0, LOGM, tl, hr, gr);
-  __syncthreads();
-  for (int i = tid; i < M; i += int(blockDim.x)) x[i] = bufs[i];
+  lines::analysis_levels_lds3<T, NU>(bufs, bufs + 2 * M, bufs + M, j0, LOGM, tl, hr, gr);
+  for (int i = tid; i < M; i += int(blockDim.x)) x[i] = bufs[2 * M + i];
 }
 
 // ---------------------------------------------------------- column passes
@@ -800,7 +802,7 @@ bool line1d_fused(int elem_bytes, int logm, int nu, int q) {
   if (!supported(elem_bytes, logm, nu, q) || logm > 11) return false;
   const int Q = 1 << q, M = 1 << logm;
   const long long tab = (4LL * nu + 2LL * (3 * nu - 1) * 2 * nu) * elem_bytes;
-  const long long fwd = (M + std::max((Q * M) / 2, M)) * 1LL * elem_bytes, adj = 1LL * Q * M * elem_bytes;
+  const long long fwd = (M + std::max((Q * M) / 2, 2 * M)) * 1LL * elem_bytes, adj = 1LL * std::max(Q, 3) * M * elem_bytes;
   return std::max(fwd, adj) + tab <= 160 * 1024;
 }
 
