@@ -296,6 +296,7 @@ CASES_2D_WAVE = [
     (5, 8, 1, 4, 0.2), (7, 9, 2, 4, None), (5, 10, 1, 4, 0.25), (7, 7, 1, 4, 0.3),  # odd orders 5 and 7
     (4, 11, 1, 3, 0.1), (2, 11, 1, 2, None),  # 2048-value lines: two phase groups in the adjoint column pass (FP32)
     (9, 8, 1, 5, 0.2), (10, 10, 1, 5, None), (10, 7, 2, 5, 0.3), (9, 10, 2, 5, 0.25),  # nu = 9, 10 up to M = 1024
+    (10, 9, 1, 5, 0.2), (9, 9, 3, 5, None),
 ]
 
 
