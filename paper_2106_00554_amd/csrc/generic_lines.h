@@ -1,5 +1,6 @@
-// Generic device code of the operator: one line of the 1D section per
-// workgroup, in LDS, for every shape; the one-level wavelet synthesis and
+// Generic device code of the operator: one line of the 1D section per group
+// of threads (a workgroup, or a share of one for short lines), in LDS, for
+// every shape; the one-level wavelet synthesis and
 // analysis (boundary-corrected and periodic); the index maps.  Used by the
 // plain kernels of the single-plan path and by the fused batch launches.
 //

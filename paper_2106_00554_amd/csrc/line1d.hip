@@ -17,6 +17,10 @@
 // * Gather / scatter: sample i of y sits at flat natural index pos[i] =
 //   s M + bitrev(gray(b)) xor (s & 1) (n = s M + b, Lemma 3.2), so both are
 //   coalesced over i.
+// * Many lines at once (k_lines_levels): every wavelet level of one line per
+//   workgroup, the lines being rows or a strided axis of an array -- the
+//   wavelet stage of the tensor-product basis and of the 1D lines outside
+//   the kernels above.
 #include "dwt_lines.h"
 #include "fast2d.h"
 #include "wave_ops.h"

@@ -327,11 +327,12 @@ int launch_transpose(const T* in, T* out, int64_t n, hipStream_t st) {
 }
 
 // Tensor-product basis: x[c1][c2] is the coefficient of r_{c1} (x) r_{c2}, so
-// xi = W x W^T with W the 1D multilevel synthesis (boundary-corrected or
-// periodic, as the plan says).  In the transposed frame xi^T = W x^T W^T: the
-// full 1D synthesis along every column, then along every row.  Each level
-// writes its block into `tmp`, which is copied back into `cur` (a memcpy
-// node, not a memset, if a caller captures the call).
+// xi = V x V^T with V the 1D multilevel synthesis (boundary-corrected or
+// periodic, as the plan says).  In the transposed frame xi^T = V x^T V^T: the
+// full 1D synthesis along every column, then along every row.  Sides below
+// 32: one launch per level and direction, each level writing its block into
+// `tmp`, which is copied back into `cur` (a memcpy node, not a memset, if a
+// caller captures the call).
 template <typename T>
 int tensor_level(const wh2wav_plan_s* p, T* cur, T* tmp, bool columns, int k, bool analysis, hipStream_t st) {
   const int64_t M = p->host.M, size = int64_t(2) << k;
@@ -355,9 +356,10 @@ bool tensor_lines(const wh2wav_plan_s* p) {
          wh2wav_fast::lines_levels_fit(H.dtype == WH2WAV_F64 ? 8 : 4, H.j);
 }
 
-// Tensor basis, forward first stage: x -> xi^T (out); W scratch.  With the
-// line kernels: U = x W^T (every row of x through the 1D synthesis), its
-// transpose W x^T, and every row of that again: W x^T W^T = xi^T.
+// Tensor basis, forward first stage: x -> xi^T (out); W scratch.  With V the
+// 1D multilevel synthesis and the line kernels: U = x V^T (every row of x
+// through V), its transpose V x^T, and every row of that again:
+// V x^T V^T = xi^T.
 template <typename T>
 int idwt2d_tensor(const wh2wav_plan_s* p, const T* x, T* out, T* W, hipStream_t st) {
   const auto& H = p->host;
@@ -376,8 +378,8 @@ int idwt2d_tensor(const wh2wav_plan_s* p, const T* x, T* out, T* W, hipStream_t 
 }
 
 // Its transpose: xi'^T (in, overwritten) -> x; W scratch.  With the line
-// kernels: every row of xi'^T through the 1D analysis (xi'^T W), the
-// transpose W^T xi', and every row again: W^T xi' W = x.
+// kernels: every row of xi'^T through the 1D analysis V^T (xi'^T V), the
+// transpose V^T xi', and every row again: V^T xi' V = x.
 template <typename T>
 int dwt2d_tensor(const wh2wav_plan_s* p, T* in, T* x, T* W, hipStream_t st) {
   const auto& H = p->host;
