@@ -213,6 +213,34 @@ def test_2d_periodic_db8_j11_q2():
     assert errs["fwd_f32"] < 1e-5 and errs["adj_f32"] < 1e-5
 
 
+@pytest.mark.timeout(900)
+def test_2d_tensor_db8_j11_q2():
+    """The tensor-product basis at the benchmark's full size: db8, M = 2048^2,
+    N = 8192^2, 12.5 % multilevel Omega.  Its wavelet stage runs every level
+    of a 2048-value line in one workgroup, rows, transpose, rows.  Every
+    output and every coefficient against the oracle's A1 X A1^T (the dense
+    1D section applied along both axes), FP64 and FP32.
+    """
+    name = "2d_db8_j11_q2_12.5pct"
+    w = inputs.WORKLOADS[name]
+    X, omega = inputs.workload_inputs(name)
+    cfg = op.Config(w["nu"], w["j"], w["q"], w["j0"], tensor=True)
+    yv = inputs.sample_vector(omega.size, 41)
+    A1 = op.matrix_1d(cfg)
+    y_ref = op.forward_2d_tensor(A1, X, omega)
+    x_ref = op.adjoint_2d_tensor(A1, yv, omega)
+    del A1
+    args = (2, w["nu"], w["j"], w["q"], w["j0"])
+    y64, x64 = gpu_pair(*args, torch.float64, X, omega, yv, basis2d="tensor")
+    y32, x32 = gpu_pair(*args, torch.float32, X, omega, yv, basis2d="tensor")
+    errs = {"fwd_f64": rel(y64, y_ref), "adj_f64": rel(x64, x_ref),
+            "fwd_f32": rel(y32, y_ref), "adj_f32": rel(x32, x_ref)}
+    print("[2048^2 db8 q=2 tensor relative l2 errors] " + ", ".join(f"{k} {v:.3e}" for k, v in errs.items()),
+          flush=True)
+    assert errs["fwd_f64"] < 1e-12 and errs["adj_f64"] < 1e-12
+    assert errs["fwd_f32"] < 1e-5 and errs["adj_f32"] < 1e-5
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_2d_j12_sampled(dtype):
     """2D beyond the wave kernels: db4, M = 4096^2, q = 1, 10 % Omega.
