@@ -1,8 +1,10 @@
 """GPU parity of the three-dimensional and unequal-sided operators against the oracle.
 
 Sec. 5 splits the d-fold inner products into 1D ones; the HIP path runs the
-wavelet levels on the whole array (k_level_nd), then the line transform
-along each axis with that axis's tables, the last pass gathering Omega.  The
+wavelet levels (isotropic: per level and axis on the whole array; tensor:
+every level of an axis in one launch of the LDS line kernel), then the line
+transform along each axis with that axis's tables, the last pass gathering
+Omega.  The
 oracle applies the dense 1D sections axis by axis (forward_nd_*), pinned in
 tests/test_oracle_nd.py.  Bar: relative l2 <= 1e-12 (FP64), <= 1e-5 (FP32).
 """
@@ -98,6 +100,24 @@ def test_three_dimensions_at_64_cubed(tensor):
     y32, x32 = gpu_pair(js, nu, q, j0, False, tensor, torch.float32, X, omega, yv)
     print(f"[64^3 tensor={tensor}] fwd f64 {rel(y64, y_ref):.2e} f32 {rel(y32, y_ref):.2e} "
           f"(vs f64 {rel(y32, y64):.2e}); adj f64 {rel(x64, x_ref):.2e} f32 {rel(x32, x_ref):.2e}", flush=True)
+    assert rel(y64, y_ref) < 1e-12 and rel(x64, x_ref) < 1e-12
+    assert rel(y32, y_ref) < 1e-5 and rel(x32, x_ref) < 1e-5
+
+
+@pytest.mark.timeout(600)
+def test_unequal_sides_2048_by_256():
+    """The tensor basis with unequal sides at 2048 x 256 (db4, q = 1, 12.5 %
+    Omega), FP32 and FP64, every output against the oracle: 2048-value lines
+    along a strided axis in the wavelet stage and both line passes."""
+    js, nu, q, j0 = (11, 8), 4, 1, 3
+    X = inputs.coefficients_nd((2048, 256), 7900)
+    omega = inputs.uniform_omega(4096 * 512, 0.125, 7901)
+    yv = inputs.sample_vector(omega.size, 7902)
+    y_ref, x_ref = oracle_pair(js, nu, q, j0, False, True, X, omega, yv)
+    y64, x64 = gpu_pair(js, nu, q, j0, False, True, torch.float64, X, omega, yv)
+    y32, x32 = gpu_pair(js, nu, q, j0, False, True, torch.float32, X, omega, yv)
+    print(f"[2048 x 256 tensor] fwd f64 {rel(y64, y_ref):.2e} f32 {rel(y32, y_ref):.2e}; "
+          f"adj f64 {rel(x64, x_ref):.2e} f32 {rel(x32, x_ref):.2e}", flush=True)
     assert rel(y64, y_ref) < 1e-12 and rel(x64, x_ref) < 1e-12
     assert rel(y32, y_ref) < 1e-5 and rel(x32, x_ref) < 1e-5
 
