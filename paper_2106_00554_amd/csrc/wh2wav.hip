@@ -137,14 +137,24 @@ LineMap lines_at(int64_t ls, int64_t es) { return LineMap{int64_t(1) << 62, 0, l
 
 // G (k_fwd_lines) and G^T (k_adj_lines): lpw lines per workgroup, each by
 // blockDim / lpw threads in its own lbytes of LDS (short lines share a
-// workgroup instead of leaving most of its threads idle).
+// workgroup instead of leaving most of its threads idle).  The dispatcher
+// deals consecutive workgroups round-robin over the 8 XCDs; the first line
+// of workgroup b is taken so that each XCD gets a contiguous band of lines,
+// and lines that share cache lines (a strided pass over neighbouring
+// columns) meet in one L2.
+__device__ __forceinline__ int64_t first_line(int lpw) {
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  const int64_t wg = nb % 8 == 0 ? (b % 8) * (nb / 8) + b / 8 : b;
+  return wg * lpw;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_fwd_lines(const T* __restrict__ in, LineMap im, T* __restrict__ out, LineMap omap, int j, int gather, RowMap rm,
             Tables<T> t, OmegaDev om, int lpw, int lbytes) {
   extern __shared__ unsigned char smem_raw[];
   const int G = int(blockDim.x) / lpw, sub = int(threadIdx.x) / G;
-  fwd_line<T>(in, im, out, omap, j, gather, rm, t, om, int64_t(blockIdx.x) * lpw + sub, smem_raw + sub * lbytes,
+  fwd_line<T>(in, im, out, omap, j, gather, rm, t, om, first_line(lpw) + sub, smem_raw + sub * lbytes,
               int(threadIdx.x) % G, G);
 }
 
@@ -154,7 +164,7 @@ k_adj_lines(const T* __restrict__ in, LineMap im, T* __restrict__ out, LineMap o
             Tables<T> t, OmegaDev om, int lpw, int lbytes) {
   extern __shared__ unsigned char smem_raw[];
   const int G = int(blockDim.x) / lpw, sub = int(threadIdx.x) / G;
-  adj_line<T>(in, im, out, omap, j, scatter, rm, t, om, int64_t(blockIdx.x) * lpw + sub, smem_raw + sub * lbytes,
+  adj_line<T>(in, im, out, omap, j, scatter, rm, t, om, first_line(lpw) + sub, smem_raw + sub * lbytes,
               int(threadIdx.x) % G, G);
 }
 
