@@ -215,21 +215,43 @@ __device__ inline void row_prefix(const uint32_t* __restrict__ words, int64_t wp
 }
 
 // L[p, s] for one phase s from xi in LDS (table product with boundary bands).
-template <typename T>
+// NU > 0: the order known at compile time -- the 2 nu - 1 taps of the phase
+// in registers and, away from the boundary bands, one unrolled correlation
+// per position; NU = 0 takes it from the tables (the fused batch launches,
+// whose instances differ).
+template <typename T, int NU = 0>
 __device__ void table_product(const T* xi, T* L, int M, int s, int tid, int nthreads,
                               const Tables<T>& t) {
-  const int nu = t.nu, Q = t.Q, band = 2 * nu - 1;
+  const int nu = NU > 0 ? NU : t.nu, Q = t.Q, band = 2 * nu - 1;
   const int right_first = M - nu > nu ? M - nu : nu;
+  constexpr int NT = NU > 0 ? 2 * NU - 1 : 1;
+  T tap[NT];
+  if constexpr (NU > 0) {
+#pragma unroll
+    for (int li = 0; li < NT; ++li) tap[li] = t.tabT[li * Q + s];
+  }
   if (t.per) {  // periodic extension: the correlation wraps around the line
     for (int p = tid; p < M; p += nthreads) {
       T acc = 0;
-      for (int l = -nu + 1; l <= nu - 1; ++l) acc += xi[(p - l) & (M - 1)] * t.tabT[(l + nu - 1) * Q + s];
+      if constexpr (NU > 0) {
+#pragma unroll
+        for (int li = 0; li < NT; ++li) acc += xi[(p - li + NU - 1) & (M - 1)] * tap[li];
+      } else {
+        for (int l = -nu + 1; l <= nu - 1; ++l) acc += xi[(p - l) & (M - 1)] * t.tabT[(l + nu - 1) * Q + s];
+      }
       L[p] = acc;
     }
     return;
   }
   for (int p = tid; p < M; p += nthreads) {
     T acc = 0;
+    if (NU > 0 && p >= 2 * nu - 1 && p <= right_first - nu) {
+      // every tap lands on an interior coefficient and no band reaches p
+#pragma unroll
+      for (int li = 0; li < NT; ++li) acc += xi[p - li + nu - 1] * tap[li];
+      L[p] = acc;
+      continue;
+    }
     for (int l = -nu + 1; l <= nu - 1; ++l) {
       const int m = p - l;
       if (m >= nu && m < right_first) acc += xi[m] * t.tabT[(l + nu - 1) * Q + s];
@@ -248,16 +270,28 @@ __device__ void table_product(const T* xi, T* L, int M, int s, int tid, int nthr
   }
 }
 
-// xi[m] += sum_p table(p, m, s) R[p] for one phase s (transpose of table_product).
-template <typename T>
+// xi[m] += sum_p table(p, m, s) R[p] for one phase s (transpose of
+// table_product; NU as there).
+template <typename T, int NU = 0>
 __device__ void table_product_t(const T* R, T* xi, int M, int s, int tid, int nthreads,
                                 const Tables<T>& t) {
-  const int nu = t.nu, Q = t.Q, band = 2 * nu - 1;
+  const int nu = NU > 0 ? NU : t.nu, Q = t.Q, band = 2 * nu - 1;
   const int right_first = M - nu > nu ? M - nu : nu;
+  constexpr int NT = NU > 0 ? 2 * NU - 1 : 1;
+  T tap[NT];
+  if constexpr (NU > 0) {
+#pragma unroll
+    for (int li = 0; li < NT; ++li) tap[li] = t.tabT[li * Q + s];
+  }
   if (t.per) {
     for (int m = tid; m < M; m += nthreads) {
       T acc = 0;
-      for (int l = -nu + 1; l <= nu - 1; ++l) acc += R[(m + l) & (M - 1)] * t.tabT[(l + nu - 1) * Q + s];
+      if constexpr (NU > 0) {
+#pragma unroll
+        for (int li = 0; li < NT; ++li) acc += R[(m + li - NU + 1) & (M - 1)] * tap[li];
+      } else {
+        for (int l = -nu + 1; l <= nu - 1; ++l) acc += R[(m + l) & (M - 1)] * t.tabT[(l + nu - 1) * Q + s];
+      }
       xi[m] += acc;
     }
     return;
@@ -265,7 +299,12 @@ __device__ void table_product_t(const T* R, T* xi, int M, int s, int tid, int nt
   for (int m = tid; m < M; m += nthreads) {
     T acc = 0;
     if (m >= nu && m < right_first) {
-      for (int l = -nu + 1; l <= nu - 1; ++l) acc += R[m + l] * t.tabT[(l + nu - 1) * Q + s];
+      if constexpr (NU > 0) {
+#pragma unroll
+        for (int li = 0; li < NT; ++li) acc += R[m + li - NU + 1] * tap[li];
+      } else {
+        for (int l = -nu + 1; l <= nu - 1; ++l) acc += R[m + l] * t.tabT[(l + nu - 1) * Q + s];
+      }
     } else if (m < nu) {
       for (int p = 0; p < band && p < M; ++p) acc += R[p] * t.bandL[(p * nu + m) * Q + s];
     } else {
@@ -312,7 +351,7 @@ __device__ __forceinline__ int64_t omega_row(int64_t line, const RowMap& rm, int
 // and every group passes the same sequence of them.  gather == 0: write the N
 // outputs in natural order r = s M + k at element r of output line `line`.
 // gather == 1: the samples of the line's Omega row go to y (`out`).
-template <typename T>
+template <typename T, int NU = 0>
 __device__ void fwd_line(const T* __restrict__ in, const LineMap& im, T* __restrict__ out, const LineMap& omap, int j,
          int gather, const RowMap& rm,
             const Tables<T>& t, const OmegaDev& om, int64_t line, unsigned char* smem, int tid, int nt) {
@@ -336,7 +375,7 @@ __device__ void fwd_line(const T* __restrict__ in, const LineMap& im, T* __restr
   const int64_t ob = gather ? 0 : line_base(omap, line);
   __syncthreads();
   for (int s = 0; s < Q; ++s) {
-    table_product(xi, L, M, s, tid, nt, t);
+    table_product<T, NU>(xi, L, M, s, tid, nt, t);
     __syncthreads();
     fwht_lds(L, M, tid, nt);
     if (!gather) {
@@ -368,7 +407,7 @@ __device__ void fwd_line(const T* __restrict__ in, const LineMap& im, T* __restr
 // N natural-order values of input line `line` (element r at r * im.es).
 // scatter == 1: the line's Omega samples come from y (`in`).  The M results
 // go to output line `line`.
-template <typename T>
+template <typename T, int NU = 0>
 __device__ void adj_line(const T* __restrict__ in, const LineMap& im, T* __restrict__ out, const LineMap& omap, int j,
          int scatter, const RowMap& rm,
             const Tables<T>& t, const OmegaDev& om, int64_t line, unsigned char* smem, int tid, int nt) {
@@ -416,7 +455,7 @@ __device__ void adj_line(const T* __restrict__ in, const LineMap& im, T* __restr
     }
     __syncthreads();
     fwht_lds(R, M, tid, nt);
-    table_product_t(R, xi, M, s, tid, nt, t);
+    table_product_t<T, NU>(R, xi, M, s, tid, nt, t);
     __syncthreads();
   }
   const int64_t ob = line_base(omap, line);

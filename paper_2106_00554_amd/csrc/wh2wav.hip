@@ -148,25 +148,28 @@ __device__ __forceinline__ int64_t first_line(int lpw) {
   return wg * lpw;
 }
 
-template <typename T>
+// NU: the wavelet order (the taps of the table product unrolled).
+template <typename T, int NU>
 __global__ void __launch_bounds__(kThreads)
 k_fwd_lines(const T* __restrict__ in, LineMap im, T* __restrict__ out, LineMap omap, int j, int gather, RowMap rm,
             Tables<T> t, OmegaDev om, int lpw, int lbytes) {
   extern __shared__ unsigned char smem_raw[];
   const int G = int(blockDim.x) / lpw, sub = int(threadIdx.x) / G;
-  fwd_line<T>(in, im, out, omap, j, gather, rm, t, om, first_line(lpw) + sub, smem_raw + sub * lbytes,
-              int(threadIdx.x) % G, G);
+  fwd_line<T, NU>(in, im, out, omap, j, gather, rm, t, om, first_line(lpw) + sub, smem_raw + sub * lbytes,
+                  int(threadIdx.x) % G, G);
 }
 
-template <typename T>
+template <typename T, int NU>
 __global__ void __launch_bounds__(kThreads)
 k_adj_lines(const T* __restrict__ in, LineMap im, T* __restrict__ out, LineMap omap, int j, int scatter, RowMap rm,
             Tables<T> t, OmegaDev om, int lpw, int lbytes) {
   extern __shared__ unsigned char smem_raw[];
   const int G = int(blockDim.x) / lpw, sub = int(threadIdx.x) / G;
-  adj_line<T>(in, im, out, omap, j, scatter, rm, t, om, first_line(lpw) + sub, smem_raw + sub * lbytes,
-              int(threadIdx.x) % G, G);
+  adj_line<T, NU>(in, im, out, omap, j, scatter, rm, t, om, first_line(lpw) + sub, smem_raw + sub * lbytes,
+                  int(threadIdx.x) % G, G);
 }
+
+#define WH2WAV_LINE_NUS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
 
 }  // namespace
 
@@ -299,20 +302,32 @@ int launch_lines(const wh2wav_plan_s* p, bool fwd, int64_t lines, int j, const T
   int rc = check_and_set_smem<T>(nullptr, lb * lpw);
   if (rc) return rc;
   const dim3 grid(unsigned(lines / lpw));
-  if (fwd)
-    hipLaunchKernelGGL(k_fwd_lines<T>, grid, dim3(kThreads), lb * lpw, st, in, im, out, om_, j, omega_side, rm, tab,
-                       omega_of(p), lpw, int(lb));
-  else
-    hipLaunchKernelGGL(k_adj_lines<T>, grid, dim3(kThreads), lb * lpw, st, in, im, out, om_, j, omega_side, rm, tab,
-                       omega_of(p), lpw, int(lb));
-  HIP_OK(hipGetLastError());
-  return WH2WAV_OK;
+  const OmegaDev om = omega_of(p);
+#define X(V)                                                                                                      \
+  if (tab.nu == V) {                                                                                              \
+    if (fwd)                                                                                                      \
+      hipLaunchKernelGGL((k_fwd_lines<T, V>), grid, dim3(kThreads), lb * lpw, st, in, im, out, om_, j, omega_side, \
+                         rm, tab, om, lpw, int(lb));                                                              \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_adj_lines<T, V>), grid, dim3(kThreads), lb * lpw, st, in, im, out, om_, j, omega_side, \
+                         rm, tab, om, lpw, int(lb));                                                              \
+    HIP_OK(hipGetLastError());                                                                                    \
+    return WH2WAV_OK;                                                                                             \
+  }
+  WH2WAV_LINE_NUS(X)
+#undef X
+  return fail(WH2WAV_EINTERNAL, "no line kernel for this wavelet order");
 }
 
 template <typename T>
 int prepare_line_kernels() {
-  HIP_OK(hipFuncSetAttribute((const void*)k_fwd_lines<T>, hipFuncAttributeMaxDynamicSharedMemorySize, int(kMaxLds)));
-  HIP_OK(hipFuncSetAttribute((const void*)k_adj_lines<T>, hipFuncAttributeMaxDynamicSharedMemorySize, int(kMaxLds)));
+#define X(V)                                                                                                      \
+  HIP_OK(hipFuncSetAttribute((const void*)k_fwd_lines<T, V>, hipFuncAttributeMaxDynamicSharedMemorySize,           \
+                             int(kMaxLds)));                                                                      \
+  HIP_OK(hipFuncSetAttribute((const void*)k_adj_lines<T, V>, hipFuncAttributeMaxDynamicSharedMemorySize,           \
+                             int(kMaxLds)));
+  WH2WAV_LINE_NUS(X)
+#undef X
   return WH2WAV_OK;
 }
 
