@@ -242,7 +242,7 @@ int build(const std::vector<wh2wav::PlanView>& views, const std::vector<size_t>&
     sparse = sparse || !v.full_omega;
   }
   const size_t elem = dtype == WH2WAV_F64 ? 8 : 4;
-  P->smem = 2 * size_t(Mmax) * elem + (sparse ? sizeof(int) * (size_t(wpr_max) + kThreads) : 0);
+  P->smem = 2 * size_t(Mmax) * elem + (sparse ? sizeof(int) * (2 * size_t(wpr_max) + kThreads) : 0);
   int dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);

@@ -191,13 +191,58 @@ __device__ void fwht_lds(T* buf, int M, int tid, int nthreads) {
   else if (h * 2 == M) fwht_lds_pass<T, 2>(buf, M, h, tid, nthreads);
 }
 
-// Exclusive prefix of popcounts of `words` mask words into pre[] (LDS).
-__device__ inline void row_prefix(const uint32_t* __restrict__ words, int64_t wpr, int* pre, int* scratch,
-                           int tid, int nthreads) {
+// dst[at(k)] = src(k) for k in [0, n), by nt threads (thread tid): each
+// thread issues U global loads before it waits for them and stores the values
+// to LDS, instead of one load and one wait per element.
+template <int U, typename T, typename Src, typename At>
+__device__ __forceinline__ void stage_lds(T* dst, int n, int tid, int nt, Src src, At at) {
+  for (int k0 = tid; k0 < n; k0 += U * nt) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * nt;
+      v[u] = k < n ? src(k) : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * nt;
+      if (k < n) dst[at(k)] = v[u];
+    }
+  }
+}
+constexpr int kInFlight = 8;
+
+// Position b (sequency order within a phase) of the u-th element of a line's
+// gather or scatter, u = iteration * threads + thread.  In natural order the
+// position is bitrev(gray(b)), so the consecutive b that coalesce the global
+// accesses all fall into one LDS bank; a wave (64 consecutive u) instead
+// takes 8 runs of 8 consecutive b, M / 8 apart: 32-byte global segments and
+// 8 distinct low bits of the natural index.  A bijection of [0, M).
+__device__ __forceinline__ int spread_pos(int u, int M) {
+  if (M < 64) return u;
+  return (u & 7) + ((u >> 3) & 7) * (M >> 3) + (u >> 6) * 8;
+}
+// The same for a sparse Omega, whose samples sit at scattered ranks anyway:
+// consecutive u take bit u / W of the mask words u mod W (W = M / 32 words per
+// phase), so the lanes of a wave spread over the high bits of b (the low
+// bits of the natural index).  A bijection of [0, 2^j).
+__device__ __forceinline__ int word_pos(int u, int j) {
+  if (j < 5) return u;
+  return ((u & ((1 << (j - 5)) - 1)) << 5) | (u >> (j - 5));
+}
+
+// The `wpr` mask words of a row into wl[] and the exclusive prefix of their
+// popcounts into pre[] (both LDS).
+__device__ inline void row_prefix(const uint32_t* __restrict__ words, int64_t wpr, int* pre, uint32_t* wl,
+                                  int* scratch, int tid, int nthreads) {
   const int64_t chunk = (wpr + nthreads - 1) / nthreads;
   const int64_t w0 = tid * chunk, w1 = w0 + chunk < wpr ? w0 + chunk : wpr;
   int local = 0;
-  for (int64_t w = w0; w < w1; ++w) local += __popc(words[w]);
+  for (int64_t w = w0; w < w1; ++w) {
+    const uint32_t v = words[w];
+    wl[w] = v;
+    local += __popc(v);
+  }
   scratch[tid] = local;
   __syncthreads();
   for (int off = 1; off < nthreads; off <<= 1) {
@@ -209,7 +254,7 @@ __device__ inline void row_prefix(const uint32_t* __restrict__ words, int64_t wp
   int run = scratch[tid] - local;
   for (int64_t w = w0; w < w1; ++w) {
     pre[w] = run;
-    run += __popc(words[w]);
+    run += __popc(wl[w]);
   }
   __syncthreads();
 }
@@ -346,7 +391,7 @@ __device__ __forceinline__ int64_t omega_row(int64_t line, const RowMap& rm, int
 
 // Forward G on line `line` of M = 2^j values, by a group of nt threads
 // (thread tid of the group; smem: the group's 2 M values and, when gathering
-// from a sparse Omega, wpr + nt ints).  Every thread of the workgroup must
+// from a sparse Omega, 2 wpr + nt ints).  Every thread of the workgroup must
 // call it, with groups of the same size: its barriers are workgroup-wide,
 // and every group passes the same sequence of them.  gather == 0: write the N
 // outputs in natural order r = s M + k at element r of output line `line`.
@@ -360,17 +405,14 @@ __device__ void fwd_line(const T* __restrict__ in, const LineMap& im, T* __restr
   T* L = xi + M;
   int* pre = reinterpret_cast<int*>(L + M);
   int* scratch = pre + (gather && !om.full ? om.wpr : 0);
+  uint32_t* wl = reinterpret_cast<uint32_t*>(scratch + nt);
   const int64_t ib = line_base(im, line);
-  for (int p = tid; p < M; p += nt) xi[p] = in[ib + p * im.es];
+  stage_lds<kInFlight>(xi, M, tid, nt, [&](int p) { return in[ib + p * im.es]; }, [](int p) { return p; });
   int64_t n1 = 0, base = 0;
-  const uint32_t* words = nullptr;
   if (gather) {
     n1 = omega_row(line, rm, Q);
     base = om.row_ptr[n1];
-    if (!om.full) {
-      words = om.mask + n1 * om.wpr;
-      row_prefix(words, om.wpr, pre, scratch, tid, nt);
-    }
+    if (!om.full) row_prefix(om.mask + n1 * om.wpr, om.wpr, pre, wl, scratch, tid, nt);
   }
   const int64_t ob = gather ? 0 : line_base(omap, line);
   __syncthreads();
@@ -381,22 +423,17 @@ __device__ void fwd_line(const T* __restrict__ in, const LineMap& im, T* __restr
     if (!gather) {
       for (int k = tid; k < M; k += nt) out[ob + (int64_t(s) * M + k) * omap.es] = L[k];
     } else if (om.full) {
-      for (int b = tid; b < M; b += nt)
+      for (int u = tid; u < M; u += nt) {
+        const int b = spread_pos(u, M);
         out[base + int64_t(s) * M + b] = L[natural_of(uint32_t(b), uint32_t(s), j)];
-    } else {
-      const int64_t w0 = (int64_t(s) * M) >> 5, w1 = (int64_t(s + 1) * M + 31) >> 5;
-      for (int64_t w = w0 + tid; w < w1; w += nt) {
-        uint32_t bits = words[w];
-        int idx = pre[w];
-        while (bits) {
-          const int bit = __ffs(bits) - 1;
-          bits &= bits - 1;
-          const int64_t n2 = w * 32 + bit;
-          if (n2 >= int64_t(s + 1) * M || n2 < int64_t(s) * M) { ++idx; continue; }
-          const uint32_t b = uint32_t(n2 - int64_t(s) * M);
-          out[base + idx] = L[natural_of(b, uint32_t(s), j)];
-          ++idx;
-        }
+      }
+    } else {  // sample n2 = s M + b is number pre[word] + (set bits below it in its word) of the row
+      for (int u = tid; u < M; u += nt) {
+        const int b = word_pos(u, j);
+        const int64_t n2 = int64_t(s) * M + b;
+        const uint32_t w = wl[n2 >> 5], bit = uint32_t(n2) & 31u;
+        if ((w >> bit) & 1u)
+          out[base + pre[n2 >> 5] + __popc(w & ((1u << bit) - 1u))] = L[natural_of(uint32_t(b), uint32_t(s), j)];
       }
     }
     __syncthreads();
@@ -416,42 +453,31 @@ __device__ void adj_line(const T* __restrict__ in, const LineMap& im, T* __restr
   T* R = xi + M;
   int* pre = reinterpret_cast<int*>(R + M);
   int* scratch = pre + (scatter && !om.full ? om.wpr : 0);
+  uint32_t* wl = reinterpret_cast<uint32_t*>(scratch + nt);
   for (int p = tid; p < M; p += nt) xi[p] = 0;
   int64_t n1 = 0, base = 0;
-  const uint32_t* words = nullptr;
   if (scatter) {
     n1 = omega_row(line, rm, Q);
     base = om.row_ptr[n1];
-    if (!om.full) {
-      words = om.mask + n1 * om.wpr;
-      row_prefix(words, om.wpr, pre, scratch, tid, nt);
-    }
+    if (!om.full) row_prefix(om.mask + n1 * om.wpr, om.wpr, pre, wl, scratch, tid, nt);
   }
   const int64_t ib = scatter ? 0 : line_base(im, line);
   __syncthreads();
   for (int s = 0; s < Q; ++s) {
+    auto nat = [&](int u) { return int(natural_of(uint32_t(spread_pos(u, M)), uint32_t(s), j)); };
+    auto nat_w = [&](int u) { return int(natural_of(uint32_t(word_pos(u, j)), uint32_t(s), j)); };
     if (!scatter) {
-      for (int k = tid; k < M; k += nt) R[k] = in[ib + (int64_t(s) * M + k) * im.es];
+      stage_lds<kInFlight>(R, M, tid, nt, [&](int k) { return in[ib + (int64_t(s) * M + k) * im.es]; },
+                           [](int k) { return k; });
     } else if (om.full) {
-      for (int b = tid; b < M; b += nt)
-        R[natural_of(uint32_t(b), uint32_t(s), j)] = in[base + int64_t(s) * M + b];
-    } else {
-      for (int k = tid; k < M; k += nt) R[k] = 0;
-      __syncthreads();
-      const int64_t w0 = (int64_t(s) * M) >> 5, w1 = (int64_t(s + 1) * M + 31) >> 5;
-      for (int64_t w = w0 + tid; w < w1; w += nt) {
-        uint32_t bits = words[w];
-        int idx = pre[w];
-        while (bits) {
-          const int bit = __ffs(bits) - 1;
-          bits &= bits - 1;
-          const int64_t n2 = w * 32 + bit;
-          if (n2 >= int64_t(s + 1) * M || n2 < int64_t(s) * M) { ++idx; continue; }
-          const uint32_t b = uint32_t(n2 - int64_t(s) * M);
-          R[natural_of(b, uint32_t(s), j)] = in[base + idx];
-          ++idx;
-        }
-      }
+      stage_lds<kInFlight>(R, M, tid, nt, [&](int u) { return in[base + int64_t(s) * M + spread_pos(u, M)]; },
+                           nat);
+    } else {  // every position of R written once: the sample, or 0 off Omega
+      stage_lds<kInFlight>(R, M, tid, nt, [&](int u) {
+        const int64_t n2 = int64_t(s) * M + word_pos(u, j);
+        const uint32_t w = wl[n2 >> 5], bit = uint32_t(n2) & 31u;
+        return (w >> bit) & 1u ? in[base + pre[n2 >> 5] + __popc(w & ((1u << bit) - 1u))] : T(0);
+      }, nat_w);
     }
     __syncthreads();
     fwht_lds(R, M, tid, nt);

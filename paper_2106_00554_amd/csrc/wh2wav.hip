@@ -297,7 +297,7 @@ int launch_lines(const wh2wav_plan_s* p, bool fwd, int64_t lines, int j, const T
   while (lpw > 1 && lines % lpw) lpw >>= 1;
   const int G = kThreads / lpw;
   size_t lb = 2 * size_t(M) * sizeof(T);
-  if (omega_side && !p->host.full_omega) lb += sizeof(int) * (size_t(p->host.words_per_row) + G);
+  if (omega_side && !p->host.full_omega) lb += sizeof(int) * (2 * size_t(p->host.words_per_row) + G);
   lb = (lb + 15) / 16 * 16;
   int rc = check_and_set_smem<T>(nullptr, lb * lpw);
   if (rc) return rc;
@@ -529,10 +529,10 @@ int forward_nd(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t s
   }
   const RowMap none{0, 0, 0};
   int rc = WH2WAV_OK;
-  if (H.dim == 2) {
-    if (run(1)) rc = nd_pass<T>(p, true, 0, M1, XA, lines_at(1, M1), Z0, lines_at(1, M1), 0, none, st);
+  if (H.dim == 2) {  // Z0 transposed (M1 x N0): whole rows written, strided reads
+    if (run(1)) rc = nd_pass<T>(p, true, 0, M1, XA, lines_at(1, M1), Z0, lines_at(N0, 1), 0, none, st);
     if (rc == WH2WAV_OK && run(2))
-      rc = nd_pass<T>(p, true, 1, N0, Z0, lines_at(M1, 1), y, lines_at(0, 0), 1, RowMap{1, H.ja[0], 0}, st);
+      rc = nd_pass<T>(p, true, 1, N0, Z0, lines_at(1, N0), y, lines_at(0, 0), 1, RowMap{1, H.ja[0], 0}, st);
     return rc;
   }
   if (run(1)) {
@@ -667,10 +667,13 @@ int forward_impl(const wh2wav_plan_s* p, const T* x, T* y, void* ws, hipStream_t
     return WH2WAV_OK;
   }
   int rc = WH2WAV_OK;
-  if (run(1))  // column pass: G along the first index (rows of xi^T); Z[r, m2] with r natural
-    rc = launch_lines<T>(p, true, M, H.j, TMP, lines_at(M, 1), Z, lines_at(1, M), 0, RowMap{0, 0, 0}, t, st);
-  if (rc == WH2WAV_OK && run(2))  // row pass: G along the second index, gather Omega
-    rc = launch_lines<T>(p, true, N, H.j, Z, lines_at(M, 1), y, lines_at(0, 0), 1, RowMap{1, H.j, 0}, t, st);
+  // Z is kept transposed here (Z^T[m2, r], M x N): the column pass writes
+  // whole rows and the row pass reads with stride N -- strided reads share
+  // cache lines in L2, strided writes leave partly written lines to HBM.
+  if (run(1))  // column pass: G along the first index (rows of xi^T); Z^T[m2, r] with r natural
+    rc = launch_lines<T>(p, true, M, H.j, TMP, lines_at(M, 1), Z, lines_at(N, 1), 0, RowMap{0, 0, 0}, t, st);
+  if (rc == WH2WAV_OK && run(2))  // row pass: G along the second index (columns of Z^T), gather Omega
+    rc = launch_lines<T>(p, true, N, H.j, Z, lines_at(1, N), y, lines_at(0, 0), 1, RowMap{1, H.j, 0}, t, st);
   return rc;
 }
 
@@ -871,7 +874,7 @@ int plan_body(const wh2wav_desc* desc, wh2wav_plan_t* out) {
   int64_t Mline = H.M;  // longest line of the LDS line kernels
   for (int a = 0; H.nd && a < H.dim; ++a) Mline = std::max(Mline, H.Ma[a]);
   if (!use_fast(p) && !use_fast1d(p) &&
-      2 * size_t(Mline) * elem + sizeof(int) * (size_t(H.words_per_row) + kThreads) > kMaxLds)
+      2 * size_t(Mline) * elem + sizeof(int) * (2 * size_t(H.words_per_row) + kThreads) > kMaxLds)
     return fail(WH2WAV_EUNSUPPORTED, "M too large for the LDS line kernels");
   rc = H.dtype == WH2WAV_F64 ? prepare_line_kernels<double>() : prepare_line_kernels<float>();
   if (rc != WH2WAV_OK) return rc;
