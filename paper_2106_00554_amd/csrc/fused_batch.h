@@ -38,6 +38,7 @@ struct Program {
   int dtype = 0, dir = 0;
   int ninst = 0;
   size_t smem = 0;          // dynamic LDS per workgroup
+  int nu = 0;               // wavelet order shared by every instance, 0 for a mix
   void* d_inst = nullptr;   // Inst<T>[ninst]
   void* d_stage = nullptr;  // Stage[all rounds]
   std::vector<Round> rounds;

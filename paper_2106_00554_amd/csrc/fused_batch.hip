@@ -64,8 +64,10 @@ __device__ __forceinline__ T* buffer(const Inst<T>& I, int id, char* ws, void* c
 }
 
 // One round: the items [item0, item0 + nitems) of the stages
-// [stage0, stage0 + nstages), a grid-stride loop of whole workgroups.
-template <typename T>
+// [stage0, stage0 + nstages), a grid-stride loop of whole workgroups.  NU: the
+// wavelet order of every instance when they share one (the line code then
+// unrolls its taps), 0 for a mix.
+template <typename T, int NU>
 __global__ void __launch_bounds__(kThreads) k_round(const Inst<T>* __restrict__ insts,
                                                     const Stage* __restrict__ stages, int stage0, int nstages,
                                                     int64_t item0, int64_t nitems, char* ws, void* const* io) {
@@ -111,14 +113,24 @@ __global__ void __launch_bounds__(kThreads) k_round(const Inst<T>* __restrict__ 
         if (S.out_too) buffer<T>(I, kOut, ws, io, S.inst)[pos] = v;
       }
     } else if (S.kind == kFwdLines) {
-      fwd_line<T>(src, S.im, dst, S.omap, S.j, S.gather, S.rm, I.t, I.om, tile, smem_raw, int(threadIdx.x),
-                  int(blockDim.x));
+      fwd_line<T, NU>(src, S.im, dst, S.omap, S.j, S.gather, S.rm, I.t, I.om, tile, smem_raw, int(threadIdx.x),
+                      int(blockDim.x));
     } else {
-      adj_line<T>(src, S.im, dst, S.omap, S.j, S.gather, S.rm, I.t, I.om, tile, smem_raw, int(threadIdx.x),
-                  int(blockDim.x));
+      adj_line<T, NU>(src, S.im, dst, S.omap, S.j, S.gather, S.rm, I.t, I.om, tile, smem_raw, int(threadIdx.x),
+                      int(blockDim.x));
     }
     __syncthreads();  // the next item reuses the LDS
   }
+}
+
+#define WH2WAV_ROUND_NUS(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
+template <typename T>
+const void* round_kernel(int nu) {
+#define X(V) \
+  if (nu == V) return reinterpret_cast<const void*>(k_round<T, V>);
+  WH2WAV_ROUND_NUS(X)
+#undef X
+  return nullptr;
 }
 
 LineMap lines_at(int64_t ls, int64_t es) { return LineMap{int64_t(1) << 62, 0, ls, es}; }
@@ -212,8 +224,7 @@ int upload(const std::vector<wh2wav::PlanView>& views, const std::vector<size_t>
   if (e == hipSuccess)
     e = hipMemcpy(P->d_stage, stages.data(), sizeof(Stage) * stages.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return herr(e, "fused program upload");
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_round<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          int(P->smem));
+  e = hipFuncSetAttribute(round_kernel<T>(P->nu), hipFuncAttributeMaxDynamicSharedMemorySize, int(P->smem));
   if (e != hipSuccess) return herr(e, "fused kernel setup");
   return WH2WAV_OK;
 }
@@ -233,12 +244,14 @@ int build(const std::vector<wh2wav::PlanView>& views, const std::vector<size_t>&
   size_t longest = 0;
   int64_t Mmax = 1, wpr_max = 0;
   bool sparse = false;
+  P->nu = members.empty() ? 0 : views[members[0]].nu;  // the shared wavelet order, or 0
   for (int slot = 0; slot < P->ninst; ++slot) {
     const auto& v = views[members[slot]];
     chains.push_back(chain(v, slot, dir));
     longest = std::max(longest, chains.back().size());
     Mmax = std::max(Mmax, v.M);
     wpr_max = std::max(wpr_max, v.wpr);
+    if (v.nu != P->nu) P->nu = 0;
     sparse = sparse || !v.full_omega;
   }
   const size_t elem = dtype == WH2WAV_F64 ? 8 : 4;
@@ -269,16 +282,18 @@ int build(const std::vector<wh2wav::PlanView>& views, const std::vector<size_t>&
 }
 
 int launch(const Program& P, void* ws, void* const* io_dev, hipStream_t st) {
+  const void* kernel = P.dtype == WH2WAV_F64 ? round_kernel<double>(P.nu) : round_kernel<float>(P.nu);
+  if (!kernel) return wh2wav::set_error(WH2WAV_EINTERNAL, "no fused kernel for this wavelet order");
+  const void* insts = P.d_inst;
+  const Stage* stages = static_cast<const Stage*>(P.d_stage);
+  char* wsc = static_cast<char*>(ws);
   for (const Round& rd : P.rounds) {
-    if (P.dtype == WH2WAV_F64)
-      hipLaunchKernelGGL(k_round<double>, dim3(unsigned(rd.grid)), dim3(kThreads), P.smem, st,
-                         static_cast<const Inst<double>*>(P.d_inst), static_cast<const Stage*>(P.d_stage), rd.stage0,
-                         rd.nstages, rd.item0, rd.nitems, static_cast<char*>(ws), io_dev);
-    else
-      hipLaunchKernelGGL(k_round<float>, dim3(unsigned(rd.grid)), dim3(kThreads), P.smem, st,
-                         static_cast<const Inst<float>*>(P.d_inst), static_cast<const Stage*>(P.d_stage), rd.stage0,
-                         rd.nstages, rd.item0, rd.nitems, static_cast<char*>(ws), io_dev);
-    hipError_t e = hipGetLastError();
+    int stage0 = rd.stage0, nstages = rd.nstages;
+    int64_t item0 = rd.item0, nitems = rd.nitems;
+    void* const* io = io_dev;
+    void* args[] = {&insts, &stages, &stage0, &nstages, &item0, &nitems, &wsc, &io};
+    hipError_t e = hipLaunchKernel(kernel, dim3(unsigned(rd.grid)), dim3(kThreads), args, P.smem, st);
+    if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return herr(e, "fused round");
   }
   return WH2WAV_OK;
