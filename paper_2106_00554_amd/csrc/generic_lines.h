@@ -155,8 +155,22 @@ __device__ T analysis_value_per(const T* __restrict__ src, int64_t es, int64_t o
   return acc;
 }
 
-// Natural-order Walsh-Hadamard transform of buf[0, M) in LDS by the whole
-// workgroup.  The butterflies of the index bits commute, so they run three
+// Barrier of a group of nt threads that works on one line.  Groups are
+// aligned to waves, and every group of a workgroup has the same size and
+// passes the same barriers; a group within one wave (nt <= 64) needs only
+// its wave's LDS accesses kept in order, not a workgroup barrier.
+__device__ __forceinline__ void group_sync(int nt) {
+  if (nt <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// Natural-order Walsh-Hadamard transform of buf[0, M) in LDS by a group of
+// nthreads threads.  The butterflies of the index bits commute, so they run three
 // bits at a time: each work item loads the 8 values whose indices differ in
 // bits b .. b+2, applies the three butterfly stages in registers and stores
 // them back -- one barrier per three stages.  The last one or two bits, if
@@ -180,7 +194,7 @@ __device__ __forceinline__ void fwht_lds_pass(T* buf, int M, int h, int tid, int
 #pragma unroll
     for (int i = 0; i < F; ++i) buf[base + i * h] = v[i];
   }
-  __syncthreads();
+  group_sync(nthreads);
 }
 
 template <typename T>
@@ -235,6 +249,17 @@ __device__ __forceinline__ int word_pos(int u, int j) {
 // popcounts into pre[] (both LDS).
 __device__ inline void row_prefix(const uint32_t* __restrict__ words, int64_t wpr, int* pre, uint32_t* wl,
                                   int* scratch, int tid, int nthreads) {
+  if (wpr <= 64) {  // a short row: each word's prefix summed directly (two barriers instead of a scan)
+    for (int w = tid; w < wpr; w += nthreads) wl[w] = words[w];
+    group_sync(nthreads);
+    for (int w = tid; w < wpr; w += nthreads) {
+      int acc = 0;
+      for (int i = 0; i < w; ++i) acc += __popc(wl[i]);
+      pre[w] = acc;
+    }
+    group_sync(nthreads);
+    return;
+  }
   const int64_t chunk = (wpr + nthreads - 1) / nthreads;
   const int64_t w0 = tid * chunk, w1 = w0 + chunk < wpr ? w0 + chunk : wpr;
   int local = 0;
@@ -244,26 +269,26 @@ __device__ inline void row_prefix(const uint32_t* __restrict__ words, int64_t wp
     local += __popc(v);
   }
   scratch[tid] = local;
-  __syncthreads();
+  group_sync(nthreads);
   for (int off = 1; off < nthreads; off <<= 1) {
     int v = tid >= off ? scratch[tid - off] : 0;
-    __syncthreads();
+    group_sync(nthreads);
     scratch[tid] += v;
-    __syncthreads();
+    group_sync(nthreads);
   }
   int run = scratch[tid] - local;
   for (int64_t w = w0; w < w1; ++w) {
     pre[w] = run;
     run += __popc(wl[w]);
   }
-  __syncthreads();
+  group_sync(nthreads);
 }
 
 // L[p, s] for one phase s from xi in LDS (table product with boundary bands).
 // NU > 0: the order known at compile time -- the 2 nu - 1 taps of the phase
 // in registers and, away from the boundary bands, one unrolled correlation
-// per position; NU = 0 takes it from the tables (the fused batch launches,
-// whose instances differ).
+// per position; NU = 0 takes it from the tables (the fused batch launches
+// over instances of different orders).
 template <typename T, int NU = 0>
 __device__ void table_product(const T* xi, T* L, int M, int s, int tid, int nthreads,
                               const Tables<T>& t) {
@@ -392,8 +417,9 @@ __device__ __forceinline__ int64_t omega_row(int64_t line, const RowMap& rm, int
 // Forward G on line `line` of M = 2^j values, by a group of nt threads
 // (thread tid of the group; smem: the group's 2 M values and, when gathering
 // from a sparse Omega, 2 wpr + nt ints).  Every thread of the workgroup must
-// call it, with groups of the same size: its barriers are workgroup-wide,
-// and every group passes the same sequence of them.  gather == 0: write the N
+// call it, with groups of the same size: its barriers are workgroup-wide
+// when a group spans more than one wave, and every group passes the same
+// sequence of them.  gather == 0: write the N
 // outputs in natural order r = s M + k at element r of output line `line`.
 // gather == 1: the samples of the line's Omega row go to y (`out`).
 template <typename T, int NU = 0>
@@ -415,10 +441,10 @@ __device__ void fwd_line(const T* __restrict__ in, const LineMap& im, T* __restr
     if (!om.full) row_prefix(om.mask + n1 * om.wpr, om.wpr, pre, wl, scratch, tid, nt);
   }
   const int64_t ob = gather ? 0 : line_base(omap, line);
-  __syncthreads();
+  group_sync(nt);
   for (int s = 0; s < Q; ++s) {
     table_product<T, NU>(xi, L, M, s, tid, nt, t);
-    __syncthreads();
+    group_sync(nt);
     fwht_lds(L, M, tid, nt);
     if (!gather) {
       for (int k = tid; k < M; k += nt) out[ob + (int64_t(s) * M + k) * omap.es] = L[k];
@@ -436,7 +462,7 @@ __device__ void fwd_line(const T* __restrict__ in, const LineMap& im, T* __restr
           out[base + pre[n2 >> 5] + __popc(w & ((1u << bit) - 1u))] = L[natural_of(uint32_t(b), uint32_t(s), j)];
       }
     }
-    __syncthreads();
+    group_sync(nt);
   }
 }
 
@@ -462,7 +488,7 @@ __device__ void adj_line(const T* __restrict__ in, const LineMap& im, T* __restr
     if (!om.full) row_prefix(om.mask + n1 * om.wpr, om.wpr, pre, wl, scratch, tid, nt);
   }
   const int64_t ib = scatter ? 0 : line_base(im, line);
-  __syncthreads();
+  group_sync(nt);
   for (int s = 0; s < Q; ++s) {
     auto nat = [&](int u) { return int(natural_of(uint32_t(spread_pos(u, M)), uint32_t(s), j)); };
     auto nat_w = [&](int u) { return int(natural_of(uint32_t(word_pos(u, j)), uint32_t(s), j)); };
@@ -479,10 +505,10 @@ __device__ void adj_line(const T* __restrict__ in, const LineMap& im, T* __restr
         return (w >> bit) & 1u ? in[base + pre[n2 >> 5] + __popc(w & ((1u << bit) - 1u))] : T(0);
       }, nat_w);
     }
-    __syncthreads();
+    group_sync(nt);
     fwht_lds(R, M, tid, nt);
     table_product_t<T, NU>(R, xi, M, s, tid, nt, t);
-    __syncthreads();
+    group_sync(nt);
   }
   const int64_t ob = line_base(omap, line);
   for (int m = tid; m < M; m += nt) out[ob + m * omap.es] = xi[m];
